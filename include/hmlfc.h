@@ -1,0 +1,153 @@
+/*
+ * hmlfc.h -- C ABI of the MI355X (gfx950) HMLFC light-field decode + render library.
+ *
+ * HMLFC (Pratapa & Manocha, "HMLFC: Hierarchical Motion-Compensated Light
+ * Field Compression for Interactive Rendering") stores a two-plane light
+ * field as a tree of residual views (RLFC hierarchy) whose non-reference
+ * views are phase-shifted motion-compensated against a reference view of
+ * the same cluster, block-coded with bounded integer sequences.  This
+ * library loads such a stream into device memory and serves random-access
+ * sample decoding and novel-view rendering with hand-written HIP kernels.
+ *
+ * Conventions shared by every call:
+ *  - Light-field samples are addressed (b, a, y, x): b = view row (v),
+ *    a = view column (u), y = image row (t), x = image column (s).
+ *  - A camera is float[18]: a row-major 3x3 homography h_uv followed by
+ *    h_st.  Output pixel (i, j) (column, row) is mapped at its centre
+ *    (i + 0.5, j + 0.5, 1); dividing by the third component gives the ray's
+ *    (u, v) in view-grid units and (s, t) in image pixels.
+ *  - "Device" pointers are HIP device allocations owned by the caller (the
+ *    library never allocates device memory except inside lf_encode's host
+ *    work and lf_footprint_bytes' scratch, both outside the render path).
+ *    "Host" pointers are ordinary process memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call that takes a stream only enqueues work on it; outputs are
+ *    ready when the stream is synchronised.  Argument checks happen on the
+ *    host before anything is enqueued.
+ *  - Return value: LF_OK, or a negative lf_status; lf_last_error() gives a
+ *    thread-local message for the last failure.
+ *  - A handle is immutable after loading; calls that only read it may run
+ *    concurrently on different streams.
+ *
+ * Stream format (little-endian; the encoder writes it, the loader checks
+ * it): a 1024-byte header (magic "HMLFCv1", grid sizes, tree height H,
+ * block size Bs, per-level quantisation steps and search windows, section
+ * offsets, and a per-(channel, level) motion-vector directory), then
+ *   root     int16 [3][nb_H][na_H][height][width]   level-H RKVs (YCoCg)
+ *   table    8-byte entries [3][n_nodes][n_blocks]: u32 payload word,
+ *            i16 minimum, u8 mode (0xFF = insignificant block), u8 0
+ *   payload  u32 words of bounded-integer-sequence block payloads
+ *   mv       u32 words: per (channel, level) BISE (mx + 4W, my + 4W)
+ *            pairs, then 2-bit phase codes (0: +1, 1: -1, 2: none)
+ * Nodes are numbered breadth-first from the top level (H-1) down to the
+ * leaf views (level 0), raster order within a level (Compressed Stream
+ * Structure).
+ */
+#ifndef HMLFC_H
+#define HMLFC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lf_handle lf_handle;
+
+typedef enum {
+    LF_OK = 0,
+    LF_EINVAL = -1,  /* bad argument: null pointer, size, range           */
+    LF_ENOMEM = -2,  /* caller-provided buffer too small                  */
+    LF_EFORMAT = -3, /* stream is malformed or inconsistent               */
+    LF_EDEVICE = -4  /* a HIP call or kernel launch failed                */
+} lf_status;
+
+typedef struct {
+    int32_t na, nb;          /* view grid: columns (u), rows (v)              */
+    int32_t width, height;   /* view image size                               */
+    int32_t levels;          /* tree height H                                 */
+    int32_t block;           /* block size Bs                                 */
+    int32_t root_na, root_nb;/* level-H grid                                  */
+    int64_t n_nodes;         /* SRV nodes (levels 0..H-1)                     */
+    int64_t n_pred_records;  /* motion-compensated blocks over all channels   */
+    int64_t n_refs;          /* reference SRV views per channel               */
+    int64_t arena_bytes;     /* device bytes the handle occupies              */
+    int64_t stream_bytes;    /* compressed stream size                        */
+    int64_t payload_bytes;   /* block payload section size                    */
+} lf_info;
+
+/* ---------------------------------------------------------------------- */
+/* Loading (Decompression Memory Overhead: the top-level RKVs and every    */
+/* reference SRV are decoded once, before any sample is requested).        */
+/* ---------------------------------------------------------------------- */
+
+/* Parse a stream's header on the host and report the device arena size
+ * lf_load_compressed needs.  host_stream: nbytes of stream.  Errors:
+ * LF_EINVAL (null), LF_EFORMAT (malformed). */
+lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_bytes);
+
+/* Validate the stream completely on the host, copy it into the caller's
+ * device arena (d_arena, arena_bytes >= lf_query_arena) and decode every
+ * reference SRV into resident int16 planes.  The handle borrows d_arena
+ * until lf_free; host_stream may be released when the call returns (the
+ * copy is complete on return).  Errors: LF_EINVAL, LF_EFORMAT (any header
+ * field, section size or block offset out of range), LF_ENOMEM (arena too
+ * small), LF_EDEVICE. */
+lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
+                             void* stream, lf_handle** out);
+
+/* Release the host-side handle (the arena stays the caller's). */
+lf_status lf_free(lf_handle* h);
+
+lf_status lf_get_info(const lf_handle* h, lf_info* out);
+
+/* ---------------------------------------------------------------------- */
+/* Random-access decoding (Decoding Procedure; Random Access for           */
+/* Interactive Rendering): each requested sample walks its tree path from  */
+/* the leaf view to the root, re-compensates motion-compensated blocks     */
+/* from the resident reference, adds the root RKV and inverts the colour   */
+/* transform.                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* d_coords: device int32 [n][4] = (b, a, y, x); coordinates outside the
+ * grid are clamped to it.  d_rgb: device uint8 [n][3].  n = 0 is a no-op. */
+lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t n, uint8_t* d_rgb, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Novel-view rendering fused with decoding (Random Access for             */
+/* Interactive Rendering; two-plane interpolation of Light Field           */
+/* Rendering).  Each ray's (u, v, s, t) is clamped to the grid; the 16     */
+/* neighbouring samples are decoded and blended quadrilinearly in FP32     */
+/* (s, then t, then u, then v) after scaling to [0, 1].                    */
+/* ---------------------------------------------------------------------- */
+
+/* d_cams: device float [n_views][18].  d_out: device float
+ * [n_views][3][height][width] (planar RGB).  width, height >= 1. */
+lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
+                          int32_t height, float* d_out, void* stream);
+
+/* Ray coordinates as the renderer computes them (binary32, no contraction):
+ * d_uvst: device float [n_views][height][width][4] = (u, v, s, t) before
+ * clamping.  For checking the renderer's arithmetic. */
+lf_status lf_ray_coords(const float* d_cams, int32_t n_views, int32_t width, int32_t height, float* d_uvst,
+                        void* stream);
+
+/* Per-view footprint bytes: the output (12 bytes per ray) plus every
+ * distinct predictive block's table entry, payload words and share of the
+ * motion-vector stream, and 2 bytes per pixel of every distinct reference
+ * or root block the view's samples read (through non-zero-weight prediction
+ * taps for references).  Reuse across views is not credited.  host_out:
+ * double [n_views].  Uses a temporary device buffer of about
+ * 3 * (2 * n_nodes + root views) * n_blocks bytes per call (the library
+ * allocates and frees it; this call synchronises `stream`). */
+lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
+                             int32_t height, double* host_out, void* stream);
+
+/* Message for the calling thread's last non-OK status. */
+const char* lf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

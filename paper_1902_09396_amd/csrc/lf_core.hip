@@ -1,0 +1,347 @@
+// HMLFC light-field library: stream loading, random-access decoding and the
+// per-ray reference renderer, behind the C ABI of include/hmlfc.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/hmlfc.h"
+#include "lf_geom.h"
+#include "lf_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+lf_status lf_fail(lf_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+extern "C" const char* lf_last_error(void) { return g_err.c_str(); }
+
+lf_status lf_check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return lf_fail(LF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return LF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host-side stream parsing (every offset and size is checked before upload)
+// ---------------------------------------------------------------------------
+
+static uint32_t rd32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
+
+static int64_t bise_bits_host(int mode, int64_t n)
+{
+    int fam = mode >> 5, b = mode & 31;
+    if (fam == 0) return n * b;
+    if (fam == 1) return (n + 4) / 5 * (8 + 5 * b);
+    return (n + 2) / 3 * (7 + 3 * b);
+}
+
+static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
+{
+    memset(L, 0, sizeof *L);
+    if (!s) return lf_fail(LF_EINVAL, "null stream");
+    if (n < LF_HDR_BYTES || memcmp(s, "HMLFCv1\0", 8) != 0) return lf_fail(LF_EFORMAT, "bad magic");
+    if (rd32(s + 8) != LF_HDR_BYTES || rd32(s + 12) != 1) return lf_fail(LF_EFORMAT, "bad header size/version");
+    int32_t d[8];
+    memcpy(d, s + 16, 32);
+    LfGeom& g = L->g;
+    g.na = d[0];
+    g.nb = d[1];
+    g.w = d[2];
+    g.h = d[3];
+    g.H = d[4];
+    g.bs = d[5];
+    if (g.na < 1 || g.nb < 1 || g.w < 1 || g.h < 1 || g.H < 1 || g.H > LF_MAX_LEVELS || g.bs < 1 || g.bs > 64 ||
+        g.w % g.bs || g.h % g.bs || d[6] != 3 || d[7] != 4 || g.na > 4096 || g.nb > 4096 || g.w > 16384 ||
+        g.h > 16384)
+        return lf_fail(LF_EFORMAT, "bad geometry");
+    g.nbx = g.w / g.bs;
+    g.nblk = g.nbx * (g.h / g.bs);
+    g.na_l[0] = g.na;
+    g.nb_l[0] = g.nb;
+    for (int l = 0; l < g.H; l++) {
+        g.na_l[l + 1] = (g.na_l[l] + 1) / 2;
+        g.nb_l[l + 1] = (g.nb_l[l] + 1) / 2;
+    }
+    g.root_na = g.na_l[g.H];
+    g.root_nb = g.nb_l[g.H];
+    int64_t nodes = 0, refs = 0;
+    for (int l = g.H - 1; l >= 0; l--) {
+        g.node_base[l] = (int)nodes;
+        nodes += (int64_t)g.na_l[l] * g.nb_l[l];
+    }
+    for (int l = 0; l < g.H; l++) {
+        g.ref_base[l] = (int)refs;
+        refs += (int64_t)g.na_l[l + 1] * g.nb_l[l + 1];
+    }
+    g.n_nodes = (int)nodes;
+    g.n_refs = (int)refs;
+    for (int l = 0; l < g.H; l++) {
+        int32_t st, wn;
+        memcpy(&st, s + 48 + 4 * l, 4);
+        memcpy(&wn, s + 80 + 4 * l, 4);
+        if (st < 1 || st > 4096 || wn < 0 || wn > 1024) return lf_fail(LF_EFORMAT, "bad step/window at level %d", l);
+        g.step[l] = st;
+        g.bias[l] = 4 * wn;
+    }
+    const int64_t plane = (int64_t)g.w * g.h;
+    L->root_off = rd64(s + 112);
+    L->root_bytes = rd64(s + 120);
+    L->table_off = rd64(s + 128);
+    L->table_bytes = rd64(s + 136);
+    L->payload_off = rd64(s + 144);
+    L->payload_bytes = rd64(s + 152);
+    L->mv_off = rd64(s + 160);
+    L->mv_bytes = rd64(s + 168);
+    const uint64_t N = n;
+    if (L->root_bytes != (uint64_t)(3 * (int64_t)g.root_na * g.root_nb * plane * 2) ||
+        L->table_bytes != (uint64_t)(3 * nodes * g.nblk * 8))
+        return lf_fail(LF_EFORMAT, "section sizes do not match the geometry");
+    struct {
+        uint64_t o, b;
+    } sec[4] = {{L->root_off, L->root_bytes}, {L->table_off, L->table_bytes}, {L->payload_off, L->payload_bytes},
+                {L->mv_off, L->mv_bytes}};
+    for (auto& x : sec)
+        if (x.o < LF_HDR_BYTES || x.o > N || x.b > N - x.o) return lf_fail(LF_EFORMAT, "section outside the stream");
+    if ((L->root_off & 1) || (L->table_off & 3) || (L->payload_off & 3) || (L->mv_off & 3) || (L->payload_bytes & 3) ||
+        (L->mv_bytes & 3) || L->payload_bytes < 8 || L->mv_bytes < 8)
+        return lf_fail(LF_EFORMAT, "misaligned section");
+    const int64_t pwords = (int64_t)(L->payload_bytes / 4), mwords = (int64_t)(L->mv_bytes / 4);
+    // block payloads: every 64-bit read window must stay inside the payload section
+    const uint8_t* tab = s + L->table_off;
+    const int64_t nent = 3 * nodes * g.nblk;
+    for (int64_t e = 0; e < nent; e++) {
+        const uint8_t* t = tab + 8 * e;
+        int mode = t[6];
+        if (mode == LF_MODE_ZERO) continue;
+        if ((mode >> 5) > 2 || (mode & 31) > 20) return lf_fail(LF_EFORMAT, "bad block mode at entry %lld", (long long)e);
+        int64_t words = (bise_bits_host(mode, (int64_t)g.bs * g.bs) + 31) / 32;
+        if ((int64_t)rd32(t) + words + 1 > pwords) return lf_fail(LF_EFORMAT, "block payload out of range");
+    }
+    int64_t rec = 0;
+    for (int c = 0; c < 3; c++)
+        for (int l = g.H - 1; l >= 0; l--) {
+            const uint8_t* dd = s + 176 + (c * LF_MAX_LEVELS + l) * 16;
+            g.mv_word[c][l] = rd32(dd);
+            g.sig_word[c][l] = rd32(dd + 4);
+            uint32_t count = rd32(dd + 8);
+            g.mv_mode[c][l] = dd[12];
+            int64_t npn = (int64_t)(g.nb_l[l] / 2) * g.na_l[l] + (int64_t)((g.nb_l[l] + 1) / 2) * (g.na_l[l] / 2);
+            int64_t expect = npn * g.nblk;
+            if ((int64_t)count != expect) return lf_fail(LF_EFORMAT, "motion record count mismatch");
+            if (expect > 0) {
+                int m = g.mv_mode[c][l];
+                if ((m >> 5) > 2 || (m & 31) > 20) return lf_fail(LF_EFORMAT, "bad motion-vector mode");
+                if ((int64_t)g.mv_word[c][l] + (bise_bits_host(m, 2 * expect) + 31) / 32 + 1 > mwords ||
+                    (int64_t)g.sig_word[c][l] + (2 * expect + 31) / 32 + 1 > mwords)
+                    return lf_fail(LF_EFORMAT, "motion-vector section out of range");
+            }
+            g.rec_base[c][l] = rec;
+            rec += expect;
+        }
+    L->n_rec = rec;
+    // arena: [root][table][payload][mv][refs], 256-byte aligned
+    L->a_root = 0;
+    L->a_table = align256(L->a_root + (int64_t)L->root_bytes);
+    L->a_payload = align256(L->a_table + (int64_t)L->table_bytes);
+    L->a_mv = align256(L->a_payload + (int64_t)L->payload_bytes);
+    L->a_refs = align256(L->a_mv + (int64_t)L->mv_bytes);
+    L->arena = align256(L->a_refs + 3 * refs * plane * 2);
+    L->stream_bytes = (int64_t)n;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_bytes)
+{
+    if (!arena_bytes) return lf_fail(LF_EINVAL, "null output");
+    LfLayout L;
+    lf_status st = lf_parse((const uint8_t*)host_stream, nbytes, &L);
+    if (st != LF_OK) return st;
+    *arena_bytes = L.arena;
+    return LF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reference planes (Decompression Memory Overhead)
+// ---------------------------------------------------------------------------
+
+__global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int64_t total = 3 * (int64_t)g.n_refs * plane;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t px = t % plane;
+        int64_t r = (t / plane) % g.n_refs;
+        int c = (int)(t / (plane * g.n_refs));
+        int l = 0;
+        while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
+        int local = (int)(r - g.ref_base[l]);
+        int Bp = local / g.na_l[l + 1], Ap = local % g.na_l[l + 1];
+        int node = g.node_base[l] + (2 * Bp) * g.na_l[l] + 2 * Ap;
+        int y = (int)(px / g.w), x = (int)(px % g.w);
+        int blk = (y / g.bs) * g.nbx + x / g.bs;
+        int i = (y % g.bs) * g.bs + x % g.bs;
+        refs[t] = (int16_t)lf_residual(g, p, c, l, node, blk, i);
+    }
+}
+
+extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
+                                        void* stream, lf_handle** out)
+{
+    if (!out || !d_arena) return lf_fail(LF_EINVAL, "null argument");
+    *out = nullptr;
+    LfLayout L;
+    lf_status st = lf_parse((const uint8_t*)host_stream, nbytes, &L);
+    if (st != LF_OK) return st;
+    if (arena_bytes < L.arena)
+        return lf_fail(LF_ENOMEM, "arena of %lld bytes, %lld needed", (long long)arena_bytes, (long long)L.arena);
+    if (((uintptr_t)d_arena) & 255) return lf_fail(LF_EINVAL, "arena must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* A = (uint8_t*)d_arena;
+    const uint8_t* S = (const uint8_t*)host_stream;
+    struct {
+        int64_t dst;
+        uint64_t src, n;
+    } cp[4] = {{L.a_root, L.root_off, L.root_bytes},
+               {L.a_table, L.table_off, L.table_bytes},
+               {L.a_payload, L.payload_off, L.payload_bytes},
+               {L.a_mv, L.mv_off, L.mv_bytes}};
+    for (auto& c : cp)
+        if (hipMemcpyAsync(A + c.dst, S + c.src, c.n, hipMemcpyHostToDevice, s) != hipSuccess)
+            return lf_fail(LF_EDEVICE, "upload failed");
+    lf_handle* h = new (std::nothrow) lf_handle;
+    if (!h) return lf_fail(LF_EINVAL, "out of host memory");
+    h->L = L;
+    h->arena = A;
+    h->p.root = (const int16_t*)(A + L.a_root);
+    h->p.table = (const uint2*)(A + L.a_table);
+    h->p.payload = (const uint32_t*)(A + L.a_payload);
+    h->p.mv = (const uint32_t*)(A + L.a_mv);
+    h->p.refs = (const int16_t*)(A + L.a_refs);
+    const int64_t total = 3 * (int64_t)L.g.n_refs * L.g.w * L.g.h;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (total > 0) {
+        hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs);
+        st = lf_check_launch("load_refs");
+        if (st != LF_OK) {
+            delete h;
+            return st;
+        }
+    }
+    // the caller may free host_stream on return: finish the copies
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        delete h;
+        return lf_fail(LF_EDEVICE, "stream synchronise failed");
+    }
+    *out = h;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_free(lf_handle* h)
+{
+    delete h;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
+{
+    if (!h || !o) return lf_fail(LF_EINVAL, "null argument");
+    const LfGeom& g = h->L.g;
+    o->na = g.na;
+    o->nb = g.nb;
+    o->width = g.w;
+    o->height = g.h;
+    o->levels = g.H;
+    o->block = g.bs;
+    o->root_na = g.root_na;
+    o->root_nb = g.root_nb;
+    o->n_nodes = g.n_nodes;
+    o->n_pred_records = h->L.n_rec;
+    o->n_refs = g.n_refs;
+    o->arena_bytes = h->L.arena;
+    o->stream_bytes = h->L.stream_bytes;
+    o->payload_bytes = (int64_t)h->L.payload_bytes;
+    return LF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// random-access sample decoding
+// ---------------------------------------------------------------------------
+
+__global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ coords, int64_t n,
+                                uint8_t* __restrict__ rgb)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int4 q = reinterpret_cast<const int4*>(coords)[k];
+    int b = lf_clampi(q.x, 0, g.nb - 1), a = lf_clampi(q.y, 0, g.na - 1);
+    int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
+    int Y = lf_decode_channel(g, p, 0, b, a, y, x);
+    int Co = lf_decode_channel(g, p, 1, b, a, y, x);
+    int Cg = lf_decode_channel(g, p, 2, b, a, y, x);
+    int r, gg, bl;
+    lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
+    rgb[3 * k] = (uint8_t)r;
+    rgb[3 * k + 1] = (uint8_t)gg;
+    rgb[3 * k + 2] = (uint8_t)bl;
+}
+
+extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t n, uint8_t* d_rgb,
+                                      void* stream)
+{
+    if (!h || n < 0) return lf_fail(LF_EINVAL, "bad argument");
+    if (n == 0) return LF_OK;
+    if (!d_coords || !d_rgb) return lf_fail(LF_EINVAL, "null buffer");
+    if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
+    hipLaunchKernelGGL(k_decode_pixels, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->L.g, h->p,
+                       d_coords, n, d_rgb);
+    return lf_check_launch("decode_pixels");
+}
+
+// ---------------------------------------------------------------------------
+// ray coordinates (exposed for checking the renderer's arithmetic)
+// ---------------------------------------------------------------------------
+
+__global__ void k_ray_coords(const float* __restrict__ cams, int nv, int wo, int ho, float4* __restrict__ out)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t npix = (int64_t)wo * ho;
+    if (r >= npix * nv) return;
+    int v = (int)(r / npix);
+    int j = (int)((r % npix) / wo), i = (int)(r % wo);
+    float u, vv, s, t;
+    lf_ray(cams + 18 * v, i, j, u, vv, s, t);
+    out[r] = make_float4(u, vv, s, t);
+}
+
+extern "C" lf_status lf_ray_coords(const float* d_cams, int32_t n_views, int32_t width, int32_t height,
+                                   float* d_uvst, void* stream)
+{
+    if (!d_cams || !d_uvst || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    int64_t total = (int64_t)n_views * width * height;
+    if (total == 0) return LF_OK;
+    hipLaunchKernelGGL(k_ray_coords, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       d_cams, n_views, width, height, (float4*)d_uvst);
+    return lf_check_launch("ray_coords");
+}

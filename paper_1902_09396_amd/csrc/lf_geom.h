@@ -1,0 +1,199 @@
+// Stream geometry and device-side decoding primitives of the HMLFC library.
+//
+// The tree (RLFC: Hierarchical Compression Scheme) has levels 0 (leaf views)
+// .. H (root RKVs); level l+1 clusters the 2x2 grid-aligned nodes of level l,
+// so node (B, A) of level l has parent (B >> 1, A >> 1).  In every cluster the
+// (even, even) node is the reference SRV; the others are predictive SRVs,
+// motion-compensated against it (Phase-shifted Motion Compensation).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define LF_MAX_LEVELS 8
+#define LF_HDR_BYTES 1024
+#define LF_MODE_ZERO 0xFF
+
+struct LfGeom {
+    int na, nb, w, h, H, bs, nbx, nblk;
+    int na_l[LF_MAX_LEVELS + 1], nb_l[LF_MAX_LEVELS + 1];
+    int node_base[LF_MAX_LEVELS];  // first BFS node index of each level
+    int ref_base[LF_MAX_LEVELS];   // first reference plane of each level
+    int step[LF_MAX_LEVELS];       // dequantisation step
+    int bias[LF_MAX_LEVELS];       // 4 * search window: motion-vector offset
+    int n_nodes, n_refs;
+    int root_na, root_nb;
+    uint32_t mv_word[3][LF_MAX_LEVELS];
+    uint32_t sig_word[3][LF_MAX_LEVELS];
+    int mv_mode[3][LF_MAX_LEVELS];
+    int64_t rec_base[3][LF_MAX_LEVELS];  // motion record base (relaxed shift index)
+};
+
+struct LfPtrs {
+    const int16_t* root;      // [3][root_nb][root_na][h][w]
+    const uint2* table;       // [3][n_nodes][nblk]: x = payload word, y = min | mode << 16
+    const uint32_t* payload;  // block payload words (+ slack)
+    const uint32_t* mv;       // motion-vector section words (+ slack)
+    const int16_t* refs;      // [3][n_refs][h][w] decoded reference SRVs
+};
+
+// Ordinal of predictive node (B, A) among the predictive nodes of its level,
+// raster order: rows with odd B are entirely predictive, rows with even B
+// only at odd A.
+__host__ __device__ inline int pred_ordinal(int na_l, int B, int A)
+{
+    return (B >> 1) * na_l + ((B + 1) >> 1) * (na_l >> 1) + ((B & 1) ? A : (A >> 1));
+}
+
+// ---------------------------------------------------------------------------
+// Bounded integer sequences (Bounded Integer Sequence Encoding).  Mode byte:
+// family in bits 7..5 (0: b-bit fields; 1: groups of 5 = 8-bit base-3 high
+// part + five b-bit low parts; 2: groups of 3 = 7-bit base-5 high part +
+// three b-bit low parts), b in bits 4..0.  LSB-first bit order; every field
+// lies inside a 64-bit window starting at its word.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lf_field(const uint32_t* __restrict__ w, uint32_t pos, int n)
+{
+    uint32_t q = pos >> 5;
+    uint64_t x = ((uint64_t)w[q + 1] << 32) | w[q];
+    return (uint32_t)(x >> (pos & 31u)) & ((1u << n) - 1u);
+}
+
+__device__ __forceinline__ uint32_t lf_bise_get(const uint32_t* __restrict__ w, int mode, uint32_t i)
+{
+    const int fam = mode >> 5, b = mode & 31;
+    if (fam == 0) return lf_field(w, i * (uint32_t)b, b);
+    if (fam == 1) {
+        uint32_t g = i / 5u, k = i - 5u * g;
+        uint32_t base = g * (uint32_t)(8 + 5 * b);
+        uint32_t t = lf_field(w, base, 8);
+        for (uint32_t s = 0; s < k; s++) t /= 3u;
+        uint32_t lo = lf_field(w, base + 8u + k * (uint32_t)b, b);
+        return ((t % 3u) << b) | lo;
+    }
+    uint32_t g = i / 3u, k = i - 3u * g;
+    uint32_t base = g * (uint32_t)(7 + 3 * b);
+    uint32_t q = lf_field(w, base, 7);
+    for (uint32_t s = 0; s < k; s++) q /= 5u;
+    uint32_t lo = lf_field(w, base + 7u + k * (uint32_t)b, b);
+    return ((q % 5u) << b) | lo;
+}
+
+// Dequantised residual of pixel i of block blk of BFS node `node` (level l).
+__device__ __forceinline__ int lf_residual(const LfGeom& g, const LfPtrs& p, int c, int l, int node, int blk,
+                                           int i)
+{
+    uint2 e = p.table[((size_t)c * g.n_nodes + node) * g.nblk + blk];
+    int mode = (int)((e.y >> 16) & 0xFFu);
+    if (mode == LF_MODE_ZERO) return 0;
+    int mn = (int)(int16_t)(e.y & 0xFFFFu);
+    return (mn + (int)lf_bise_get(p.payload + e.x, mode, (uint32_t)i)) * g.step[l];
+}
+
+// Motion record j of (channel c, level l): quarter-pel vector and phase.
+__device__ __forceinline__ void lf_motion(const LfGeom& g, const LfPtrs& p, int c, int l, uint32_t j, int& mx,
+                                          int& my, int& sg)
+{
+    const uint32_t* w = p.mv + g.mv_word[c][l];
+    const int mode = g.mv_mode[c][l];
+    mx = (int)lf_bise_get(w, mode, 2u * j) - g.bias[l];
+    my = (int)lf_bise_get(w, mode, 2u * j + 1u) - g.bias[l];
+    uint32_t code = lf_field(p.mv + g.sig_word[c][l], 2u * j, 2);
+    sg = code == 0u ? 1 : (code == 1u ? -1 : 0);
+}
+
+__device__ __forceinline__ int lf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// Quarter-pel bilinear prediction from an int16 reference plane, taps
+// clamped to the plane, rounded as (sum w * tap + 8) >> 4 with weights
+// (4 - fx)(4 - fy), fx(4 - fy), (4 - fx)fy, fx fy.
+__device__ __forceinline__ int lf_qpel(const int16_t* __restrict__ plane, int w, int h, int y, int x, int mx,
+                                       int my)
+{
+    int X = 4 * x + mx, Y = 4 * y + my;
+    int x0 = X >> 2, y0 = Y >> 2, fx = X & 3, fy = Y & 3;
+    int xa = lf_clampi(x0, 0, w - 1), xb = lf_clampi(x0 + 1, 0, w - 1);
+    int ya = lf_clampi(y0, 0, h - 1), yb = lf_clampi(y0 + 1, 0, h - 1);
+    int acc = (4 - fx) * (4 - fy) * plane[ya * w + xa] + fx * (4 - fy) * plane[ya * w + xb] +
+              (4 - fx) * fy * plane[yb * w + xa] + fx * fy * plane[yb * w + xb];
+    return (acc + 8) >> 4;
+}
+
+__device__ __forceinline__ const int16_t* lf_ref_plane(const LfGeom& g, const LfPtrs& p, int c, int l, int Bp,
+                                                       int Ap)
+{
+    return p.refs + ((size_t)c * g.n_refs + g.ref_base[l] + Bp * g.na_l[l + 1] + Ap) * (size_t)(g.w * g.h);
+}
+
+// One YCoCg channel of sample (b, a, y, x): root RKV plus the SRV of every
+// level on the path (Decoding Procedure).  Reference SRVs come from the
+// resident planes; predictive SRVs are residual + phase * prediction.
+__device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c, int b, int a, int y, int x)
+{
+    const int plane = g.w * g.h;
+    int v = p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * plane + y * g.w + x];
+    const int blk = (y / g.bs) * g.nbx + x / g.bs;
+    const int i = (y % g.bs) * g.bs + x % g.bs;
+    for (int l = 0; l < g.H; l++) {
+        int B = b >> l, A = a >> l;
+        const int16_t* ref = lf_ref_plane(g, p, c, l, B >> 1, A >> 1);
+        if (!((A | B) & 1)) {
+            v += ref[y * g.w + x];
+            continue;
+        }
+        int node = g.node_base[l] + B * g.na_l[l] + A;
+        int r = lf_residual(g, p, c, l, node, blk, i);
+        int mx, my, sg;
+        lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
+        if (sg) r += sg * lf_qpel(ref, g.w, g.h, y, x, mx, my);
+        v += r;
+    }
+    return v;
+}
+
+// Inverse reversible YCoCg lifting, then clamp to 8 bits.
+__device__ __forceinline__ void lf_ycocg_to_rgb(int Y, int Co, int Cg, int& r, int& gg, int& b)
+{
+    int t = Y - (Cg >> 1);
+    gg = Cg + t;
+    b = t - (Co >> 1);
+    r = b + Co;
+    r = lf_clampi(r, 0, 255);
+    gg = lf_clampi(gg, 0, 255);
+    b = lf_clampi(b, 0, 255);
+}
+
+// Ray coordinates: (h0 px + h1 py) + h2 per row, each product and sum
+// rounded separately (no fused multiply-add), then one IEEE division.
+__device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float& u, float& v, float& s, float& t)
+{
+#pragma clang fp contract(off)
+    const float px = (float)i + 0.5f, py = (float)j + 0.5f;
+    float q[6];
+#pragma unroll
+    for (int r = 0; r < 6; r++) {
+        const float* h = cam + (r < 3 ? 0 : 9) + 3 * (r % 3);
+        float a = h[0] * px;
+        float bb = h[1] * py;
+        float sum = a + bb;
+        q[r] = sum + h[2];
+    }
+    u = q[0] / q[2];
+    v = q[1] / q[2];
+    s = q[3] / q[5];
+    t = q[4] / q[5];
+}
+
+// Clamp a coordinate to [0, n-1]; lower neighbour k (<= n-2), upper
+// neighbour, fraction c - k.
+__device__ __forceinline__ void lf_axis(float c, int n, int& k0, int& k1, float& f)
+{
+    c = fminf(fmaxf(c, 0.0f), (float)(n - 1));
+    int k = (int)floorf(c);
+    k = min(k, n - 2);
+    k = max(k, 0);
+    k0 = k;
+    k1 = min(k + 1, n - 1);
+    f = c - (float)k;
+}

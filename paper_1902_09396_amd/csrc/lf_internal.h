@@ -1,0 +1,27 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <cstdarg>
+#include <cstdint>
+
+#include "../../include/hmlfc.h"
+#include "lf_geom.h"
+
+struct LfLayout {
+    LfGeom g;
+    uint64_t root_off, root_bytes, table_off, table_bytes, payload_off, payload_bytes, mv_off, mv_bytes;
+    int64_t n_rec;        // motion records over all channels and levels
+    int64_t stream_bytes;
+    // arena offsets
+    int64_t a_root, a_table, a_payload, a_mv, a_refs, arena;
+};
+
+struct lf_handle {
+    LfLayout L;
+    uint8_t* arena;
+    LfPtrs p;
+};
+
+lf_status lf_fail(lf_status s, const char* fmt, ...);
+lf_status lf_check_launch(const char* what);
+lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L);

@@ -1,0 +1,172 @@
+"""Python binding of libhmlfc.so: argument marshalling only.
+
+Every step of decoding and rendering runs in the library's HIP kernels; torch
+provides device memory and the current stream.  There is no CPU fallback: if
+the library is missing or no GPU is visible, calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhmlfc.so")
+
+LF_OK, LF_EINVAL, LF_ENOMEM, LF_EFORMAT, LF_EDEVICE = 0, -1, -2, -3, -4
+_NAMES = {LF_EINVAL: "LF_EINVAL", LF_ENOMEM: "LF_ENOMEM", LF_EFORMAT: "LF_EFORMAT", LF_EDEVICE: "LF_EDEVICE"}
+
+
+class LFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class LfInfo(C.Structure):
+    _fields_ = [("na", C.c_int32), ("nb", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("levels", C.c_int32), ("block", C.c_int32), ("root_na", C.c_int32), ("root_nb", C.c_int32),
+                ("n_nodes", C.c_int64), ("n_pred_records", C.c_int64), ("n_refs", C.c_int64),
+                ("arena_bytes", C.c_int64), ("stream_bytes", C.c_int64), ("payload_bytes", C.c_int64)]
+
+
+_lib = None
+
+# C-ABI entry points: name -> (restype, argtypes)
+_P, _I32, _I64, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+SIGNATURES = {
+    "lf_query_arena": (C.c_int, [_P, _SZ, _P]),
+    "lf_load_compressed": (C.c_int, [_P, _SZ, _P, _I64, _P, _P]),
+    "lf_free": (C.c_int, [_P]),
+    "lf_get_info": (C.c_int, [_P, _P]),
+    "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
+    "lf_render_views": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
+    "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libhmlfc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhmlfc.so is not built; run __graft_entry__.build() or "
+                               "python paper_1902_09396_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != LF_OK:
+        raise LFError(status, lib().lf_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s" % (name, dtype))
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the HMLFC library runs only on the GPU")
+
+
+class LightField:
+    """A compressed light field resident in device memory."""
+
+    def __init__(self, stream, device=None):
+        require_gpu()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        host = np.ascontiguousarray(np.frombuffer(bytes(stream), np.uint8) if isinstance(stream, (bytes, bytearray))
+                                    else np.asarray(stream, dtype=np.uint8))
+        self.stream_bytes = host.size
+        need = C.c_int64()
+        check(lib().lf_query_arena(host.ctypes.data_as(C.c_void_p), host.size, C.byref(need)))
+        with torch.cuda.device(self.device):
+            # torch's caching allocator returns 512-byte aligned blocks
+            self.arena = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            check(lib().lf_load_compressed(host.ctypes.data_as(C.c_void_p), host.size, _ptr(self.arena),
+                                           int(need.value), _stream(), C.byref(h)))
+        self._h = h
+        info = LfInfo()
+        check(lib().lf_get_info(self._h, C.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in LfInfo._fields_}
+        self.na, self.nb = info.na, info.nb
+        self.width, self.height = info.width, info.height
+        self.levels, self.block = info.levels, info.block
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lf_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def decode_pixels(self, coords: torch.Tensor) -> torch.Tensor:
+        """coords: int32 [n, 4] (b, a, y, x) on the device -> uint8 [n, 3] RGB."""
+        coords = _dev(coords, torch.int32, "coords").reshape(-1, 4)
+        out = torch.empty((coords.shape[0], 3), dtype=torch.uint8, device=coords.device)
+        check(lib().lf_decode_pixels(self._h, _ptr(coords), coords.shape[0], _ptr(out), _stream()))
+        return out
+
+    def render_views(self, cams: torch.Tensor, width: int, height: int, out: torch.Tensor | None = None):
+        """cams: float32 [V, 18] on the device -> float32 [V, 3, height, width]."""
+        cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+        if out is None:
+            out = torch.empty((cams.shape[0], 3, height, width), dtype=torch.float32, device=cams.device)
+        elif out.shape != (cams.shape[0], 3, height, width) or not out.is_contiguous() or out.dtype != torch.float32:
+            raise ValueError("out must be a contiguous float32 [V, 3, H, W] tensor")
+        check(lib().lf_render_views(self._h, _ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
+        return out
+
+    def footprint_bytes(self, cams: torch.Tensor, width: int, height: int) -> np.ndarray:
+        cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+        out = np.zeros(cams.shape[0], dtype=np.float64)
+        check(lib().lf_footprint_bytes(self._h, _ptr(cams), cams.shape[0], width, height,
+                                       out.ctypes.data_as(C.c_void_p), _stream()))
+        return out
+
+
+def ray_coords(cams: torch.Tensor, width: int, height: int) -> torch.Tensor:
+    """(u, v, s, t) per output pixel as the renderer computes them: [V, H, W, 4]."""
+    cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+    out = torch.empty((cams.shape[0], height, width, 4), dtype=torch.float32, device=cams.device)
+    check(lib().lf_ray_coords(_ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
+    return out
+
+
+def query_arena(stream) -> int:
+    host = np.ascontiguousarray(np.asarray(stream, dtype=np.uint8))
+    need = C.c_int64()
+    check(lib().lf_query_arena(host.ctypes.data_as(C.c_void_p), host.size, C.byref(need)))
+    return int(need.value)
