@@ -1,0 +1,206 @@
+"""Benchmark: fused random-access decode + novel-view rendering on one MI355X.
+
+Workload: a 17x17 grid of 512x512 RGB views (seeded layered scene with six
+planes in front of a smooth-depth terrain, disparity in [-4, 4] px), encoded
+with a 4-level tree, 16x16 blocks, quarter-pel motion vectors and step 4;
+a step renders the 120-frame 512x512 orbit camera path in one launch.
+
+Prints one JSON line: rays/s for the whole job, the render kernel's achieved
+algorithmic bytes per second against the HBM peak (algorithmic bytes = the
+per-view footprint bytes of the 120 views), p50/p99 single-view latency, and
+the CPU oracle timed on a bounded sample of the same rays.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "rendered rays/sec (Grays/s) + achieved HBM GB/s; p50/p99 view latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_path512_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("lf_geom.h", "lf_render.hip", "lf_core.hip"):
+        with open(os.path.join(ROOT, "paper_1902_09396_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on this kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="path512")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: automatic)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (views shard across GPUs "
+              "with no per-frame exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    cfg = lfscene.get_config(args.workload)
+    L = cfg["lf"]
+    t0 = time.time()
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    log("scene %.1fs" % (time.time() - t0))
+    t0 = time.time()
+    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+    log("encode %.1fs, %d bytes" % (time.time() - t0, stream.size))
+    field = lf.LightField(stream, device="cuda:0")
+    cams_np = lfscene.make_views(cfg)
+    V, wo, ho = cams_np.shape[0], cfg["views"]["wo"], cfg["views"]["ho"]
+    cams = torch.from_numpy(cams_np).cuda()
+    out = torch.empty((V, 3, ho, wo), dtype=torch.float32, device="cuda")
+    rays_per_step = V * wo * ho
+
+    t0 = time.time()
+    fp = field.footprint_bytes(cams, wo, ho)
+    bytes_per_launch = float(fp.sum())
+    log("footprint %.1fs: %.2f MB/view mean" % (time.time() - t0, fp.mean() / 1e6))
+
+    stream_t = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        field.render_views(cams, wo, ho, out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream_t)
+        field.render_views(cams, wo, ho, out)
+        ev[k][1].record(stream_t)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_per_step = 1e3 * t_total / args.steps
+    value = rays_per_step / (ms_per_step * 1e-3) / 1e9
+
+    # single-view latency: each view alone in its own launch
+    lat = []
+    one = torch.empty((1, 3, ho, wo), dtype=torch.float32, device="cuda")
+    for v in range(V):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream_t)
+        field.render_views(cams[v:v + 1], wo, ho, one)
+        b.record(stream_t)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+    lat = np.array(lat)
+
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = load_traffic()
+    result = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "Grays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%dx%d views of %dx%d RGB, %d-level tree, %dx%d blocks, step %d, quarter-pel MVs; "
+                        "%d-frame %dx%d orbit path per step" % (L["na"], L["nb"], L["w"], L["h"],
+                                                                 cfg["enc"]["levels"], cfg["enc"]["block"],
+                                                                 cfg["enc"]["block"], cfg["enc"]["step"][0], V, wo, ho),
+            "views_per_step": V,
+            "width": wo,
+            "height": ho,
+            "stream_bytes": int(stream.size),
+        },
+        "hbm_gbs": round(achieved, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
+                       "unit": "ms per 512x512 view, one view per launch"},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_render_tiles",
+            "kernel_ms": round(kernel_ms, 4),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg, light, cams_np, wo, ho, args.cpu_rays)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(cfg, light, cams_np, wo, ho, n_rays):
+    """The oracle renders a bounded random sample of the same rays on the host cores."""
+    import oracle
+
+    t0 = time.time()
+    stream = oracle.encode(light, cfg["enc"])
+    log("oracle encode %.1fs" % (time.time() - t0))
+    o = oracle.OracleLF(stream)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    rng = np.random.default_rng(7)
+    # calibrate on a small sample, then size the timed sample to about 15 s
+    probe = 2000
+    rays = np.stack([rng.integers(0, cams_np.shape[0], probe), rng.integers(0, wo, probe),
+                     rng.integers(0, ho, probe)], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    o.render_rays(cams_np, wo, ho, rays)
+    per_ray = (time.perf_counter() - t0) / probe
+    n = n_rays or int(min(max(15.0 / max(per_ray, 1e-9), 10000), 5_000_000))
+    rays = np.stack([rng.integers(0, cams_np.shape[0], n), rng.integers(0, wo, n), rng.integers(0, ho, n)],
+                    1).astype(np.int32)
+    t0 = time.perf_counter()
+    o.render_rays(cams_np, wo, ho, rays)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": cores, "kind": "oracle",
+            "sample": "%d uniformly random rays of the 120-frame path (seed 7), OpenMP over rays, %.1f s" % (n, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -127,6 +127,12 @@ lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t 
 lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                           int32_t height, float* d_out, void* stream);
 
+/* The same rendering with one thread per ray and no staging (every ray walks
+ * its 16 samples' tree paths itself).  Same arguments and results as
+ * lf_render_views, bit for bit; kept as the simple reference path. */
+lf_status lf_render_views_per_ray(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
+                                  int32_t height, float* d_out, void* stream);
+
 /* Ray coordinates as the renderer computes them (binary32, no contraction):
  * d_uvst: device float [n_views][height][width][4] = (u, v, s, t) before
  * clamping.  For checking the renderer's arithmetic. */
@@ -143,6 +149,35 @@ lf_status lf_ray_coords(const float* d_cams, int32_t n_views, int32_t width, int
  * allocates and frees it; this call synchronises `stream`). */
 lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                              int32_t height, double* host_out, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Encoding (host, OpenMP; not on the render path).  Follows the paper's   */
+/* pipeline: reversible YCoCg, RLFC hierarchy of 2x2-cluster rounded-mean  */
+/* RKVs, top-down closed loop with phase-shifted quarter-pel motion        */
+/* compensation of the non-reference SRVs of every cluster (Eq. 1-2),      */
+/* uniform quantisation with the two block thresholds, and bounded-integer */
+/* sequence coding in breadth-first node order.                            */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t levels;      /* tree height H (1..8)                                   */
+    int32_t block;       /* block size Bs (1..64, divides width and height)        */
+    int32_t step[8];     /* quantisation step per level (1 = lossless)             */
+    int32_t t_ref[8];    /* block threshold for reference SRVs                     */
+    int32_t t_pred[8];   /* block threshold for motion-compensated residuals       */
+    int32_t win[8];      /* search window W per level, whole pixels                */
+    int32_t subpel;      /* 1: quarter-pel refinement around the integer best      */
+    int32_t zero_phase;  /* 1: allow "no prediction" when it is strictly cheaper   */
+    int32_t no_mc;       /* 1: no motion compensation (plain hierarchy)            */
+} lf_encode_params;
+
+/* host_lf: host uint8 [nb][na][height][width][3] RGB.  On success
+ * *out_stream is a malloc'ed stream of *out_bytes bytes, released with
+ * lf_encode_free.  threads <= 0 uses the OpenMP default.  Errors: LF_EINVAL
+ * (geometry, parameters, or values outside the stream's integer ranges). */
+lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
+                    const lf_encode_params* params, int32_t threads, uint8_t** out_stream, size_t* out_bytes);
+void lf_encode_free(uint8_t* stream);
 
 /* Message for the calling thread's last non-OK status. */
 const char* lf_last_error(void);

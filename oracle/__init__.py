@@ -66,6 +66,7 @@ def lib():
             "orc_decode_srv": (C.c_int, [P, P]),
             "orc_ray_coords": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, P]),
             "orc_render": (C.c_int, [P, P, C.c_int, C.c_int, C.c_int, C.c_int, P]),
+            "orc_render_rays": (C.c_int, [P, P, C.c_int, C.c_int, P, i64, P]),
             "orc_render_dense": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_int, C.c_int,
                                            C.c_int, P]),
             "orc_footprint_bytes": (C.c_int, [P, P, C.c_int, C.c_int, C.c_int, P]),
@@ -264,6 +265,17 @@ class OracleLF:
         cams = np.ascontiguousarray(cams, dtype=np.float32).reshape(-1, 18)
         out = np.empty((cams.shape[0], 3, ho, wo), dtype=np.float64)
         lib().orc_render(self._h, _p(cams), cams.shape[0], wo, ho, 0, _p(out))
+        return out
+
+    def render_rays(self, cams: np.ndarray, wo: int, ho: int, rays: np.ndarray) -> np.ndarray:
+        """Selected rays (view, i, j) -> float64 [n][3]."""
+        cams = np.ascontiguousarray(cams, dtype=np.float32).reshape(-1, 18)
+        rays = np.ascontiguousarray(rays, dtype=np.int32).reshape(-1, 3)
+        if rays.size and (rays[:, 0].max() >= cams.shape[0] or rays[:, 0].min() < 0):
+            raise ValueError("view index out of range")
+        out = np.empty((rays.shape[0], 3), dtype=np.float64)
+        if lib().orc_render_rays(self._h, _p(cams), wo, ho, _p(rays), rays.shape[0], _p(out)) != 0:
+            raise ValueError("ray out of range")
         return out
 
     def footprint_bytes(self, cams: np.ndarray, wo: int, ho: int) -> np.ndarray:

@@ -126,11 +126,14 @@ static int better(int64_t c, int mx, int my, int64_t bc, int bmx, int bmy)
     return mx < bmx;
 }
 
-static int64_t block_cost(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
-                          int mx, int my, int sigma)
+/* quarter-pel cost with early abandon: stops (returning a value above
+ * `bound`) once the partial sum exceeds it, which cannot change a ranking
+ * that only keeps candidates with cost <= bound */
+static int64_t block_cost_bounded(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
+                                  int mx, int my, int sigma, int64_t bound)
 {
     int64_t s = 0;
-    for (int y = by0; y < by0 + bs; y++)
+    for (int y = by0; y < by0 + bs && s <= bound; y++)
         for (int x = bx0; x < bx0 + bs; x++) {
             int32_t pred = sigma * orc_qpel(r, w, h, y, x, mx, my);
             s += iabs(p[(int64_t)y * w + x] - pred);
@@ -138,58 +141,52 @@ static int64_t block_cost(const int32_t* p, const int32_t* r, int w, int h, int 
     return s;
 }
 
-/* integer-pel cost: orc_qpel with fx = fy = 0 equals the clamped tap itself */
-static int64_t block_cost_int(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
-                              int dx, int dy, int sigma)
-{
-    int64_t s = 0;
-    for (int y = by0; y < by0 + bs; y++) {
-        int yy = orc_clampi(y + dy, 0, h - 1);
-        for (int x = bx0; x < bx0 + bs; x++) {
-            int xx = orc_clampi(x + dx, 0, w - 1);
-            s += iabs(p[(int64_t)y * w + x] - sigma * r[(int64_t)yy * w + xx]);
-        }
-    }
-    return s;
-}
-
 int64_t orc_mc_search(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
                       int win, int subpel, int zero_phase, int* mx, int* my, int* sigma)
 {
-    int64_t best_cost[2];
-    int best_mx[2], best_my[2];
+    /* index 0: sigma = +1 (Eq. 1, subtractive error), index 1: sigma = -1 (Eq. 2, additive error) */
+    int64_t best_cost[2] = {INT64_MAX, INT64_MAX};
+    int best_mx[2] = {0, 0}, best_my[2] = {0, 0};
     const int sig[2] = {+1, -1};
-    for (int si = 0; si < 2; si++) {
-        int64_t bc = INT64_MAX;
-        int bmx = 0, bmy = 0;
-        for (int dy = -win; dy <= win; dy++)
-            for (int dx = -win; dx <= win; dx++) {
-                int64_t c = block_cost_int(p, r, w, h, by0, bx0, bs, dx, dy, sig[si]);
-                if (bc == INT64_MAX || better(c, 4 * dx, 4 * dy, bc, bmx, bmy)) {
-                    bc = c;
-                    bmx = 4 * dx;
-                    bmy = 4 * dy;
+    /* integer positions: Q with fx = fy = 0 is the clamped tap itself, so both
+     * errors are summed directly from the taps in one pass */
+    for (int dy = -win; dy <= win; dy++)
+        for (int dx = -win; dx <= win; dx++) {
+            int64_t cp = 0, cm = 0;
+            for (int y = by0; y < by0 + bs && (cp <= best_cost[0] || cm <= best_cost[1]); y++) {
+                int yy = orc_clampi(y + dy, 0, h - 1);
+                for (int x = bx0; x < bx0 + bs; x++) {
+                    int xx = orc_clampi(x + dx, 0, w - 1);
+                    int32_t pv = p[(int64_t)y * w + x], rv = r[(int64_t)yy * w + xx];
+                    cp += iabs(pv - rv);
+                    cm += iabs(pv + rv);
                 }
             }
-        if (subpel) {
-            int cmx = bmx, cmy = bmy;
+            int64_t c2[2] = {cp, cm};
+            for (int si = 0; si < 2; si++)
+                if (best_cost[si] == INT64_MAX || better(c2[si], 4 * dx, 4 * dy, best_cost[si], best_mx[si], best_my[si])) {
+                    best_cost[si] = c2[si];
+                    best_mx[si] = 4 * dx;
+                    best_my[si] = 4 * dy;
+                }
+        }
+    /* quarter-pel refinement around each phase's integer best */
+    if (subpel)
+        for (int si = 0; si < 2; si++) {
+            int cmx = best_mx[si], cmy = best_my[si];
             for (int ey = -3; ey <= 3; ey++)
                 for (int ex = -3; ex <= 3; ex++) {
                     int qx = cmx + ex, qy = cmy + ey;
                     if (qx < -4 * win || qx > 4 * win || qy < -4 * win || qy > 4 * win) continue;
                     if ((qx & 3) == 0 && (qy & 3) == 0) continue; /* integer positions already ranked */
-                    int64_t c = block_cost(p, r, w, h, by0, bx0, bs, qx, qy, sig[si]);
-                    if (better(c, qx, qy, bc, bmx, bmy)) {
-                        bc = c;
-                        bmx = qx;
-                        bmy = qy;
+                    int64_t c = block_cost_bounded(p, r, w, h, by0, bx0, bs, qx, qy, sig[si], best_cost[si]);
+                    if (better(c, qx, qy, best_cost[si], best_mx[si], best_my[si])) {
+                        best_cost[si] = c;
+                        best_mx[si] = qx;
+                        best_my[si] = qy;
                     }
                 }
         }
-        best_cost[si] = bc;
-        best_mx[si] = bmx;
-        best_my[si] = bmy;
-    }
     int pick = best_cost[1] < best_cost[0] ? 1 : 0;
     *mx = best_mx[pick];
     *my = best_my[pick];
@@ -386,6 +383,7 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
     /* 1. colour transform, I[0][c][b][a] planes */
     int32_t* I[ORC_MAX_LEVELS + 1];
     for (int l = 0; l <= H; l++) I[l] = (int32_t*)malloc(sizeof(int32_t) * 3 * na_l[l] * nb_l[l] * plane);
+#pragma omp parallel for collapse(2) schedule(static)
     for (int b = 0; b < nb; b++)
         for (int a = 0; a < na; a++)
             for (int64_t px = 0; px < plane; px++) {
@@ -401,6 +399,7 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
     /* 2. representative key views: rounded mean over each 2x2 cluster */
     for (int l = 0; l < H; l++) {
         int64_t nv0 = (int64_t)na_l[l] * nb_l[l], nv1 = (int64_t)na_l[l + 1] * nb_l[l + 1];
+#pragma omp parallel for collapse(3) schedule(static)
         for (int c = 0; c < 3; c++)
             for (int B = 0; B < nb_l[l + 1]; B++)
                 for (int A = 0; A < na_l[l + 1]; A++) {

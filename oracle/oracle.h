@@ -99,6 +99,8 @@ int orc_decode_srv(const orc_lf* lf, int32_t* out);
 /* ---- renderer ---- */
 int orc_ray_coords(const float* cam, int wo, int ho, int i, int j, float* uvst4);
 int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int nthreads, double* out);
+int orc_render_rays(const orc_lf* lf, const float* cams, int wo, int ho, const int32_t* rays, int64_t n,
+                    double* out);
 int orc_render_dense(const uint8_t* lf, int nb, int na, int h, int w, const float* cams, int nv,
                      int wo, int ho, double* out);
 int orc_footprint_bytes(const orc_lf* lf, const float* cams, int nv, int wo, int ho, double* out);

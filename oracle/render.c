@@ -125,6 +125,38 @@ int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int 
     return status;
 }
 
+/* Selected rays only: rays[k] = (view, i, j); out[k][3]. */
+int orc_render_rays(const orc_lf* lf, const float* cams, int wo, int ho, const int32_t* rays, int64_t n,
+                    double* out)
+{
+    int status = 0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < n; r++) {
+        int v = rays[3 * r], i = rays[3 * r + 1], j = rays[3 * r + 2];
+        if (i < 0 || i >= wo || j < 0 || j >= ho || v < 0) {
+            status = -1;
+            continue;
+        }
+        footprint fp;
+        ray_footprint(cams + 18 * v, wo, ho, i, j, lf->na, lf->nb, lf->w, lf->h, &fp);
+        int32_t coords[16 * 4];
+        uint8_t rgb[16 * 3];
+        for (int k = 0; k < 16; k++) {
+            coords[4 * k] = fp.b[k >> 3];
+            coords[4 * k + 1] = fp.a[(k >> 2) & 1];
+            coords[4 * k + 2] = fp.y[(k >> 1) & 1];
+            coords[4 * k + 3] = fp.x[k & 1];
+        }
+        if (orc_decode_at(lf, coords, 16, rgb)) status = -1;
+        for (int c = 0; c < 3; c++) {
+            double s[2][2][2][2];
+            for (int k = 0; k < 16; k++) s[k >> 3][(k >> 2) & 1][(k >> 1) & 1][k & 1] = rgb[3 * k + c] / 255.0;
+            out[3 * r + c] = blend16(s, &fp);
+        }
+    }
+    return status;
+}
+
 int orc_render_dense(const uint8_t* L, int nb, int na, int h, int w, const float* cams, int nv, int wo, int ho,
                      double* out)
 {

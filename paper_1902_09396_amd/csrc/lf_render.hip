@@ -83,8 +83,171 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
     return lf_check_launch("render_rays");
 }
 
+// ---------------------------------------------------------------------------
+// Tiled renderer.  A workgroup renders a TW x TH tile of one view.  It first
+// finds the tile's footprint (the box of views and of image pixels its rays
+// touch), decodes every sample of that box once into LDS as packed RGBA8,
+// then each thread blends its ray's 16 samples from LDS.  Rays of one tile
+// share nearly all of their samples, so this replaces 16 tree walks per ray
+// by about 5.  A tile whose footprint exceeds the LDS budget falls back to
+// per-ray decoding (same arithmetic, same result).
+// ---------------------------------------------------------------------------
+
+#define TW 32
+#define TH 8
+#define TILE_THREADS (TW * TH)
+#define FOOT_MAX 6144  // packed samples staged per tile (24 KiB)
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ void __launch_bounds__(TILE_THREADS) k_render_tiles(LfGeom g, LfPtrs p, const float* __restrict__ cams,
+                                                                int nv, int wo, int ho, int tiles_x, int tiles_y,
+                                                                float* __restrict__ out)
+{
+    __shared__ uint32_t foot[FOOT_MAX];
+    __shared__ int red[8][TILE_THREADS / 64];
+    // XCD-aware order: consecutive workgroup ids go round-robin over the 8
+    // XCDs; give each XCD a contiguous range of tiles (neighbouring tiles and
+    // consecutive views share stream data in that XCD's L2).
+    const int64_t n_tiles = (int64_t)tiles_x * tiles_y * nv;
+    const int64_t bid = blockIdx.x;
+    const int64_t per_xcd = (n_tiles + 7) / 8;
+    const int64_t xcd = bid & 7, slot = bid >> 3;
+    const int64_t tile = xcd * per_xcd + slot;
+    if (tile >= n_tiles) return;  // uniform per workgroup
+    const int v = (int)(tile / ((int64_t)tiles_x * tiles_y));
+    const int tt = (int)(tile - (int64_t)v * tiles_x * tiles_y);
+    const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = txi * TW + lx, j = tyi * TH + ly;
+    const bool live = i < wo && j < ho;
+    const float* cam = cams + 18 * v;
+
+    float u, vv, s, t;
+    lf_ray(cam, live ? i : txi * TW, live ? j : tyi * TH, u, vv, s, t);
+    int a0, a1, b0, b1, x0, x1, y0, y1;
+    float fu, fv, fs, ft;
+    lf_axis(u, g.na, a0, a1, fu);
+    lf_axis(vv, g.nb, b0, b1, fv);
+    lf_axis(s, g.w, x0, x1, fs);
+    lf_axis(t, g.h, y0, y1, ft);
+
+    // footprint box of the tile (dead lanes repeat the tile's first ray)
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int r0 = wave_min(a0), r1 = wave_max(a1), r2 = wave_min(b0), r3 = wave_max(b1);
+    int r4 = wave_min(x0), r5 = wave_max(x1), r6 = wave_min(y0), r7 = wave_max(y1);
+    if (lane == 0) {
+        red[0][wid] = r0;
+        red[1][wid] = r1;
+        red[2][wid] = r2;
+        red[3][wid] = r3;
+        red[4][wid] = r4;
+        red[5][wid] = r5;
+        red[6][wid] = r6;
+        red[7][wid] = r7;
+    }
+    __syncthreads();
+    int amin = red[0][0], amax = red[1][0], bmin = red[2][0], bmax = red[3][0];
+    int xmin = red[4][0], xmax = red[5][0], ymin = red[6][0], ymax = red[7][0];
+#pragma unroll
+    for (int k = 1; k < TILE_THREADS / 64; k++) {
+        amin = min(amin, red[0][k]);
+        amax = max(amax, red[1][k]);
+        bmin = min(bmin, red[2][k]);
+        bmax = max(bmax, red[3][k]);
+        xmin = min(xmin, red[4][k]);
+        xmax = max(xmax, red[5][k]);
+        ymin = min(ymin, red[6][k]);
+        ymax = max(ymax, red[7][k]);
+    }
+    const int nva = amax - amin + 1, nvb = bmax - bmin + 1;
+    const int sx = xmax - xmin + 1, sy = ymax - ymin + 1;
+    const int np = sx * sy;
+    const int64_t items = (int64_t)nva * nvb * np;
+    float o[3];
+    if (items <= FOOT_MAX) {
+        // decode the footprint once
+        for (int it = threadIdx.x; it < (int)items; it += TILE_THREADS) {
+            const int vi = it / np, pi = it - vi * np;
+            const int b = bmin + vi / nva, a = amin + vi % nva;
+            const int y = ymin + pi / sx, x = xmin + pi % sx;
+            int Y = lf_decode_channel(g, p, 0, b, a, y, x);
+            int Co = lf_decode_channel(g, p, 1, b, a, y, x);
+            int Cg = lf_decode_channel(g, p, 2, b, a, y, x);
+            int r, gg, bl;
+            lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
+            foot[it] = (uint32_t)r | ((uint32_t)gg << 8) | ((uint32_t)bl << 16);
+        }
+        __syncthreads();
+        // blend
+        float view[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int b = (q >> 1) ? b1 : b0, a = (q & 1) ? a1 : a0;
+            const int base = ((b - bmin) * nva + (a - amin)) * np;
+            uint32_t sm[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int y = (k >> 1) ? y1 : y0, x = (k & 1) ? x1 : x0;
+                sm[k] = foot[base + (y - ymin) * sx + (x - xmin)];
+            }
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                float c00 = (float)((sm[0] >> (8 * c)) & 255u) / 255.0f;
+                float c01 = (float)((sm[1] >> (8 * c)) & 255u) / 255.0f;
+                float c10 = (float)((sm[2] >> (8 * c)) & 255u) / 255.0f;
+                float c11 = (float)((sm[3] >> (8 * c)) & 255u) / 255.0f;
+                view[q][c] = lf_lerp(lf_lerp(c00, c01, fs), lf_lerp(c10, c11, fs), ft);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; c++) o[c] = lf_lerp(lf_lerp(view[0][c], view[1][c], fu), lf_lerp(view[2][c], view[3][c], fu), fv);
+    } else {
+        lf_render_one(g, p, cam, i, j, o);
+    }
+    if (live) {
+        const int64_t npix = (int64_t)wo * ho;
+        const int64_t px = (int64_t)j * wo + i;
+#pragma unroll
+        for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
+    }
+}
+
+lf_status lf_launch_render_tiles(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,
+                                 hipStream_t s)
+{
+    const int tx = (wo + TW - 1) / TW, ty = (ho + TH - 1) / TH;
+    const int64_t n_tiles = (int64_t)tx * ty * nv;
+    const int64_t grid = ((n_tiles + 7) / 8) * 8;
+    if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
+    hipLaunchKernelGGL(k_render_tiles, dim3((unsigned)grid), dim3(TILE_THREADS), 0, s, h->L.g, h->p, d_cams, nv, wo,
+                       ho, tx, ty, d_out);
+    return lf_check_launch("render_tiles");
+}
+
 extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                                      int32_t height, float* d_out, void* stream)
+{
+    if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (n_views == 0) return LF_OK;
+    if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
+    return lf_launch_render_tiles(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
+}
+
+extern "C" lf_status lf_render_views_per_ray(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
+                                             int32_t height, float* d_out, void* stream)
 {
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;

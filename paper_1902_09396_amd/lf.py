@@ -44,8 +44,11 @@ SIGNATURES = {
     "lf_get_info": (C.c_int, [_P, _P]),
     "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
     "lf_render_views": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_render_views_per_ray": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_encode": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
+    "lf_encode_free": (None, [_P]),
     "lf_last_error": (C.c_char_p, []),
 }
 
@@ -139,14 +142,18 @@ class LightField:
         check(lib().lf_decode_pixels(self._h, _ptr(coords), coords.shape[0], _ptr(out), _stream()))
         return out
 
-    def render_views(self, cams: torch.Tensor, width: int, height: int, out: torch.Tensor | None = None):
-        """cams: float32 [V, 18] on the device -> float32 [V, 3, height, width]."""
+    def render_views(self, cams: torch.Tensor, width: int, height: int, out: torch.Tensor | None = None,
+                     per_ray: bool = False):
+        """cams: float32 [V, 18] on the device -> float32 [V, 3, height, width].
+
+        per_ray=True selects the unstaged one-thread-per-ray kernel (same results)."""
         cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
         if out is None:
             out = torch.empty((cams.shape[0], 3, height, width), dtype=torch.float32, device=cams.device)
         elif out.shape != (cams.shape[0], 3, height, width) or not out.is_contiguous() or out.dtype != torch.float32:
             raise ValueError("out must be a contiguous float32 [V, 3, H, W] tensor")
-        check(lib().lf_render_views(self._h, _ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
+        fn = lib().lf_render_views_per_ray if per_ray else lib().lf_render_views
+        check(fn(self._h, _ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
         return out
 
     def footprint_bytes(self, cams: torch.Tensor, width: int, height: int) -> np.ndarray:
@@ -163,6 +170,30 @@ def ray_coords(cams: torch.Tensor, width: int, height: int) -> torch.Tensor:
     out = torch.empty((cams.shape[0], height, width, 4), dtype=torch.float32, device=cams.device)
     check(lib().lf_ray_coords(_ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
     return out
+
+
+class EncodeParams(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("block", C.c_int32), ("step", C.c_int32 * 8), ("t_ref", C.c_int32 * 8),
+                ("t_pred", C.c_int32 * 8), ("win", C.c_int32 * 8), ("subpel", C.c_int32), ("zero_phase", C.c_int32),
+                ("no_mc", C.c_int32)]
+
+
+def encode(light_field: np.ndarray, enc: dict, threads: int = 0) -> np.ndarray:
+    """Encode a uint8 [nb][na][h][w][3] light field on the host; returns the stream bytes."""
+    lf = np.ascontiguousarray(light_field, dtype=np.uint8)
+    nb, na, h, w, _ = lf.shape
+    p = EncodeParams()
+    p.levels, p.block = enc["levels"], enc["block"]
+    for l in range(enc["levels"]):
+        p.step[l], p.t_ref[l], p.t_pred[l], p.win[l] = enc["step"][l], enc["t_ref"][l], enc["t_pred"][l], enc["win"][l]
+    p.subpel, p.zero_phase, p.no_mc = int(enc.get("subpel", True)), int(enc.get("zero_phase", False)), \
+        int(enc.get("no_mc", False))
+    out = C.c_void_p()
+    n = C.c_size_t()
+    check(lib().lf_encode(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads, C.byref(out), C.byref(n)))
+    buf = np.ctypeslib.as_array(C.cast(out, C.POINTER(C.c_uint8)), shape=(n.value,)).copy()
+    lib().lf_encode_free(out)
+    return buf
 
 
 def query_arena(stream) -> int:

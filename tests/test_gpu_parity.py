@@ -133,6 +133,22 @@ def test_render_mid_orbit(torch_mod, lfmod, mid_stream, mid_oracle):
     assert np.abs(got - expect).max() <= RENDER_TOL
 
 
+def test_tiled_equals_per_ray(torch_mod, lfmod, mid_stream, tiny_stream, tiny_cams_ez):
+    torch = torch_mod
+    M = lfmod.LightField(mid_stream)
+    cams = _cams_dev(torch, lfscene.camera_path_orbit(6, 17, 17, 128, 128, 100, 70))
+    a = M.render_views(cams, 100, 70).cpu().numpy()
+    b = M.render_views(cams, 100, 70, per_ray=True).cpu().numpy()
+    assert np.array_equal(a, b)
+    # zoomed-out wide cameras: footprints exceed the staging budget and take the per-ray branch
+    T = lfmod.LightField(tiny_stream)
+    wide = lfscene.random_pinhole_cameras(3, 8, 8, 64, 64, 40, 40, seed=5, ez_range=(-8.0, -6.0),
+                                          zoom_range=(4.0, 6.0), rho=1.0)
+    a = T.render_views(_cams_dev(torch, wide), 40, 40).cpu().numpy()
+    b = T.render_views(_cams_dev(torch, wide), 40, 40, per_ray=True).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
 def test_render_deterministic(torch_mod, lfmod, mid_stream):
     torch = torch_mod
     cams = _cams_dev(torch, lfscene.camera_path_orbit(8, 17, 17, 128, 128, 96, 80))
