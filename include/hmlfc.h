@@ -151,6 +151,40 @@ lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams, int32_t n_
                              int32_t height, double* host_out, void* stream);
 
 /* ---------------------------------------------------------------------- */
+/* Relaxed model and adjoint (encoder-side refinement).  Parameters: a     */
+/* real residual for every SRV value, float [3][n_nodes][height][width]    */
+/* in breadth-first node order, and a real shift per motion-compensated    */
+/* block, float [n_pred_records][2] = (dx, dy) in pixels, records ordered  */
+/* by channel, then level from H-1 down to 0, then predictive node (raster */
+/* order), then block.  A reference SRV equals its residual plane; a       */
+/* predictive SRV is phase * bilinear(reference, shifted by (dx, dy)) plus */
+/* its residual (the motion re-compensation of the Decoding Procedure with */
+/* real values and no rounding); the colour inverse is linear, nothing is  */
+/* clamped, and rays blend as in lf_render_views.                          */
+/* ---------------------------------------------------------------------- */
+
+/* Dequantised residuals and motion vectors / 4 of the loaded stream. */
+lf_status lf_export_params(const lf_handle* h, float* d_residual, float* d_shift, void* stream);
+
+/* Relaxed forward render; same camera and output layout as lf_render_views. */
+lf_status lf_render_relaxed(const lf_handle* h, const float* d_residual, const float* d_shift, const float* d_cams,
+                            int32_t n_views, int32_t width, int32_t height, float* d_out, void* stream);
+
+/* Device workspace bytes lf_render_backward needs for this view batch. */
+lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, int32_t width, int32_t height, int64_t* bytes);
+
+/* Adjoint of lf_render_relaxed: given d_grad_out = dL/d(out) (same layout
+ * as the output), writes dL/d(residual) and dL/d(shift) (overwritten, not
+ * accumulated).  Deterministic and free of atomics: the forward's ray
+ * geometry is recomputed, never stored.  d_workspace: caller-owned,
+ * 256-byte aligned, >= lf_backward_workspace bytes.  Errors: LF_EINVAL,
+ * LF_ENOMEM (workspace too small), LF_EDEVICE. */
+lf_status lf_render_backward(const lf_handle* h, const float* d_residual, const float* d_shift, const float* d_cams,
+                             int32_t n_views, int32_t width, int32_t height, const float* d_grad_out,
+                             float* d_grad_residual, float* d_grad_shift, void* d_workspace, int64_t workspace_bytes,
+                             void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Encoding (host, OpenMP; not on the render path).  Follows the paper's   */
 /* pipeline: reversible YCoCg, RLFC hierarchy of 2x2-cluster rounded-mean  */
 /* RKVs, top-down closed loop with phase-shifted quarter-pel motion        */

@@ -1,0 +1,516 @@
+// Relaxed (real-valued) forward model and its adjoint, for encoder-side
+// refinement of the dequantised residual planes and per-block shifts.
+//
+// Relaxed model: parameters are a real residual for every SRV value,
+// res[c][node][y][x] (BFS node order), and a real shift per motion-compensated
+// block, shift[rec] = (dx, dy) in pixels (initially the quarter-pel vector / 4;
+// Phase-shifted Motion Compensation).  A reference SRV equals its residual
+// plane; a predictive SRV is phase * bilinear(reference, shifted) + its
+// residual, without rounding; a sample is root + the sum of its path's SRVs;
+// the colour inverse is the linear one (R = Y + Co/2 - Cg/2, G = Y + Cg/2,
+// B = Y - Co/2 - Cg/2); nothing is clamped; rendering is the quadrilinear
+// blend of the renderer.  Within a block every pixel has the same bilinear
+// fraction (floor(x + dx) = x + floor(dx)), which both directions use.
+//
+// Adjoint, deterministic and without atomics:
+//  1. every ray emits (sample index, ray * 16 + corner) pairs;
+//  2. a stable radix sort groups them by sample;
+//  3. a segmented reduction walks each sample's run in ray order, recomputes
+//     each ray's blend weight from its camera (nothing of the forward is
+//     stored) and applies the colour transpose;
+//  4. node gradients are summed up the tree level by level in fixed order;
+//  5. each reference residual pulls the phase-signed bilinear transpose of
+//     its predictive siblings' gradients;
+//  6. each block's shift gradient is a fixed-order workgroup reduction.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "lf_internal.h"
+
+__device__ __forceinline__ float ad_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
+
+struct AdRay {
+    int a0, a1, b0, b1, x0, x1, y0, y1;
+    float fu, fv, fs, ft;
+};
+
+__device__ __forceinline__ AdRay ad_ray(const LfGeom& g, const float* __restrict__ cam, int i, int j)
+{
+    AdRay r;
+    float u, v, s, t;
+    lf_ray(cam, i, j, u, v, s, t);
+    lf_axis(u, g.na, r.a0, r.a1, r.fu);
+    lf_axis(v, g.nb, r.b0, r.b1, r.fv);
+    lf_axis(s, g.w, r.x0, r.x1, r.fs);
+    lf_axis(t, g.h, r.y0, r.y1, r.ft);
+    return r;
+}
+
+// record index of predictive node (B, A) of level l, channel c, block blk
+__device__ __forceinline__ int64_t ad_record(const LfGeom& g, int c, int l, int B, int A, int blk)
+{
+    return g.rec_base[c][l] + (int64_t)pred_ordinal(g.na_l[l], B, A) * g.nblk + blk;
+}
+
+__device__ __forceinline__ int ad_phase(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, int blk)
+{
+    int mx, my, sg;
+    lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
+    return sg;
+}
+
+// ---------------------------------------------------------------------------
+// parameter export: dequantised residuals and vector / 4
+// ---------------------------------------------------------------------------
+
+__global__ void k_export_residual(LfGeom g, LfPtrs p, float* __restrict__ res)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int64_t total = 3 * (int64_t)g.n_nodes * plane;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t px = t % plane;
+        const int node = (int)((t / plane) % g.n_nodes);
+        const int c = (int)(t / (plane * g.n_nodes));
+        int l = 0;
+        while (node < g.node_base[l]) l++;
+        const int y = (int)(px / g.w), x = (int)(px % g.w);
+        const int blk = (y / g.bs) * g.nbx + x / g.bs, i = (y % g.bs) * g.bs + x % g.bs;
+        res[t] = (float)lf_residual(g, p, c, l, node, blk, i);
+    }
+}
+
+__global__ void k_export_shift(LfGeom g, LfPtrs p, int64_t n_rec, float2* __restrict__ shift)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rec) return;
+    int c = 0, l = g.H - 1;
+    while (c < 2 && r >= g.rec_base[c + 1][g.H - 1]) c++;
+    while (l > 0 && r >= g.rec_base[c][l - 1]) l--;
+    const uint32_t j = (uint32_t)(r - g.rec_base[c][l]);
+    int mx, my, sg;
+    lf_motion(g, p, c, l, j, mx, my, sg);
+    shift[r] = make_float2((float)mx * 0.25f, (float)my * 0.25f);
+}
+
+extern "C" lf_status lf_export_params(const lf_handle* h, float* d_residual, float* d_shift, void* stream)
+{
+    if (!h || !d_residual || !d_shift) return lf_fail(LF_EINVAL, "null argument");
+    const LfGeom& g = h->L.g;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_export_residual, dim3(65536), dim3(256), 0, s, g, h->p, d_residual);
+    if (h->L.n_rec > 0)
+        hipLaunchKernelGGL(k_export_shift, dim3((unsigned)((h->L.n_rec + 255) / 256)), dim3(256), 0, s, g, h->p,
+                           h->L.n_rec, (float2*)d_shift);
+    return lf_check_launch("export_params");
+}
+
+// ---------------------------------------------------------------------------
+// relaxed forward
+// ---------------------------------------------------------------------------
+
+// bilinear sample of a real plane at (y + dy, x + dx), taps clamped
+__device__ __forceinline__ float ad_bilerp(const float* __restrict__ R, int w, int h, int y, int x, float2 d)
+{
+    const float fdx = floorf(d.x), fdy = floorf(d.y);
+    const float fx = d.x - fdx, fy = d.y - fdy;
+    const int x0 = x + (int)fdx, y0 = y + (int)fdy;
+    const int xa = lf_clampi(x0, 0, w - 1), xb = lf_clampi(x0 + 1, 0, w - 1);
+    const int ya = lf_clampi(y0, 0, h - 1), yb = lf_clampi(y0 + 1, 0, h - 1);
+    return ad_lerp(ad_lerp(R[ya * w + xa], R[ya * w + xb], fx), ad_lerp(R[yb * w + xa], R[yb * w + xb], fx), fy);
+}
+
+__device__ inline float ad_channel(const LfGeom& g, const LfPtrs& p, const float* __restrict__ res,
+                                   const float2* __restrict__ shift, int c, int b, int a, int y, int x)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    float v = (float)p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * plane + y * g.w + x];
+    const int blk = (y / g.bs) * g.nbx + x / g.bs;
+    for (int l = 0; l < g.H; l++) {
+        const int B = b >> l, A = a >> l;
+        const int node = g.node_base[l] + B * g.na_l[l] + A;
+        float s = res[((int64_t)c * g.n_nodes + node) * plane + y * g.w + x];
+        if ((A | B) & 1) {
+            const int sg = ad_phase(g, p, c, l, B, A, blk);
+            if (sg) {
+                const int rnode = g.node_base[l] + (B & ~1) * g.na_l[l] + (A & ~1);
+                const float q = ad_bilerp(res + ((int64_t)c * g.n_nodes + rnode) * plane, g.w, g.h, y, x,
+                                          shift[ad_record(g, c, l, B, A, blk)]);
+                s += sg > 0 ? q : -q;
+            }
+        }
+        v += s;
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_render_relaxed(LfGeom g, LfPtrs p, const float* __restrict__ res,
+                                                        const float2* __restrict__ shift,
+                                                        const float* __restrict__ cams, int nv, int wo, int ho,
+                                                        float* __restrict__ out)
+{
+    const int64_t npix = (int64_t)wo * ho;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= npix * nv) return;
+    const int v = (int)(r / npix);
+    const int64_t px = r - (int64_t)v * npix;
+    const int j = (int)(px / wo), i = (int)(px % wo);
+    const AdRay ry = ad_ray(g, cams + 18 * v, i, j);
+    float sm[16][3];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int b = (k & 8) ? ry.b1 : ry.b0, a = (k & 4) ? ry.a1 : ry.a0;
+        const int y = (k & 2) ? ry.y1 : ry.y0, x = (k & 1) ? ry.x1 : ry.x0;
+        const float Y = ad_channel(g, p, res, shift, 0, b, a, y, x);
+        const float Co = ad_channel(g, p, res, shift, 1, b, a, y, x);
+        const float Cg = ad_channel(g, p, res, shift, 2, b, a, y, x);
+        sm[k][0] = Y + 0.5f * Co - 0.5f * Cg;
+        sm[k][1] = Y + 0.5f * Cg;
+        sm[k][2] = Y - 0.5f * Co - 0.5f * Cg;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float vw[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            vw[q] = ad_lerp(ad_lerp(sm[4 * q][c], sm[4 * q + 1][c], ry.fs), ad_lerp(sm[4 * q + 2][c], sm[4 * q + 3][c], ry.fs),
+                            ry.ft);
+        out[((int64_t)v * 3 + c) * npix + px] =
+            ad_lerp(ad_lerp(vw[0], vw[1], ry.fu), ad_lerp(vw[2], vw[3], ry.fu), ry.fv) * (1.0f / 255.0f);
+    }
+}
+
+extern "C" lf_status lf_render_relaxed(const lf_handle* h, const float* d_residual, const float* d_shift,
+                                       const float* d_cams, int32_t n_views, int32_t width, int32_t height, float* d_out,
+                                       void* stream)
+{
+    if (!h || !d_residual || !d_shift || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (n_views == 0) return LF_OK;
+    if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
+    const int64_t total = (int64_t)n_views * width * height;
+    if ((total + 255) / 256 > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many rays");
+    hipLaunchKernelGGL(k_render_relaxed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       h->L.g, h->p, d_residual, (const float2*)d_shift, d_cams, n_views, width, height, d_out);
+    return lf_check_launch("render_relaxed");
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+
+struct BwdLayout {
+    int64_t n_pairs, n_samples;
+    int end_bit;
+    size_t sort_bytes;
+    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_gs, o_max, total;
+};
+
+static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
+
+static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayout* B)
+{
+    const LfGeom& g = h->L.g;
+    B->n_pairs = (int64_t)nv * wo * ho * 16;
+    B->n_samples = (int64_t)g.na * g.nb * g.w * g.h;
+    if (B->n_pairs > 0xFFFFFFFFll || B->n_samples > 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many rays or samples");
+    int eb = 1;
+    while (eb < 32 && ((int64_t)1 << eb) < B->n_samples) eb++;
+    B->end_bit = eb;
+    size_t sb = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, sb, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (uint32_t*)nullptr, (int)B->n_pairs, 0, eb) != hipSuccess)
+        return lf_fail(LF_EDEVICE, "sort workspace query failed");
+    B->sort_bytes = sb;
+    const int64_t pb = al256(B->n_pairs * 4);
+    B->o_kin = 0;
+    B->o_kout = B->o_kin + pb;
+    B->o_vin = B->o_kout + pb;
+    B->o_vout = B->o_vin + pb;
+    B->o_sort = B->o_vout + pb;
+    B->o_gs = B->o_sort + al256((int64_t)sb);
+    B->o_max = B->o_gs + al256(3 * B->n_samples * 4);
+    B->total = B->o_max + 256;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, int32_t width, int32_t height,
+                                           int64_t* bytes)
+{
+    if (!h || !bytes || n_views < 1 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    BwdLayout B;
+    lf_status st = bwd_layout(h, n_views, width, height, &B);
+    if (st != LF_OK) return st;
+    *bytes = B.total;
+    return LF_OK;
+}
+
+__global__ void k_ad_pairs(LfGeom g, const float* __restrict__ cams, int nv, int wo, int ho, uint32_t* __restrict__ keys,
+                           uint32_t* __restrict__ vals)
+{
+    const int64_t npix = (int64_t)wo * ho;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= npix * nv) return;
+    const int v = (int)(r / npix);
+    const int64_t px = r - (int64_t)v * npix;
+    const AdRay ry = ad_ray(g, cams + 18 * v, (int)(px % wo), (int)(px / wo));
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int b = (k & 8) ? ry.b1 : ry.b0, a = (k & 4) ? ry.a1 : ry.a0;
+        const int y = (k & 2) ? ry.y1 : ry.y0, x = (k & 1) ? ry.x1 : ry.x0;
+        keys[r * 16 + k] = (uint32_t)((((int64_t)b * g.na + a) * g.h + y) * g.w + x);
+        vals[r * 16 + k] = (uint32_t)(r * 16 + k);
+    }
+}
+
+__global__ void k_ad_fill(float* __restrict__ p, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0.0f;
+}
+
+// one thread per run of equal keys: sum the run in ray order
+__global__ void k_ad_segments(LfGeom g, const float* __restrict__ cams, int wo, int ho,
+                              const float* __restrict__ grad_out, const uint32_t* __restrict__ keys,
+                              const uint32_t* __restrict__ vals, int64_t n_pairs, int64_t n_samples,
+                              float* __restrict__ gs /* [3][n_samples] YCoCg */)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    const uint32_t key = keys[i];
+    if (i > 0 && keys[i - 1] == key) return;
+    const int64_t npix = (int64_t)wo * ho;
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int64_t jx = i; jx < n_pairs && keys[jx] == key; jx++) {
+        const uint32_t val = vals[jx];
+        const int64_t ray = val >> 4;
+        const int k = (int)(val & 15u);
+        const int v = (int)(ray / npix);
+        const int64_t px = ray - (int64_t)v * npix;
+        const AdRay ry = ad_ray(g, cams + 18 * v, (int)(px % wo), (int)(px / wo));
+        const float w = ((k & 8) ? ry.fv : 1.0f - ry.fv) * ((k & 4) ? ry.fu : 1.0f - ry.fu) *
+                        ((k & 2) ? ry.ft : 1.0f - ry.ft) * ((k & 1) ? ry.fs : 1.0f - ry.fs) * (1.0f / 255.0f);
+#pragma unroll
+        for (int c = 0; c < 3; c++) acc[c] = fmaf(w, grad_out[((int64_t)v * 3 + c) * npix + px], acc[c]);
+    }
+    // colour transpose of R = Y + Co/2 - Cg/2, G = Y + Cg/2, B = Y - Co/2 - Cg/2
+    gs[key] = acc[0] + acc[1] + acc[2];
+    gs[n_samples + key] = 0.5f * (acc[0] - acc[2]);
+    gs[2 * n_samples + key] = 0.5f * (acc[1] - acc[0] - acc[2]);
+}
+
+// node gradients: level 0 copies the sample gradient, level l sums its children
+__global__ void k_ad_tree(LfGeom g, int l, const float* __restrict__ gs, int64_t n_samples, float* __restrict__ gres)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int64_t nodes_l = (int64_t)g.na_l[l] * g.nb_l[l];
+    const int64_t total = 3 * nodes_l * plane;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t px = t % plane;
+        const int64_t loc = (t / plane) % nodes_l;
+        const int c = (int)(t / (plane * nodes_l));
+        const int B = (int)(loc / g.na_l[l]), A = (int)(loc % g.na_l[l]);
+        float v;
+        if (l == 0) {
+            v = gs[c * n_samples + ((int64_t)B * g.na + A) * plane + px];
+        } else {
+            v = 0.0f;
+            for (int jj = 0; jj < 2; jj++)
+                for (int ii = 0; ii < 2; ii++) {
+                    const int Bc = 2 * B + jj, Ac = 2 * A + ii;
+                    if (Bc >= g.nb_l[l - 1] || Ac >= g.na_l[l - 1]) continue;
+                    v += gres[((int64_t)c * g.n_nodes + g.node_base[l - 1] + Bc * g.na_l[l - 1] + Ac) * plane + px];
+                }
+        }
+        gres[((int64_t)c * g.n_nodes + g.node_base[l] + loc) * plane + px] = v;
+    }
+}
+
+__global__ void k_ad_maxshift(const float2* __restrict__ shift, int64_t n, float* __restrict__ out)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) m = fmaxf(m, fmaxf(fabsf(shift[t].x), fabsf(shift[t].y)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// pixel range [lo, hi] of [k0, k1] whose tap (x + fd + o), clamped to [0, n-1], equals X
+__device__ __forceinline__ void ad_tap_range(int X, int n, int fd, int o, int k0, int k1, int& lo, int& hi)
+{
+    if (n == 1) {
+        lo = k0;
+        hi = k1;
+    } else if (X == 0) {
+        lo = k0;
+        hi = min(k1, -fd - o);
+    } else if (X == n - 1) {
+        lo = max(k0, n - 1 - fd - o);
+        hi = k1;
+    } else {
+        lo = max(k0, X - fd - o);
+        hi = min(k1, X - fd - o);
+    }
+}
+
+// reference residual gradient: own node gradient plus the phase-signed
+// bilinear transpose of every predictive sibling's gradient (pull form)
+__global__ void k_ad_reference(LfGeom g, LfPtrs p, const float2* __restrict__ shift, const float* __restrict__ maxshift,
+                               float* __restrict__ gres)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int64_t total = 3 * (int64_t)g.n_refs * plane;
+    const int reach = (int)ceilf(fminf(maxshift[0], (float)(g.w + g.h))) + 2;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t px = t % plane;
+        const int r = (int)((t / plane) % g.n_refs);
+        const int c = (int)(t / (plane * g.n_refs));
+        int l = 0;
+        while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
+        const int loc = r - g.ref_base[l];
+        const int Br = 2 * (loc / g.na_l[l + 1]), Ar = 2 * (loc % g.na_l[l + 1]);
+        const int Y = (int)(px / g.w), X = (int)(px % g.w);
+        const int64_t rnode = g.node_base[l] + Br * g.na_l[l] + Ar;
+        float acc = gres[((int64_t)c * g.n_nodes + rnode) * plane + px];
+        const int kx0 = max(0, (X - reach) / g.bs), kx1 = min(g.nbx - 1, (X + reach) / g.bs);
+        const int nby = g.h / g.bs;
+        const int ky0 = max(0, (Y - reach) / g.bs), ky1 = min(nby - 1, (Y + reach) / g.bs);
+        for (int sib = 1; sib < 4; sib++) {
+            const int B = Br + (sib >> 1), A = Ar + (sib & 1);
+            if (B >= g.nb_l[l] || A >= g.na_l[l]) continue;
+            const float* gp = gres + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
+            for (int ky = ky0; ky <= ky1; ky++)
+                for (int kx = kx0; kx <= kx1; kx++) {
+                    const int blk = ky * g.nbx + kx;
+                    const int sg = ad_phase(g, p, c, l, B, A, blk);
+                    if (!sg) continue;
+                    const float2 d = shift[ad_record(g, c, l, B, A, blk)];
+                    const float fdx = floorf(d.x), fdy = floorf(d.y);
+                    const float fx = d.x - fdx, fy = d.y - fdy;
+                    const int ix = (int)fdx, iy = (int)fdy;
+                    float blk_acc = 0.0f;
+                    for (int oy = 0; oy < 2; oy++) {
+                        int ylo, yhi;
+                        ad_tap_range(Y, g.h, iy, oy, ky * g.bs, ky * g.bs + g.bs - 1, ylo, yhi);
+                        if (ylo > yhi) continue;
+                        const float wy = oy ? fy : 1.0f - fy;
+                        for (int ox = 0; ox < 2; ox++) {
+                            int xlo, xhi;
+                            ad_tap_range(X, g.w, ix, ox, kx * g.bs, kx * g.bs + g.bs - 1, xlo, xhi);
+                            if (xlo > xhi) continue;
+                            const float wxy = wy * (ox ? fx : 1.0f - fx);
+                            float sum = 0.0f;
+                            for (int y = ylo; y <= yhi; y++)
+                                for (int x = xlo; x <= xhi; x++) sum += gp[y * g.w + x];
+                            blk_acc = fmaf(wxy, sum, blk_acc);
+                        }
+                    }
+                    acc += sg > 0 ? blk_acc : -blk_acc;
+                }
+        }
+        gres[((int64_t)c * g.n_nodes + rnode) * plane + px] = acc;
+    }
+}
+
+// shift gradients: one workgroup per motion record, fixed-order reduction
+__global__ void __launch_bounds__(256) k_ad_shift(LfGeom g, LfPtrs p, const float* __restrict__ res,
+                                                  const float2* __restrict__ shift, const float* __restrict__ gres_pred,
+                                                  float2* __restrict__ gshift)
+{
+    __shared__ float rx[256], ryy[256];
+    const int64_t rec = blockIdx.x;
+    int c = 0, l = g.H - 1;
+    while (c < 2 && rec >= g.rec_base[c + 1][g.H - 1]) c++;
+    while (l > 0 && rec >= g.rec_base[c][l - 1]) l--;
+    const int64_t j = rec - g.rec_base[c][l];
+    const int pord = (int)(j / g.nblk), blk = (int)(j % g.nblk);
+    // invert the predictive ordinal: rows with odd B hold na_l nodes, even rows na_l / 2
+    const int na = g.na_l[l], pair = na + na / 2;
+    int B = 2 * (pord / pair), rem = pord % pair, A;
+    if (rem < na / 2) {
+        A = 2 * rem + 1;
+    } else {
+        B += 1;
+        A = rem - na / 2;
+    }
+    const int64_t plane = (int64_t)g.w * g.h;
+    int mx, my, sg;
+    lf_motion(g, p, c, l, (uint32_t)j, mx, my, sg);
+    float sx = 0.0f, sy = 0.0f;
+    if (sg) {
+        const float2 d = shift[rec];
+        const float fdx = floorf(d.x), fdy = floorf(d.y);
+        const float fx = d.x - fdx, fy = d.y - fdy;
+        const float* R = res + ((int64_t)c * g.n_nodes + g.node_base[l] + (B & ~1) * na + (A & ~1)) * plane;
+        const float* gp = gres_pred + ((int64_t)c * g.n_nodes + g.node_base[l] + B * na + A) * plane;
+        const int by0 = (blk / g.nbx) * g.bs, bx0 = (blk % g.nbx) * g.bs;
+        for (int q = threadIdx.x; q < g.bs * g.bs; q += blockDim.x) {
+            const int y = by0 + q / g.bs, x = bx0 + q % g.bs;
+            const int x0 = x + (int)fdx, y0 = y + (int)fdy;
+            const int xa = lf_clampi(x0, 0, g.w - 1), xb = lf_clampi(x0 + 1, 0, g.w - 1);
+            const int ya = lf_clampi(y0, 0, g.h - 1), yb = lf_clampi(y0 + 1, 0, g.h - 1);
+            const float t00 = R[ya * g.w + xa], t01 = R[ya * g.w + xb], t10 = R[yb * g.w + xa], t11 = R[yb * g.w + xb];
+            const float gv = (float)sg * gp[y * g.w + x];
+            sx = fmaf(gv, (1.0f - fy) * (t01 - t00) + fy * (t11 - t10), sx);
+            sy = fmaf(gv, (1.0f - fx) * (t10 - t00) + fx * (t11 - t01), sy);
+        }
+    }
+    rx[threadIdx.x] = sx;
+    ryy[threadIdx.x] = sy;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            rx[threadIdx.x] += rx[threadIdx.x + s];
+            ryy[threadIdx.x] += ryy[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gshift[rec] = make_float2(rx[0], ryy[0]);
+}
+
+extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_residual, const float* d_shift,
+                                        const float* d_cams, int32_t n_views, int32_t width, int32_t height,
+                                        const float* d_grad_out, float* d_grad_residual, float* d_grad_shift,
+                                        void* d_workspace, int64_t workspace_bytes, void* stream)
+{
+    if (!h || !d_residual || !d_shift || !d_cams || !d_grad_out || !d_grad_residual || !d_grad_shift || !d_workspace ||
+        n_views < 1 || width < 1 || height < 1)
+        return lf_fail(LF_EINVAL, "bad argument");
+    const LfGeom& g = h->L.g;
+    BwdLayout Bl;
+    lf_status st = bwd_layout(h, n_views, width, height, &Bl);
+    if (st != LF_OK) return st;
+    if (workspace_bytes < Bl.total)
+        return lf_fail(LF_ENOMEM, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes, (long long)Bl.total);
+    if (((uintptr_t)d_workspace) & 255) return lf_fail(LF_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* W = (uint8_t*)d_workspace;
+    uint32_t *kin = (uint32_t*)(W + Bl.o_kin), *kout = (uint32_t*)(W + Bl.o_kout);
+    uint32_t *vin = (uint32_t*)(W + Bl.o_vin), *vout = (uint32_t*)(W + Bl.o_vout);
+    float* gs = (float*)(W + Bl.o_gs);
+    float* mxs = (float*)(W + Bl.o_max);
+    const int64_t rays = (int64_t)n_views * width * height;
+    hipLaunchKernelGGL(k_ad_pairs, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, d_cams, n_views, width,
+                       height, kin, vin);
+    size_t sb = Bl.sort_bytes;
+    if (hipcub::DeviceRadixSort::SortPairs(W + Bl.o_sort, sb, kin, kout, vin, vout, (int)Bl.n_pairs, 0, Bl.end_bit, s) !=
+        hipSuccess)
+        return lf_fail(LF_EDEVICE, "radix sort failed");
+    hipLaunchKernelGGL(k_ad_fill, dim3(4096), dim3(256), 0, s, gs, 3 * Bl.n_samples);
+    hipLaunchKernelGGL(k_ad_segments, dim3((unsigned)((Bl.n_pairs + 255) / 256)), dim3(256), 0, s, g, d_cams, width,
+                       height, d_grad_out, kout, vout, Bl.n_pairs, Bl.n_samples, gs);
+    for (int l = 0; l < g.H; l++)
+        hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, gs, Bl.n_samples, d_grad_residual);
+    hipLaunchKernelGGL(k_ad_maxshift, dim3(1), dim3(256), 0, s, (const float2*)d_shift, h->L.n_rec, mxs);
+    // shift gradients read the predictive nodes' gradients, which the
+    // reference pass leaves untouched; run them first to keep the order plain
+    if (h->L.n_rec > 0)
+        hipLaunchKernelGGL(k_ad_shift, dim3((unsigned)h->L.n_rec), dim3(256), 0, s, g, h->p, d_residual,
+                           (const float2*)d_shift, d_grad_residual, (float2*)d_grad_shift);
+    hipLaunchKernelGGL(k_ad_reference, dim3(16384), dim3(256), 0, s, g, h->p, (const float2*)d_shift, mxs,
+                       d_grad_residual);
+    return lf_check_launch("render_backward");
+}

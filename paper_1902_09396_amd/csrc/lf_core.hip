@@ -94,11 +94,13 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     }
     g.n_nodes = (int)nodes;
     g.n_refs = (int)refs;
+    // device code addresses reference planes with 32-bit element offsets
+    if (3 * refs * (int64_t)g.w * g.h >= ((int64_t)1 << 32)) return lf_fail(LF_EFORMAT, "light field too large");
     for (int l = 0; l < g.H; l++) {
         int32_t st, wn;
         memcpy(&st, s + 48 + 4 * l, 4);
         memcpy(&wn, s + 80 + 4 * l, 4);
-        if (st < 1 || st > 4096 || wn < 0 || wn > 1024) return lf_fail(LF_EFORMAT, "bad step/window at level %d", l);
+        if (st < 1 || st > 4096 || wn < 0 || wn > 255) return lf_fail(LF_EFORMAT, "bad step/window at level %d", l);
         g.step[l] = st;
         g.bias[l] = 4 * wn;
     }

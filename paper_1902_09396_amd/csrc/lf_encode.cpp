@@ -235,7 +235,7 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
     if (H < 1 || H > LF_MAX_LEVELS || bs < 1 || bs > 64 || w < 1 || h < 1 || w % bs || h % bs || na < 1 || nb < 1)
         return lf_fail(LF_EINVAL, "bad geometry");
     for (int l = 0; l < H; l++)
-        if (prm->step[l] < 1 || prm->step[l] > 4096 || prm->win[l] < 0 || prm->win[l] > 1024)
+        if (prm->step[l] < 1 || prm->step[l] > 4096 || prm->win[l] < 0 || prm->win[l] > 255)
             return lf_fail(LF_EINVAL, "bad step/window");
     if (threads > 0) omp_set_num_threads(threads);
     int na_l[LF_MAX_LEVELS + 1], nb_l[LF_MAX_LEVELS + 1];

@@ -47,6 +47,10 @@ SIGNATURES = {
     "lf_render_views_per_ray": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_export_params": (C.c_int, [_P, _P, _P, _P]),
+    "lf_render_relaxed": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_backward_workspace": (C.c_int, [_P, _I32, _I32, _I32, _P]),
+    "lf_render_backward": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _P, _I64, _P]),
     "lf_encode": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "lf_encode_free": (None, [_P]),
     "lf_last_error": (C.c_char_p, []),
@@ -155,6 +159,48 @@ class LightField:
         fn = lib().lf_render_views_per_ray if per_ray else lib().lf_render_views
         check(fn(self._h, _ptr(cams), cams.shape[0], width, height, _ptr(out), _stream()))
         return out
+
+    # ---- relaxed model (encoder-side refinement) ----
+    def export_params(self):
+        """(residual float32 [3, n_nodes, h, w], shift float32 [n_records, 2]) on the device."""
+        res = torch.empty((3, self.info["n_nodes"], self.height, self.width), dtype=torch.float32, device=self.device)
+        sh = torch.empty((max(self.info["n_pred_records"], 0), 2), dtype=torch.float32, device=self.device)
+        check(lib().lf_export_params(self._h, _ptr(res), _ptr(sh), _stream()))
+        return res, sh
+
+    def render_relaxed(self, residual: torch.Tensor, shift: torch.Tensor, cams: torch.Tensor, width: int,
+                       height: int) -> torch.Tensor:
+        residual = _dev(residual, torch.float32, "residual")
+        shift = _dev(shift, torch.float32, "shift")
+        self._check_params(residual, shift)
+        cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+        out = torch.empty((cams.shape[0], 3, height, width), dtype=torch.float32, device=cams.device)
+        check(lib().lf_render_relaxed(self._h, _ptr(residual), _ptr(shift), _ptr(cams), cams.shape[0], width, height,
+                                      _ptr(out), _stream()))
+        return out
+
+    def render_backward(self, residual, shift, cams, width, height, grad_out):
+        residual = _dev(residual, torch.float32, "residual")
+        shift = _dev(shift, torch.float32, "shift")
+        self._check_params(residual, shift)
+        cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+        grad_out = _dev(grad_out, torch.float32, "grad_out")
+        if tuple(grad_out.shape) != (cams.shape[0], 3, height, width):
+            raise ValueError("grad_out must be [V, 3, H, W]")
+        need = C.c_int64()
+        check(lib().lf_backward_workspace(self._h, cams.shape[0], width, height, C.byref(need)))
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=cams.device)
+        g_res = torch.empty_like(residual)
+        g_sh = torch.empty_like(shift)
+        check(lib().lf_render_backward(self._h, _ptr(residual), _ptr(shift), _ptr(cams), cams.shape[0], width, height,
+                                       _ptr(grad_out), _ptr(g_res), _ptr(g_sh), _ptr(ws), int(need.value), _stream()))
+        return g_res, g_sh
+
+    def _check_params(self, residual, shift):
+        if tuple(residual.shape) != (3, self.info["n_nodes"], self.height, self.width):
+            raise ValueError("residual must be [3, n_nodes, h, w]")
+        if tuple(shift.shape) != (self.info["n_pred_records"], 2):
+            raise ValueError("shift must be [n_records, 2]")
 
     def footprint_bytes(self, cams: torch.Tensor, width: int, height: int) -> np.ndarray:
         cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
