@@ -109,7 +109,7 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
 #define TW 32
 #define TH 8
 #define NT (TW * TH)
-#define FMAX 8           // views per workgroup (upper bound of the group size)
+#define FMAX 16          // views per workgroup (upper bound of the group size)
 #define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
 
 // Staging budgets (entries) for a group of `fpg` views of one 32x8 tile; the
@@ -123,7 +123,8 @@ __host__ __device__ inline Budget lf_budget(int fpg)
     if (fpg <= 1) return Budget{2048, 4096, 192};
     if (fpg == 2) return Budget{2560, 6144, 256};
     if (fpg <= 4) return Budget{3584, 10240, 352};
-    return Budget{5120, 16384, 512};
+    if (fpg <= 8) return Budget{5120, 16384, 512};
+    return Budget{8192, 28672, 768};
 }
 
 __host__ __device__ inline size_t lf_lds_bytes(Budget b)
@@ -212,13 +213,15 @@ __device__ __forceinline__ Plan lf_plan(const LfGeom& g, const Box& b, const Bud
     P.bky0 = b.ymin / g.bs;
     P.nbkx = b.xmax / g.bs - P.bkx0 + 1;
     P.nbk = P.nbkx * (b.ymax / g.bs - P.bky0 + 1);
+    // staged values: nodes of levels 1..H-1 and the root views (level H), per
+    // channel and footprint pixel; descriptors: levels 0..H-1, per block
     int ns = 0, nd = 0;
-    for (int l = 0; l < g.H; l++) {
+    for (int l = 0; l <= g.H; l++) {
         const int B0 = b.bmin >> l, A0 = b.amin >> l;
         const int nB = (b.bmax >> l) - B0 + 1, nA = (b.amax >> l) - A0 + 1;
         if (lv) lv[l] = LevelInfo{B0, nB, A0, nA, ns, nd};
         if (l >= 1) ns += 3 * nB * nA;
-        nd += 3 * nB * nA * P.nbk;
+        if (l < g.H) nd += 3 * nB * nA * P.nbk;
     }
     P.nslots = ns;
     P.ndesc = nd;
@@ -237,7 +240,7 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
     int16_t* sval = reinterpret_cast<int16_t*>(rgba + bud.rgba);    // [bud.sval]
     __shared__ int fbox[FMAX][8];
     __shared__ int red[FMAX][8][NT / 64];
-    __shared__ LevelInfo lvl[LF_MAX_LEVELS];
+    __shared__ LevelInfo lvl[LF_MAX_LEVELS + 1];
 
     // XCD-aware order: workgroup ids go round-robin over the 8 XCDs, so give
     // each XCD a contiguous range of (view group, tile) work: consecutive
@@ -318,40 +321,66 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
             desc[d] = lf_make_desc(g, p, c, l, L.B0 + bi, L.A0 + ai, blk);
         }
         __syncthreads();
-        // phase 1b: SRV values of the shared ancestors (levels >= 1), once per node and pixel
-        for (int it = threadIdx.x; it < P.nslots * P.npix; it += NT) {
-            const int slot = it / P.npix, px = it - slot * P.npix;
-            int l = 1;
-            while (l + 1 < g.H && slot >= lvl[l + 1].sbase) l++;
-            const LevelInfo L = lvl[l];
-            const int node_c = slot - L.sbase;  // (c * nB + bi) * nA + ai
-            const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
-            const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
-            sval[it] = (int16_t)lf_srv_from_desc(g, p, desc[L.dbase + node_c * P.nbk + kb], y, x);
+        // phase 1b: values shared by several views, once per node and pixel:
+        // SRVs of levels 1..H-1 and the root RKV (level H)
+        {
+            const int total = P.nslots * P.npix;
+            auto stage = [&](int it) -> int {
+                const int slot = it / P.npix, px = it - slot * P.npix;
+                int l = 1;
+                while (l < g.H && slot >= lvl[l + 1].sbase) l++;
+                const LevelInfo L = lvl[l];
+                const int node_c = slot - L.sbase;  // (c * nB + bi) * nA + ai
+                const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
+                if (l == g.H) {
+                    const int ai = node_c % L.nA, rest = node_c / L.nA;
+                    const int bi = rest % L.nB, c = rest / L.nB;
+                    return p.root[((size_t)(c * g.root_nb + L.B0 + bi) * g.root_na + L.A0 + ai) * (size_t)(g.w * g.h) +
+                                  y * g.w + x];
+                }
+                const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
+                return lf_srv_from_desc(g, p, desc[L.dbase + node_c * P.nbk + kb], y, x);
+            };
+            // two independent items per trip keep more loads in flight
+            for (int it = threadIdx.x; it < total; it += 2 * NT) {
+                const int it2 = it + NT;
+                const int v1 = stage(it);
+                const int v2 = it2 < total ? stage(it2) : 0;
+                sval[it] = (int16_t)v1;
+                if (it2 < total) sval[it2] = (int16_t)v2;
+            }
         }
         __syncthreads();
-        // phase 2: every (view, pixel) sample: root + level-0 SRV + staged ancestors
-        for (int it = threadIdx.x; it < P.nviews * P.npix; it += NT) {
-            const int vi = it / P.npix, px = it - vi * P.npix;
-            const int b = bx.bmin + vi / P.nva, a = bx.amin + vi % P.nva;
-            const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
-            const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
-            int ch[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                int v = p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * (size_t)(g.w * g.h) +
-                               y * g.w + x];
+        // phase 2: every (view, pixel) sample: level-0 SRV + staged ancestors and root
+        {
+            const int total = P.nviews * P.npix;
+            auto assemble = [&](int it) -> uint32_t {
+                const int vi = it / P.npix, px = it - vi * P.npix;
+                const int b = bx.bmin + vi / P.nva, a = bx.amin + vi % P.nva;
+                const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
+                const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
                 const LevelInfo L0 = lvl[0];
-                v += lf_srv_from_desc(g, p, desc[((c * L0.nB + (b - L0.B0)) * L0.nA + (a - L0.A0)) * P.nbk + kb], y, x);
-                for (int l = 1; l < g.H; l++) {
-                    const LevelInfo L = lvl[l];
-                    v += sval[(L.sbase + (c * L.nB + ((b >> l) - L.B0)) * L.nA + ((a >> l) - L.A0)) * P.npix + px];
+                int ch[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    int v = lf_srv_from_desc(g, p, desc[((c * L0.nB + (b - L0.B0)) * L0.nA + (a - L0.A0)) * P.nbk + kb], y, x);
+                    for (int l = 1; l <= g.H; l++) {
+                        const LevelInfo L = lvl[l];
+                        v += sval[(L.sbase + (c * L.nB + ((b >> l) - L.B0)) * L.nA + ((a >> l) - L.A0)) * P.npix + px];
+                    }
+                    ch[c] = v;
                 }
-                ch[c] = v;
+                int R, G, B;
+                lf_ycocg_to_rgb(ch[0], ch[1], ch[2], R, G, B);
+                return (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+            };
+            for (int it = threadIdx.x; it < total; it += 2 * NT) {
+                const int it2 = it + NT;
+                const uint32_t v1 = assemble(it);
+                const uint32_t v2 = it2 < total ? assemble(it2) : 0u;
+                rgba[it] = v1;
+                if (it2 < total) rgba[it2] = v2;
             }
-            int R, G, B;
-            lf_ycocg_to_rgb(ch[0], ch[1], ch[2], R, G, B);
-            rgba[it] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
         }
         __syncthreads();
         // phase 3: blend every ray of the group's views
@@ -397,6 +426,14 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int64_t n_work = (int64_t)tx * ty * ((nv + fpg - 1) / fpg);
     const int64_t grid = ((n_work + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
+    const size_t lds = lf_lds_bytes(lf_budget(fpg));
+    static bool attr_set = false;
+    if (lds > 65536 && !attr_set) {
+        if (hipFuncSetAttribute((const void*)k_render_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess)
+            return lf_fail(LF_EDEVICE, "cannot reserve %zu bytes of LDS", lds);
+        attr_set = true;
+    }
     hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), lf_lds_bytes(lf_budget(fpg)), s, h->L.g, h->p,
                        d_cams, nv, wo, ho, tx, ty, fpg, d_out);
     return lf_check_launch("render_batch");
