@@ -73,6 +73,9 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
         g.w % g.bs || g.h % g.bs || d[6] != 3 || d[7] != 4 || g.na > 4096 || g.nb > 4096 || g.w > 16384 ||
         g.h > 16384)
         return lf_fail(LF_EFORMAT, "bad geometry");
+    if (g.bs & (g.bs - 1)) return lf_fail(LF_EFORMAT, "block size %d is not a power of two", g.bs);
+    g.bsl = 0;
+    while ((1 << g.bsl) < g.bs) g.bsl++;
     g.nbx = g.w / g.bs;
     g.nblk = g.nbx * (g.h / g.bs);
     g.na_l[0] = g.na;

@@ -16,6 +16,7 @@
 
 struct LfGeom {
     int na, nb, w, h, H, bs, nbx, nblk;
+    int bsl;  // log2 of the block size (a power of two)
     int na_l[LF_MAX_LEVELS + 1], nb_l[LF_MAX_LEVELS + 1];
     int node_base[LF_MAX_LEVELS];  // first BFS node index of each level
     int ref_base[LF_MAX_LEVELS];   // first reference plane of each level
@@ -133,8 +134,8 @@ __device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c,
 {
     const int plane = g.w * g.h;
     int v = p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * plane + y * g.w + x];
-    const int blk = (y / g.bs) * g.nbx + x / g.bs;
-    const int i = (y % g.bs) * g.bs + x % g.bs;
+    const int blk = (y >> g.bsl) * g.nbx + (x >> g.bsl);
+    const int i = ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1));
     for (int l = 0; l < g.H; l++) {
         int B = b >> l, A = a >> l;
         const int16_t* ref = lf_ref_plane(g, p, c, l, B >> 1, A >> 1);

@@ -109,40 +109,45 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
 #define TW 32
 #define TH 8
 #define NT (TW * TH)
-#define FMAX 16          // views per workgroup (upper bound of the group size)
+#define FMAX 32          // views per workgroup (upper bound of the group size)
+#define LMAX 64          // nodes of one level inside a group's bounding rectangle
 #define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
+#define SLOT_MAX 160
 
-// Staging budgets (entries) for a group of `fpg` views of one 32x8 tile; the
-// footprint of one 512x512 orbit view is 33x9 pixels in about 2x2 views.
-struct Budget {
-    int rgba, sval, desc;
-};
+// LDS staging budgets (entries): descriptors (16 B), assembled samples (4 B),
+// staged ancestor/root values (2 B).  About 46 KiB plus 6 KiB of tables keeps
+// three 256-thread workgroups resident per CU.
+#define B_DESC 384
+#define B_RGBA 4096
+#define B_SVAL 12288
+#define LDS_DYN_BYTES (B_DESC * 16 + B_RGBA * 4 + B_SVAL * 2)
 
-__host__ __device__ inline Budget lf_budget(int fpg)
+// 16-bit packed min/max (both halves at once)
+typedef unsigned short lf_u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
 {
-    if (fpg <= 1) return Budget{2048, 4096, 192};
-    if (fpg == 2) return Budget{2560, 6144, 256};
-    if (fpg <= 4) return Budget{3584, 10240, 352};
-    if (fpg <= 8) return Budget{5120, 16384, 512};
-    return Budget{8192, 28672, 768};
+    lf_u16x2 x = __builtin_bit_cast(lf_u16x2, a), y = __builtin_bit_cast(lf_u16x2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
 }
 
-__host__ __device__ inline size_t lf_lds_bytes(Budget b)
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b)
 {
-    return (size_t)b.desc * 16 + (size_t)b.rgba * 4 + (size_t)b.sval * 2;
+    lf_u16x2 x = __builtin_bit_cast(lf_u16x2, a), y = __builtin_bit_cast(lf_u16x2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
 }
 
-__device__ __forceinline__ int wave_min(int v)
+__device__ __forceinline__ uint32_t wave_pk_min(uint32_t v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = pk_min(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
 
-__device__ __forceinline__ int wave_max(int v)
+__device__ __forceinline__ uint32_t wave_pk_max(uint32_t v)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    for (int o = 32; o > 0; o >>= 1) v = pk_max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
 }
 
@@ -164,83 +169,99 @@ __device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, 
                       ((uint32_t)mx & 0xFFFu) | (((uint32_t)my & 0xFFFu) << 12) | (mode << 24), ref);
 }
 
-// SRV value at (y, x) of the node a descriptor belongs to.
-__device__ __forceinline__ int lf_srv_from_desc(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x)
+// Bounded-integer value i of a block, one code path for the three families
+// (no divergence between neighbouring blocks of different families): a value
+// is (high digit << b) | b-bit low part, where the group of G values (G = 1,
+// 5 or 3) starts with an hb-bit header (hb = 0, 8 or 7) whose digit k is read
+// from a table: digits[t] packs the base-3 digits of t (2 bits each) and
+// digits[256 + q] the base-5 digits of q (3 bits each); digits[0] = 0.
+__device__ __forceinline__ uint32_t lf_bise_any(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i,
+                                                const uint16_t* __restrict__ digits)
 {
-    const int mode = (int)(d.z >> 24);
-    if (mode == MODE_PLANE) return p.refs[d.w + (uint32_t)(y * g.w + x)];
+    const uint32_t fam = mode >> 5, b = mode & 31u;
+    const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
+    const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
+    const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
+    const uint32_t grp = fam == 0u ? i : __umulhi(i, mg);
+    const uint32_t k = i - grp * gs;
+    const uint32_t base = __umul24(grp, hb + gs * b);
+    const uint32_t head = lf_field(w, base, (int)hb);
+    const uint32_t lo = lf_field(w, base + hb + __umul24(k, b), (int)b);
+    const uint32_t dig = digits[(fam == 2u ? 256u : 0u) + head];
+    const uint32_t hi = fam == 2u ? (dig >> (3u * k)) & 7u : (dig >> (2u * k)) & 3u;
+    return (hi << b) | lo;
+}
+
+// SRV value at (y, x) of the node a descriptor belongs to.
+__device__ __forceinline__ int lf_srv_from_desc(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x,
+                                                const uint16_t* __restrict__ digits)
+{
+    const uint32_t mode = d.z >> 24;
+    if (mode == MODE_PLANE) return p.refs[d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x];
     int r = 0;
     if (mode != LF_MODE_ZERO) {
-        const int i = (y % g.bs) * g.bs + (x % g.bs);
+        const uint32_t i = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x & (g.bs - 1));
         const int mn = (int)(int16_t)(d.y & 0xFFFFu);
         const int step = (int)((d.y >> 16) & 0x1FFFu);
-        r = (mn + (int)lf_bise_get(p.payload + d.x, mode, (uint32_t)i)) * step;
+        r = __mul24(mn + (int)lf_bise_any(p.payload + d.x, mode, i, digits), step);
     }
     const uint32_t code = d.y >> 29;
     if (code < 2u) {
         const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
-        const int q = lf_qpel(p.refs + d.w, g.w, g.h, y, x, mx, my);
+        const int16_t* R = p.refs + d.w;
+        const int X = 4 * x + mx, Y = 4 * y + my;
+        const int x0 = X >> 2, y0 = Y >> 2, fx = X & 3, fy = Y & 3;
+        const int xa = lf_clampi(x0, 0, g.w - 1), xb = lf_clampi(x0 + 1, 0, g.w - 1);
+        const int ra = __mul24(lf_clampi(y0, 0, g.h - 1), g.w), rb = __mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w);
+        const int top = (4 - fx) * R[ra + xa] + fx * R[ra + xb];
+        const int bot = (4 - fx) * R[rb + xa] + fx * R[rb + xb];
+        const int q = ((4 - fy) * top + fy * bot + 8) >> 4;
         r += code == 0u ? q : -q;
     }
     return r;
 }
 
-struct Box {
-    int amin, amax, bmin, bmax, xmin, xmax, ymin, ymax;
-};
-
-struct LevelInfo {
-    int B0, nB, A0, nA, sbase, dbase;
-};
-
-struct Plan {
-    int nva, nvb, sx, sy, npix, nviews;
-    int bkx0, bky0, nbkx, nbk;
-    int nslots, ndesc;
-    bool fits;
-};
-
-__device__ __forceinline__ Plan lf_plan(const LfGeom& g, const Box& b, const Budget& bud, LevelInfo* lv /* may be null */)
+// floor(n / d) for n, d < 2^16: m = ceil(2^32 / d) for d >= 2 (exact in that
+// range); d = 1 would need m = 2^32, so it is encoded as m = 0 (identity)
+__device__ __forceinline__ uint32_t lf_magic(uint32_t d)
 {
-    Plan P;
-    P.nva = b.amax - b.amin + 1;
-    P.nvb = b.bmax - b.bmin + 1;
-    P.sx = b.xmax - b.xmin + 1;
-    P.sy = b.ymax - b.ymin + 1;
-    P.npix = P.sx * P.sy;
-    P.nviews = P.nva * P.nvb;
-    P.bkx0 = b.xmin / g.bs;
-    P.bky0 = b.ymin / g.bs;
-    P.nbkx = b.xmax / g.bs - P.bkx0 + 1;
-    P.nbk = P.nbkx * (b.ymax / g.bs - P.bky0 + 1);
-    // staged values: nodes of levels 1..H-1 and the root views (level H), per
-    // channel and footprint pixel; descriptors: levels 0..H-1, per block
-    int ns = 0, nd = 0;
-    for (int l = 0; l <= g.H; l++) {
-        const int B0 = b.bmin >> l, A0 = b.amin >> l;
-        const int nB = (b.bmax >> l) - B0 + 1, nA = (b.amax >> l) - A0 + 1;
-        if (lv) lv[l] = LevelInfo{B0, nB, A0, nA, ns, nd};
-        if (l >= 1) ns += 3 * nB * nA;
-        if (l < g.H) nd += 3 * nB * nA * P.nbk;
-    }
-    P.nslots = ns;
-    P.ndesc = nd;
-    P.fits = (int64_t)P.nviews * P.npix <= bud.rgba && (int64_t)ns * P.npix <= bud.sval && nd <= bud.desc;
-    return P;
+    return d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1) / d);
 }
+__device__ __forceinline__ int lf_qdiv(int n, uint32_t m) { return m ? (int)__umulhi((uint32_t)n, m) : n; }
+
+// Plan of one group of views: the footprint's pixel box, and per level l
+// (0 = leaf views .. H = root) the bounding rectangle of the nodes the group
+// reaches, which of them some ray actually reaches ("used"), and their
+// compact numbering.  Only used nodes are staged.
+struct GroupPlan {
+    int ok;
+    int xmin, ymin, sx, npix;
+    int bkx0, bky0, nbkx, nbk;
+    int B0[LF_MAX_LEVELS + 1], A0[LF_MAX_LEVELS + 1], nA[LF_MAX_LEVELS + 1];
+    int nused[LF_MAX_LEVELS + 1];
+    int sbase[LF_MAX_LEVELS + 1];  // first staged slot of each level (levels 1..H)
+    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (levels 0..H-1)
+    int nslots, ndesc;
+    uint32_t m_npix, m_sx, m_nbk;
+};
+
+#define FALLBACK_MARK 0x7FC0DEADu  // NaN payload: "this tile of this view needs per-ray decoding"
 
 __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, int tiles_x, int tiles_y, int fpg,
                                                      float* __restrict__ out)
 {
     extern __shared__ uint4 lds_dyn[];
-    const Budget bud = lf_budget(fpg);
-    uint4* desc = lds_dyn;                                   // [bud.desc]
-    uint32_t* rgba = reinterpret_cast<uint32_t*>(desc + bud.desc);  // [bud.rgba]
-    int16_t* sval = reinterpret_cast<int16_t*>(rgba + bud.rgba);    // [bud.sval]
-    __shared__ int fbox[FMAX][8];
-    __shared__ int red[FMAX][8][NT / 64];
-    __shared__ LevelInfo lvl[LF_MAX_LEVELS + 1];
+    uint4* desc = lds_dyn;                                        // [B_DESC]
+    uint32_t* rgba = reinterpret_cast<uint32_t*>(desc + B_DESC);  // [B_RGBA]
+    int16_t* sval = reinterpret_cast<int16_t*>(rgba + B_RGBA);    // [B_SVAL]
+    uint32_t* red = rgba;  // phase-0 reduction scratch [FMAX][4][NT/64], before any sample is staged
+    __shared__ uint32_t fbox[FMAX][4];  // per view: min(a0|b0), max(a1|b1), min(x0|y0), max(x1|y1)
+    __shared__ GroupPlan gp;
+    __shared__ int8_t nodemap[LF_MAX_LEVELS + 1][LMAX];   // compact index of a rectangle entry, -1 unused
+    __shared__ uint8_t nodelist[LF_MAX_LEVELS + 1][LMAX]; // rectangle entry of a compact index
+    __shared__ uint32_t slotinfo[SLOT_MAX];
+    __shared__ uint16_t digits[384];
 
     // XCD-aware order: workgroup ids go round-robin over the 8 XCDs, so give
     // each XCD a contiguous range of (view group, tile) work: consecutive
@@ -259,140 +280,218 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
     const bool live = i < wo && j < ho;
     const int ii = live ? i : txi * TW, jj = live ? j : tyi * TH;  // dead lanes repeat the tile origin
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t t = threadIdx.x; t < 384u; t += NT) {
+        uint32_t d = 0, v = t < 256u ? t : t - 256u;
+        if (t < 256u)
+            for (int k = 0; k < 5; k++, v /= 3u) d |= (v % 3u) << (2 * k);
+        else
+            for (int k = 0; k < 3; k++, v /= 5u) d |= (v % 5u) << (3 * k);
+        digits[t] = (uint16_t)d;
+    }
 
-    // phase 0: footprint box of every view of the group
+    // phase 0: footprint box of every view of the group (packed 16-bit reductions)
     for (int f = 0; f < nf; f++) {
         const Ray r = lf_ray_setup(g, cams + 18 * (v0 + f), ii, jj);
-        int m[8] = {wave_min(r.a0), wave_max(r.a1), wave_min(r.b0), wave_max(r.b1),
-                    wave_min(r.x0), wave_max(r.x1), wave_min(r.y0), wave_max(r.y1)};
-        if (lane == 0)
-#pragma unroll
-            for (int k = 0; k < 8; k++) red[f][k][wid] = m[k];
+        const uint32_t m0 = wave_pk_min((uint32_t)r.a0 | ((uint32_t)r.b0 << 16));
+        const uint32_t m1 = wave_pk_max((uint32_t)r.a1 | ((uint32_t)r.b1 << 16));
+        const uint32_t m2 = wave_pk_min((uint32_t)r.x0 | ((uint32_t)r.y0 << 16));
+        const uint32_t m3 = wave_pk_max((uint32_t)r.x1 | ((uint32_t)r.y1 << 16));
+        if (lane == 0) {
+            red[(f * 4 + 0) * (NT / 64) + wid] = m0;
+            red[(f * 4 + 1) * (NT / 64) + wid] = m1;
+            red[(f * 4 + 2) * (NT / 64) + wid] = m2;
+            red[(f * 4 + 3) * (NT / 64) + wid] = m3;
+        }
     }
     __syncthreads();
-    if ((int)threadIdx.x < nf * 8) {
-        const int f = threadIdx.x >> 3, k = threadIdx.x & 7;
-        int v = red[f][k][0];
+    if ((int)threadIdx.x < nf * 4) {
+        const int k = threadIdx.x & 3;
+        uint32_t v = red[threadIdx.x * (NT / 64)];
 #pragma unroll
-        for (int w = 1; w < NT / 64; w++) v = (k & 1) ? max(v, red[f][k][w]) : min(v, red[f][k][w]);
-        fbox[f][k] = v;
+        for (int w = 1; w < NT / 64; w++) v = (k & 1) ? pk_max(v, red[threadIdx.x * (NT / 64) + w]) : pk_min(v, red[threadIdx.x * (NT / 64) + w]);
+        fbox[threadIdx.x >> 2][k] = v;
     }
     __syncthreads();
 
     const int64_t npix_out = (int64_t)wo * ho;
-    int f = 0;
+    int f = 0, n = nf;
     while (f < nf) {
-        // greedily grow the group of views while the union footprint fits
-        Box bx{fbox[f][0], fbox[f][1], fbox[f][2], fbox[f][3], fbox[f][4], fbox[f][5], fbox[f][6], fbox[f][7]};
-        int n = 1;
-        while (f + n < nf) {
-            const int q = f + n;
-            Box u{min(bx.amin, fbox[q][0]), max(bx.amax, fbox[q][1]), min(bx.bmin, fbox[q][2]), max(bx.bmax, fbox[q][3]),
-                  min(bx.xmin, fbox[q][4]), max(bx.xmax, fbox[q][5]), min(bx.ymin, fbox[q][6]), max(bx.ymax, fbox[q][7])};
-            if (!lf_plan(g, u, bud, nullptr).fits) break;
-            bx = u;
-            n++;
+        n = min(n, nf - f);
+        // plan the group [f, f + n): wave 0 marks the used nodes of every level
+        if (wid == 0) {
+            uint32_t lo_ab = 0xFFFFFFFFu, hi_ab = 0u, lo_xy = 0xFFFFFFFFu, hi_xy = 0u;
+            for (int q = f; q < f + n; q++) {
+                lo_ab = pk_min(lo_ab, fbox[q][0]);
+                hi_ab = pk_max(hi_ab, fbox[q][1]);
+                lo_xy = pk_min(lo_xy, fbox[q][2]);
+                hi_xy = pk_max(hi_xy, fbox[q][3]);
+            }
+            const int amin = (int)(lo_ab & 0xFFFFu), bmin = (int)(lo_ab >> 16);
+            const int amax = (int)(hi_ab & 0xFFFFu), bmax = (int)(hi_ab >> 16);
+            const int xmin = (int)(lo_xy & 0xFFFFu), ymin = (int)(lo_xy >> 16);
+            const int xmax = (int)(hi_xy & 0xFFFFu), ymax = (int)(hi_xy >> 16);
+            const int sx = xmax - xmin + 1, npix = sx * (ymax - ymin + 1);
+            const int bkx0 = xmin >> g.bsl, bky0 = ymin >> g.bsl;
+            const int nbkx = (xmax >> g.bsl) - bkx0 + 1, nbk = nbkx * ((ymax >> g.bsl) - bky0 + 1);
+            int ok = 1, ns = 0, nd = 0, nu0 = 0;
+            for (int l = 0; l <= g.H; l++) {
+                const int B0 = bmin >> l, A0 = amin >> l;
+                const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
+                const bool in_rect = nB * nA <= LMAX && lane < nB * nA;
+                bool used = false;
+                if (in_rect) {
+                    // node (B, A) covers views [B << l, (B + 1) << l) x [A << l, (A + 1) << l)
+                    const int B = B0 + lane / nA, A = A0 + lane % nA;
+                    const int vb0 = B << l, vb1 = ((B + 1) << l) - 1, va0 = A << l, va1 = ((A + 1) << l) - 1;
+                    for (int q = f; q < f + n && !used; q++) {
+                        const int qa0 = (int)(fbox[q][0] & 0xFFFFu), qb0 = (int)(fbox[q][0] >> 16);
+                        const int qa1 = (int)(fbox[q][1] & 0xFFFFu), qb1 = (int)(fbox[q][1] >> 16);
+                        used = qb0 <= vb1 && qb1 >= vb0 && qa0 <= va1 && qa1 >= va0;
+                    }
+                }
+                const uint64_t bal = __ballot(used);
+                const int cnt = __popcll(bal);
+                if (nB * nA > LMAX) ok = 0;
+                if (lane < LMAX) {
+                    const int idx = used ? __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+                    nodemap[l][lane] = (int8_t)idx;
+                    if (used) nodelist[l][idx] = (uint8_t)lane;
+                }
+                if (lane == 0) {
+                    gp.B0[l] = B0;
+                    gp.A0[l] = A0;
+                    gp.nA[l] = nA;
+                    gp.nused[l] = cnt;
+                    gp.sbase[l] = ns;
+                    if (l < g.H) gp.dbase[l] = nd;
+                }
+                if (l == 0) nu0 = cnt;
+                if (l >= 1) ns += 3 * cnt;
+                if (l < g.H) nd += 3 * cnt * nbk;
+            }
+            ok = ok && nu0 * npix <= B_RGBA && ns * npix <= B_SVAL && nd <= B_DESC && ns <= SLOT_MAX;
+            if (lane == 0) {
+                gp.ok = ok;
+                gp.xmin = xmin;
+                gp.ymin = ymin;
+                gp.sx = sx;
+                gp.npix = npix;
+                gp.bkx0 = bkx0;
+                gp.bky0 = bky0;
+                gp.nbkx = nbkx;
+                gp.nbk = nbk;
+                gp.nslots = ns;
+                gp.ndesc = nd;
+                gp.m_npix = lf_magic((uint32_t)npix);
+                gp.m_sx = lf_magic((uint32_t)sx);
+                gp.m_nbk = lf_magic((uint32_t)nbk);
+            }
         }
-        if (threadIdx.x == 0) lf_plan(g, bx, bud, lvl);
-        const Plan P = lf_plan(g, bx, bud, nullptr);
         __syncthreads();
-        if (!P.fits) {
-            // a single view whose footprint is too large: per-ray decoding
-            float o[3];
-            lf_render_one(g, p, cams + 18 * (v0 + f), ii, jj, o);
-            if (live)
-#pragma unroll
-                for (int c = 0; c < 3; c++) out[((int64_t)(v0 + f) * 3 + c) * npix_out + (int64_t)j * wo + i] = o[c];
+        if (!gp.ok) {
+            if (n > 1) {
+                n = (n + 1) / 2;  // try half the group
+                __syncthreads();
+                continue;
+            }
+            // one view whose footprint exceeds the budget: leave a marker for the per-ray pass
+            if (threadIdx.x == 0)
+                out[((int64_t)(v0 + f) * 3) * npix_out + (int64_t)(tyi * TH) * wo + txi * TW] =
+                    __uint_as_float(FALLBACK_MARK);
             f += 1;
+            n = nf;
+            __syncthreads();
             continue;
         }
-        // phase 1a: block descriptors of every node of every level in the box
-        for (int d = threadIdx.x; d < P.ndesc; d += NT) {
+        const int npix = gp.npix, sx = gp.sx, nbk = gp.nbk, nbkx = gp.nbkx;
+        const int xmin = gp.xmin, ymin = gp.ymin, bkx0 = gp.bkx0, bky0 = gp.bky0;
+        const uint32_t m_npix = gp.m_npix, m_sx = gp.m_sx, m_nbk = gp.m_nbk;
+        // phase 1a: block descriptors of the used nodes of levels 0..H-1, and
+        // the slot table of the staged values (levels 1..H)
+        for (int d = threadIdx.x; d < gp.ndesc; d += NT) {
             int l = 0;
-            while (l + 1 < g.H && d >= lvl[l + 1].dbase) l++;
-            const LevelInfo L = lvl[l];
-            int loc = d - L.dbase;
-            const int kb = loc % P.nbk;
-            loc /= P.nbk;
-            const int ai = loc % L.nA;
-            loc /= L.nA;
-            const int bi = loc % L.nB, c = loc / L.nB;
-            const int blk = (P.bky0 + kb / P.nbkx) * g.nbx + P.bkx0 + kb % P.nbkx;
-            desc[d] = lf_make_desc(g, p, c, l, L.B0 + bi, L.A0 + ai, blk);
+            while (l + 1 < g.H && d >= gp.dbase[l + 1]) l++;
+            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // c * nused + u
+            const int kb = d - gp.dbase[l] - row * nbk;
+            const int nu = gp.nused[l];
+            const int c = row / nu, u = row - c * nu;
+            const int e = nodelist[l][u];
+            const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
+            const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
+            desc[d] = lf_make_desc(g, p, c, l, B, A, blk);
+        }
+        for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
+            int l = 1;
+            while (l < g.H && sl >= gp.sbase[l + 1]) l++;
+            const int row = sl - gp.sbase[l];  // c * nused + u
+            const int nu = gp.nused[l];
+            const int c = row / nu, u = row - c * nu;
+            uint32_t info;
+            if (l == g.H) {
+                const int e = nodelist[l][u];
+                const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
+                info = 0x80000000u | (uint32_t)((c * g.root_nb + B) * g.root_na + A);
+            } else {
+                info = (uint32_t)(gp.dbase[l] + row * nbk);
+            }
+            slotinfo[sl] = info;
         }
         __syncthreads();
         // phase 1b: values shared by several views, once per node and pixel:
         // SRVs of levels 1..H-1 and the root RKV (level H)
-        {
-            const int total = P.nslots * P.npix;
-            auto stage = [&](int it) -> int {
-                const int slot = it / P.npix, px = it - slot * P.npix;
-                int l = 1;
-                while (l < g.H && slot >= lvl[l + 1].sbase) l++;
-                const LevelInfo L = lvl[l];
-                const int node_c = slot - L.sbase;  // (c * nB + bi) * nA + ai
-                const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
-                if (l == g.H) {
-                    const int ai = node_c % L.nA, rest = node_c / L.nA;
-                    const int bi = rest % L.nB, c = rest / L.nB;
-                    return p.root[((size_t)(c * g.root_nb + L.B0 + bi) * g.root_na + L.A0 + ai) * (size_t)(g.w * g.h) +
-                                  y * g.w + x];
-                }
-                const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
-                return lf_srv_from_desc(g, p, desc[L.dbase + node_c * P.nbk + kb], y, x);
-            };
-            // two independent items per trip keep more loads in flight
-            for (int it = threadIdx.x; it < total; it += 2 * NT) {
-                const int it2 = it + NT;
-                const int v1 = stage(it);
-                const int v2 = it2 < total ? stage(it2) : 0;
-                sval[it] = (int16_t)v1;
-                if (it2 < total) sval[it2] = (int16_t)v2;
+        for (int it = threadIdx.x; it < gp.nslots * npix; it += NT) {
+            const int sl = lf_qdiv(it, m_npix), px = it - sl * npix;
+            const int yl = lf_qdiv(px, m_sx);
+            const int y = ymin + yl, x = xmin + px - yl * sx;
+            const uint32_t info = slotinfo[sl];
+            int v;
+            if (info & 0x80000000u) {
+                v = p.root[(size_t)(info & 0x7FFFFFFFu) * (size_t)(g.w * g.h) + (uint32_t)__mul24(y, g.w) + (uint32_t)x];
+            } else {
+                const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x >> g.bsl) - bkx0;
+                v = lf_srv_from_desc(g, p, desc[info + kb], y, x, digits);
             }
+            sval[it] = (int16_t)v;
         }
         __syncthreads();
-        // phase 2: every (view, pixel) sample: level-0 SRV + staged ancestors and root
-        {
-            const int total = P.nviews * P.npix;
-            auto assemble = [&](int it) -> uint32_t {
-                const int vi = it / P.npix, px = it - vi * P.npix;
-                const int b = bx.bmin + vi / P.nva, a = bx.amin + vi % P.nva;
-                const int y = bx.ymin + px / P.sx, x = bx.xmin + px % P.sx;
-                const int kb = (y / g.bs - P.bky0) * P.nbkx + (x / g.bs - P.bkx0);
-                const LevelInfo L0 = lvl[0];
-                int ch[3];
+        // phase 2: every used (view, pixel) sample: level-0 SRV + staged ancestors and root
+        const int nu0 = gp.nused[0];
+        for (int it = threadIdx.x; it < nu0 * npix; it += NT) {
+            const int u = lf_qdiv(it, m_npix), px = it - u * npix;
+            const int e = nodelist[0][u];
+            const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
+            const int yl = lf_qdiv(px, m_sx);
+            const int y = ymin + yl, x = xmin + px - yl * sx;
+            const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x >> g.bsl) - bkx0;
+            int ch[3];
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    int v = lf_srv_from_desc(g, p, desc[((c * L0.nB + (b - L0.B0)) * L0.nA + (a - L0.A0)) * P.nbk + kb], y, x);
-                    for (int l = 1; l <= g.H; l++) {
-                        const LevelInfo L = lvl[l];
-                        v += sval[(L.sbase + (c * L.nB + ((b >> l) - L.B0)) * L.nA + ((a >> l) - L.A0)) * P.npix + px];
-                    }
-                    ch[c] = v;
-                }
-                int R, G, B;
-                lf_ycocg_to_rgb(ch[0], ch[1], ch[2], R, G, B);
-                return (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
-            };
-            for (int it = threadIdx.x; it < total; it += 2 * NT) {
-                const int it2 = it + NT;
-                const uint32_t v1 = assemble(it);
-                const uint32_t v2 = it2 < total ? assemble(it2) : 0u;
-                rgba[it] = v1;
-                if (it2 < total) rgba[it2] = v2;
+            for (int c = 0; c < 3; c++) ch[c] = lf_srv_from_desc(g, p, desc[__mul24(c * nu0 + u, nbk) + kb], y, x, digits);
+            for (int l = 1; l <= g.H; l++) {
+                const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
+                const int node = gp.sbase[l] + nodemap[l][el];
+                const int nu = gp.nused[l];
+#pragma unroll
+                for (int c = 0; c < 3; c++) ch[c] += sval[__mul24(node + c * nu, npix) + px];
             }
+            int R, G, B;
+            lf_ycocg_to_rgb(ch[0], ch[1], ch[2], R, G, B);
+            rgba[it] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
         }
         __syncthreads();
         // phase 3: blend every ray of the group's views
         for (int q = f; q < f + n; q++) {
             const Ray r = lf_ray_setup(g, cams + 18 * (v0 + q), ii, jj);
+            const int pix = __mul24(r.y0 - ymin, sx) + (r.x0 - xmin);
+            const int ox = r.x1 - r.x0, oy = __mul24(r.y1 - r.y0, sx);
+            int vb[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int b = (k & 2) ? r.b1 : r.b0, a = (k & 1) ? r.a1 : r.a0;
+                vb[k] = __mul24(nodemap[0][__mul24(b - gp.B0[0], gp.nA[0]) + (a - gp.A0[0])], npix) + pix;
+            }
             uint32_t s16[16];
 #pragma unroll
-            for (int k = 0; k < 16; k++) {
-                const int b = (k & 8) ? r.b1 : r.b0, a = (k & 4) ? r.a1 : r.a0;
-                const int y = (k & 2) ? r.y1 : r.y0, x = (k & 1) ? r.x1 : r.x0;
-                s16[k] = rgba[((b - bx.bmin) * P.nva + (a - bx.amin)) * P.npix + (y - bx.ymin) * P.sx + (x - bx.xmin)];
-            }
+            for (int k = 0; k < 16; k++) s16[k] = rgba[vb[k >> 2] + ((k & 2) ? oy : 0) + ((k & 1) ? ox : 0)];
             if (live) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -405,6 +504,57 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
         }
         __syncthreads();  // LDS is reused by the next group of views
         f += n;
+        n = nf;
+    }
+}
+
+// Per-ray rendering of the (view, tile) pairs the batched kernel marked.
+// Each thread checks one pair; the workgroup then renders its marked pairs.
+__global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
+                                                        int wo, int ho, int tiles_x, int tiles_y,
+                                                        float* __restrict__ out)
+{
+    __shared__ int marked[NT];
+    __shared__ int n_marked;
+    const int64_t n_pairs = (int64_t)nv * tiles_x * tiles_y;
+    const int64_t npix = (int64_t)wo * ho;
+    const int64_t pr = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (threadIdx.x == 0) n_marked = 0;
+    __syncthreads();
+    int mine = 0;
+    if (pr < n_pairs) {
+        const int v = (int)(pr / ((int64_t)tiles_x * tiles_y));
+        const int tt = (int)(pr - (int64_t)v * tiles_x * tiles_y);
+        const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
+        mine = __float_as_uint(out[(int64_t)v * 3 * npix + (int64_t)(tyi * TH) * wo + txi * TW]) == FALLBACK_MARK;
+    }
+    // compact the marked pairs of this workgroup in thread order
+    const uint64_t bal = __ballot(mine);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ int wcount[NT / 64];
+    if (lane == 0) wcount[wid] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w = 0; w < wid; w++) off += wcount[w];
+    if (mine) marked[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)threadIdx.x;
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < NT / 64; w++) t += wcount[w];
+        n_marked = t;
+    }
+    __syncthreads();
+    for (int k = 0; k < n_marked; k++) {
+        const int64_t q = (int64_t)blockIdx.x * NT + marked[k];
+        const int v = (int)(q / ((int64_t)tiles_x * tiles_y));
+        const int tt = (int)(q - (int64_t)v * tiles_x * tiles_y);
+        const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
+        const int i = txi * TW + (int)threadIdx.x % TW, j = tyi * TH + (int)threadIdx.x / TW;
+        if (i < wo && j < ho) {
+            float o[3];
+            lf_render_one(g, p, cams + 18 * v, i, j, o);
+#pragma unroll
+            for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + (int64_t)j * wo + i] = o[c];
+        }
     }
 }
 
@@ -412,7 +562,7 @@ static int frames_per_group()
 {
     static int fpg = [] {
         const char* e = getenv("HMLFC_VIEWS_PER_GROUP");
-        int v = e ? atoi(e) : 8;
+        int v = e ? atoi(e) : 16;
         return v < 1 ? 1 : (v > FMAX ? FMAX : v);
     }();
     return fpg;
@@ -426,7 +576,7 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int64_t n_work = (int64_t)tx * ty * ((nv + fpg - 1) / fpg);
     const int64_t grid = ((n_work + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
-    const size_t lds = lf_lds_bytes(lf_budget(fpg));
+    const size_t lds = LDS_DYN_BYTES;
     static bool attr_set = false;
     if (lds > 65536 && !attr_set) {
         if (hipFuncSetAttribute((const void*)k_render_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
@@ -434,8 +584,11 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
             return lf_fail(LF_EDEVICE, "cannot reserve %zu bytes of LDS", lds);
         attr_set = true;
     }
-    hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), lf_lds_bytes(lf_budget(fpg)), s, h->L.g, h->p,
+    hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
                        d_cams, nv, wo, ho, tx, ty, fpg, d_out);
+    const int64_t pairs = (int64_t)tx * ty * nv;
+    hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)((pairs + NT - 1) / NT)), dim3(NT), 0, s, h->L.g, h->p, d_cams,
+                       nv, wo, ho, tx, ty, d_out);
     return lf_check_launch("render_batch");
 }
 
