@@ -59,6 +59,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true", help="skip the one-view-per-launch latency pass")
     ap.add_argument("--cpu-rays", type=int, default=0, help="oracle sample size (0: automatic)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload instead: resident light fields, Poisson view requests")
+    ap.add_argument("--serve-fields", default="serve256,path512,serve1024,batch1080")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     return ap.parse_args()
 
 
@@ -81,6 +86,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.serve:
+        serve_bench(args)
+        return
     cfg = lfscene.get_config(args.workload)
     L = cfg["lf"]
     t0 = time.time()
@@ -176,6 +184,62 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, light, cams_np, wo, ho, args.cpu_rays)
     print(json.dumps(result), flush=True)
+
+
+def serve_bench(args):
+    """Resident light fields; Poisson requests at --serve-rate for --serve-seconds with output
+    resolutions drawn from {256^2, 512^2, 1920x1080, 2048^2} and uniformly random light field and
+    pinhole camera; served by the continuous-batching server and, on the same schedule, by one
+    render launch per request."""
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+    from paper_1902_09396_amd.serve import Server, baseline
+
+    fields, shapes = [], []
+    for name in args.serve_fields.split(","):
+        cfg = lfscene.get_config(name)
+        L = cfg["lf"]
+        t0 = time.time()
+        light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+        stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+        del light
+        fields.append(lf.LightField(stream, device="cuda:0"))
+        shapes.append((L["na"], L["nb"], L["w"], L["h"]))
+        log("field %s: %d bytes, %.1fs" % (name, stream.size, time.time() - t0))
+    rng = np.random.default_rng(55)
+    n = int(args.serve_rate * args.serve_seconds)
+    arrival = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n))
+    res = np.array([[256, 256], [512, 512], [1920, 1080], [2048, 2048]])
+    wh = res[rng.integers(0, 4, size=n)]
+    field = rng.integers(0, len(fields), size=n).astype(np.int32)
+    cams = np.zeros((n, 18), dtype=np.float32)
+    for k in range(n):
+        na, nb, w, h = shapes[field[k]]
+        cams[k] = lfscene.random_pinhole_cameras(1, na, nb, w, h, int(wh[k, 0]), int(wh[k, 1]),
+                                                 seed=int(rng.integers(1 << 30)))[0]
+    rays = float((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
+    srv = Server(fields, pool_bytes=4 << 30, max_slots=64, max_tiles=16384, chunk_tiles=1024, n_streams=2)
+    lat, mk = srv.replay(field, cams, wh, arrival)
+    stats = srv.stats()
+    srv.close()
+    lat_b, mk_b = baseline(fields, field, cams, wh, arrival)
+
+    def summary(l, m):
+        return {"p50_ms": round(float(np.percentile(l, 50)), 3), "p99_ms": round(float(np.percentile(l, 99)), 3),
+                "mean_ms": round(float(l.mean()), 3), "grays_per_s": round(rays / m / 1e9, 4), "makespan_s": round(m, 3)}
+
+    srv_sum, base_sum = summary(lat, mk), summary(lat_b, mk_b)
+    print(json.dumps({
+        "metric": "serving: p50/p99 request latency and rays/s",
+        "value": srv_sum["p99_ms"], "unit": "ms (p99)", "higher_is_better": False, "n_gpus": 1,
+        "data": "synthetic",
+        "config": {"workload": "%d resident light fields (%s); %d Poisson requests at %.0f/s; resolutions "
+                               "256^2/512^2/1920x1080/2048^2" % (len(fields), args.serve_fields, n, args.serve_rate),
+                   "offered_grays_per_s": round(rays / arrival[-1] / 1e9, 4)},
+        "server": srv_sum, "per_request_launches": base_sum, "server_stats": stats,
+    }), flush=True)
 
 
 def cpu_baseline(cfg, light, cams_np, wo, ho, n_rays):

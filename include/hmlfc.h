@@ -16,9 +16,9 @@
  *    h_st.  Output pixel (i, j) (column, row) is mapped at its centre
  *    (i + 0.5, j + 0.5, 1); dividing by the third component gives the ray's
  *    (u, v) in view-grid units and (s, t) in image pixels.
- *  - "Device" pointers are HIP device allocations owned by the caller (the
- *    library never allocates device memory except inside lf_encode's host
- *    work and lf_footprint_bytes' scratch, both outside the render path).
+ *  - "Device" pointers are HIP device allocations owned by the caller.  The
+ *    render and decode calls allocate nothing; lf_footprint_bytes allocates
+ *    a temporary buffer and the serving loop its small tables.
  *    "Host" pointers are ordinary process memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call that takes a stream only enqueues work on it; outputs are
@@ -183,6 +183,62 @@ lf_status lf_render_backward(const lf_handle* h, const float* d_residual, const 
                              int32_t n_views, int32_t width, int32_t height, const float* d_grad_out,
                              float* d_grad_residual, float* d_grad_shift, void* d_workspace, int64_t workspace_bytes,
                              void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: several loaded light fields stay resident; view requests of    */
+/* mixed resolution are admitted by output memory and request slots and   */
+/* continuously batched (32x8 tiles, round robin between requests) into    */
+/* launches of a persistent kernel, each launch a replay of a graph        */
+/* captured once per stream, with up to n_streams launches in flight.      */
+/* A request's pixels are the same as lf_render_views' for its camera.     */
+/* The server allocates only its small tables (geometry, slots, work       */
+/* lists); outputs live in the caller's pool.                              */
+/* ---------------------------------------------------------------------- */
+
+typedef struct lf_server lf_server;
+
+typedef struct {
+    int32_t max_slots;   /* requests resident on the device at once (>= 1)            */
+    int32_t max_tiles;   /* 32x8 tiles per launch (>= 1)                               */
+    int32_t chunk_tiles; /* tiles one request adds to a launch per round (>= 1)        */
+    int32_t n_streams;   /* launches in flight, 1..4                                   */
+    int32_t use_graphs;  /* 1: each launch replays a captured graph                    */
+    int32_t grid;        /* persistent workgroups per launch (0: 3 per compute unit)   */
+} lf_server_config;
+
+typedef struct {
+    int64_t submitted, admitted, completed, launches, tiles;
+} lf_server_stats;
+
+/* fields: n_fields loaded handles (block size >= 4), borrowed for the
+ * server's lifetime.  d_pool: caller-owned device memory of pool_bytes that
+ * holds request outputs (float [3][height][width] each, 256-byte aligned). */
+lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields, void* d_pool, int64_t pool_bytes,
+                           const lf_server_config* cfg, lf_server** out);
+/* Queue a request (host camera float[18]).  auto_release = 1 frees its
+ * output memory as soon as it completes (for load tests that do not read
+ * it).  LF_ENOMEM if its output can never fit the pool. */
+lf_status lf_server_submit(lf_server* s, int32_t field, const float* host_cam, int32_t width, int32_t height,
+                           int32_t auto_release, int64_t* id);
+/* Block until request id completes; its output starts at d_pool + *out_offset;
+ * latency is from submission to the completion of its last launch. */
+lf_status lf_server_wait(lf_server* s, int64_t id, double timeout_s, int64_t* out_offset, double* latency_ms);
+/* Forget a completed request and return its output memory to the pool. */
+lf_status lf_server_release(lf_server* s, int64_t id);
+lf_status lf_server_get_stats(lf_server* s, lf_server_stats* out);
+lf_status lf_server_destroy(lf_server* s);
+
+/* Open-loop replay: request k (field[k], cams[k][18], wh[k] = width, height)
+ * is submitted arrival_s[k] seconds after the call starts; latency_ms[k] is
+ * measured from submission to completion; *makespan_s ends at the last
+ * completion. */
+lf_status lf_server_replay(lf_server* s, int64_t n, const int32_t* field, const float* cams, const int32_t* wh,
+                           const double* arrival_s, double* latency_ms, double* makespan_s);
+/* The same schedule served by one lf_render_views launch per request, in
+ * arrival order on one stream (d_out holds the largest output). */
+lf_status lf_serve_baseline(lf_handle* const* fields, int32_t n_fields, int64_t n, const int32_t* field,
+                            const float* cams, const int32_t* wh, const double* arrival_s, void* d_out,
+                            int64_t out_bytes, double* latency_ms, double* makespan_s);
 
 /* ---------------------------------------------------------------------- */
 /* Encoding (host, OpenMP; not on the render path).  Follows the paper's   */

@@ -180,10 +180,21 @@ __device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float
         float sum = a + bb;
         q[r] = sum + h[2];
     }
-    u = q[0] / q[2];
-    v = q[1] / q[2];
-    s = q[3] / q[5];
-    t = q[4] / q[5];
+    // x / 1 == x exactly, so affine maps (third row 0 0 1) skip the divisions
+    if (q[2] == 1.0f) {
+        u = q[0];
+        v = q[1];
+    } else {
+        u = q[0] / q[2];
+        v = q[1] / q[2];
+    }
+    if (q[5] == 1.0f) {
+        s = q[3];
+        t = q[4];
+    } else {
+        s = q[3] / q[5];
+        t = q[4] / q[5];
+    }
 }
 
 // Clamp a coordinate to [0, n-1]; lower neighbour k (<= n-2), upper

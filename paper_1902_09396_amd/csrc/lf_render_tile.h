@@ -1,0 +1,540 @@
+// Device-side tile renderer shared by the batched render kernel and the
+// serving kernel (see lf_render.hip for the design).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lf_internal.h"
+
+__device__ __forceinline__ float lf_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
+
+struct Ray {
+    int a0, a1, b0, b1, x0, x1, y0, y1;
+    float fu, fv, fs, ft;
+};
+
+__device__ __forceinline__ Ray lf_ray_setup(const LfGeom& g, const float* __restrict__ cam, int i, int j)
+{
+    Ray r;
+    float u, v, s, t;
+    lf_ray(cam, i, j, u, v, s, t);
+    lf_axis(u, g.na, r.a0, r.a1, r.fu);
+    lf_axis(v, g.nb, r.b0, r.b1, r.fv);
+    lf_axis(s, g.w, r.x0, r.x1, r.fs);
+    lf_axis(t, g.h, r.y0, r.y1, r.ft);
+    return r;
+}
+
+// quadrilinear blend of 16 samples given as unscaled 8-bit values; order s, t, u, v
+__device__ __forceinline__ float lf_blend16(const float (&sm)[16], const Ray& r)
+{
+    float vw[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+        vw[q] = lf_lerp(lf_lerp(sm[4 * q], sm[4 * q + 1], r.fs), lf_lerp(sm[4 * q + 2], sm[4 * q + 3], r.fs), r.ft);
+    return lf_lerp(lf_lerp(vw[0], vw[1], r.fu), lf_lerp(vw[2], vw[3], r.fu), r.fv) * (1.0f / 255.0f);
+}
+
+// ---------------------------------------------------------------------------
+// per-ray reference path
+// ---------------------------------------------------------------------------
+
+__device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cam, int i, int j,
+                                     float out[3])
+{
+    const Ray r = lf_ray_setup(g, cam, i, j);
+    uint32_t px[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int b = (k & 8) ? r.b1 : r.b0, a = (k & 4) ? r.a1 : r.a0;
+        const int y = (k & 2) ? r.y1 : r.y0, x = (k & 1) ? r.x1 : r.x0;
+        int Y = lf_decode_channel(g, p, 0, b, a, y, x);
+        int Co = lf_decode_channel(g, p, 1, b, a, y, x);
+        int Cg = lf_decode_channel(g, p, 2, b, a, y, x);
+        int R, G, B;
+        lf_ycocg_to_rgb(Y, Co, Cg, R, G, B);
+        px[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float sm[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) sm[k] = (float)((px[k] >> (8 * c)) & 255u);
+        out[c] = lf_blend16(sm, r);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batched tile renderer
+// ---------------------------------------------------------------------------
+
+#define TW 32
+#define TH 8
+#define NT (TW * TH)
+#define FMAX 32          // views per workgroup (upper bound of the group size)
+#define LMAX 64          // nodes of one level inside a group's bounding rectangle
+#define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
+#define SLOT_MAX 160
+
+// LDS staging budgets (entries): descriptors (16 B), assembled samples (4 B),
+// staged ancestor/root values (2 B).  About 46 KiB plus 6 KiB of tables keeps
+// three 256-thread workgroups resident per CU.
+#define B_DESC 384
+#define B_RGBA 4096
+#define B_SVAL 12288
+#define LDS_DYN_BYTES (B_DESC * 16 + B_RGBA * 4 + B_SVAL * 2)
+
+// 16-bit packed min/max (both halves at once)
+typedef unsigned short lf_u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pk_min(uint32_t a, uint32_t b)
+{
+    lf_u16x2 x = __builtin_bit_cast(lf_u16x2, a), y = __builtin_bit_cast(lf_u16x2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
+}
+
+__device__ __forceinline__ uint32_t pk_max(uint32_t a, uint32_t b)
+{
+    lf_u16x2 x = __builtin_bit_cast(lf_u16x2, a), y = __builtin_bit_cast(lf_u16x2, b);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+}
+
+__device__ __forceinline__ uint32_t wave_pk_min(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = pk_min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_pk_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = pk_max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// Block descriptor: x = payload word, y = min (16) | step (13) << 16 | phase code << 29,
+// z = mx (12, signed) | my (12, signed) << 12 | mode << 24, w = plane offset (elements)
+// of the reference plane (predictive node) or of the node's own plane (reference node).
+__device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, int blk)
+{
+    const uint32_t plane = (uint32_t)(g.w * g.h);
+    const uint32_t ref = (uint32_t)(c * g.n_refs + g.ref_base[l] + (B >> 1) * g.na_l[l + 1] + (A >> 1)) * plane;
+    if (!((A | B) & 1)) return make_uint4(0u, 0u, (uint32_t)MODE_PLANE << 24, ref);
+    const int node = g.node_base[l] + B * g.na_l[l] + A;
+    const uint2 e = p.table[((size_t)c * g.n_nodes + node) * g.nblk + blk];
+    int mx, my, sg;
+    lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
+    const uint32_t mode = (e.y >> 16) & 0xFFu;
+    const uint32_t code = sg == 1 ? 0u : (sg == -1 ? 1u : 2u);
+    return make_uint4(e.x, (e.y & 0xFFFFu) | ((uint32_t)g.step[l] << 16) | (code << 29),
+                      ((uint32_t)mx & 0xFFFu) | (((uint32_t)my & 0xFFFu) << 12) | (mode << 24), ref);
+}
+
+// Bounded-integer value i of a block, one code path for the three families
+// (no divergence between neighbouring blocks of different families): a value
+// is (high digit << b) | b-bit low part, where the group of G values (G = 1,
+// 5 or 3) starts with an hb-bit header (hb = 0, 8 or 7) whose digit k is read
+// from a table: digits[t] packs the base-3 digits of t (2 bits each) and
+// digits[256 + q] the base-5 digits of q (3 bits each); digits[0] = 0.
+__device__ __forceinline__ uint32_t lf_bise_any(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i,
+                                                const uint16_t* __restrict__ digits)
+{
+    const uint32_t fam = mode >> 5, b = mode & 31u;
+    const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
+    const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
+    const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
+    const uint32_t grp = fam == 0u ? i : __umulhi(i, mg);
+    const uint32_t k = i - grp * gs;
+    const uint32_t base = __umul24(grp, hb + gs * b);
+    const uint32_t head = lf_field(w, base, (int)hb);
+    const uint32_t lo = lf_field(w, base + hb + __umul24(k, b), (int)b);
+    const uint32_t dig = digits[(fam == 2u ? 256u : 0u) + head];
+    const uint32_t hi = fam == 2u ? (dig >> (3u * k)) & 7u : (dig >> (2u * k)) & 3u;
+    return (hi << b) | lo;
+}
+
+// SRV values at (y, x0 .. x0 + 3) of the node a descriptor belongs to (x0 a
+// multiple of 4, so the quad lies in one block: one descriptor, one motion
+// vector, shared prediction taps and weights).
+struct Quad {
+    int v[4];
+};
+
+__device__ __forceinline__ Quad lf_srv_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
+                                            const uint16_t* __restrict__ digits)
+{
+    Quad r;
+    const uint32_t mode = d.z >> 24;
+    if (mode == MODE_PLANE) {
+        // reference node: 4 int16 of its resident plane, 8-byte aligned
+        const uint2 w2 = *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
+        r.v[0] = (int)(int16_t)(w2.x & 0xFFFFu);
+        r.v[1] = (int)(int16_t)(w2.x >> 16);
+        r.v[2] = (int)(int16_t)(w2.y & 0xFFFFu);
+        r.v[3] = (int)(int16_t)(w2.y >> 16);
+        return r;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) r.v[k] = 0;
+    if (mode != LF_MODE_ZERO) {
+        const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
+        const int mn = (int)(int16_t)(d.y & 0xFFFFu);
+        const int step = (int)((d.y >> 16) & 0x1FFFu);
+        const uint32_t* w = p.payload + d.x;
+#pragma unroll
+        for (int k = 0; k < 4; k++) r.v[k] = __mul24(mn + (int)lf_bise_any(w, mode, i0 + (uint32_t)k, digits), step);
+    }
+    const uint32_t code = d.y >> 29;
+    if (code < 2u) {
+        const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
+        const int16_t* R = p.refs + d.w;
+        const int xb = x0 + (mx >> 2), fx = mx & 3;
+        const int Y = 4 * y + my, y0 = Y >> 2, fy = Y & 3;
+        const int ra = __mul24(lf_clampi(y0, 0, g.h - 1), g.w), rb = __mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w);
+        int ta[5], tb[5];
+#pragma unroll
+        for (int c = 0; c < 5; c++) {
+            const int xc = lf_clampi(xb + c, 0, g.w - 1);
+            ta[c] = R[ra + xc];
+            tb[c] = R[rb + xc];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int top = (4 - fx) * ta[k] + fx * ta[k + 1];
+            const int bot = (4 - fx) * tb[k] + fx * tb[k + 1];
+            const int q = ((4 - fy) * top + fy * bot + 8) >> 4;
+            r.v[k] += code == 0u ? q : -q;
+        }
+    }
+    return r;
+}
+
+// floor(n / d) for n, d < 2^16: m = ceil(2^32 / d) for d >= 2 (exact in that
+// range); d = 1 would need m = 2^32, so it is encoded as m = 0 (identity)
+__device__ __forceinline__ uint32_t lf_magic(uint32_t d)
+{
+    return d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1) / d);
+}
+__device__ __forceinline__ int lf_qdiv(int n, uint32_t m) { return m ? (int)__umulhi((uint32_t)n, m) : n; }
+
+// Plan of one group of views: the footprint's pixel box, and per level l
+// (0 = leaf views .. H = root) the bounding rectangle of the nodes the group
+// reaches, which of them some ray actually reaches ("used"), and their
+// compact numbering.  Only used nodes are staged.
+struct GroupPlan {
+    int ok;
+    int xq0, ymin, sy, nq, sxp, npix;  // quad-aligned rows: x from xq0, nq quads per row, stride sxp = 4 nq
+    int bkx0, bky0, nbkx, nbk;
+    int B0[LF_MAX_LEVELS + 1], A0[LF_MAX_LEVELS + 1], nA[LF_MAX_LEVELS + 1];
+    int nused[LF_MAX_LEVELS + 1];
+    int sbase[LF_MAX_LEVELS + 1];  // first staged slot of each level (levels 1..H)
+    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (levels 0..H-1)
+    int nslots, ndesc;
+    uint32_t m_rowq, m_nq, m_nbk;  // reciprocals of sy * nq, nq and nbk
+};
+
+#define FALLBACK_MARK 0x7FC0DEADu  // NaN payload: "this tile of this view needs per-ray decoding"
+
+// LDS of one tile renderer instance.
+struct TileLds {
+    uint4* desc;       // [B_DESC]
+    uint32_t* rgba;    // [B_RGBA]
+    int16_t* sval;     // [B_SVAL]
+    uint32_t (*fbox)[4];
+    GroupPlan* gpp;
+    int8_t (*nodemap)[LMAX];
+    uint8_t (*nodelist)[LMAX];
+    uint32_t* slotinfo;
+    const uint16_t* digits;
+};
+
+#define TILE_LDS_DECL                                                                            \
+    extern __shared__ uint4 lds_dyn[];                                                           \
+    __shared__ uint32_t fbox_s[FMAX][4];                                                         \
+    __shared__ GroupPlan gp_s;                                                                   \
+    __shared__ int8_t nodemap_s[LF_MAX_LEVELS + 1][LMAX];                                        \
+    __shared__ uint8_t nodelist_s[LF_MAX_LEVELS + 1][LMAX];                                      \
+    __shared__ uint32_t slotinfo_s[SLOT_MAX];                                                    \
+    __shared__ uint16_t digits_s[384];                                                           \
+    const TileLds S{lds_dyn,                                                                     \
+                    reinterpret_cast<uint32_t*>(lds_dyn + B_DESC),                               \
+                    reinterpret_cast<int16_t*>(reinterpret_cast<uint32_t*>(lds_dyn + B_DESC) + B_RGBA), \
+                    fbox_s, &gp_s, nodemap_s, nodelist_s, slotinfo_s, digits_s};                 \
+    for (uint32_t t = threadIdx.x; t < 384u; t += NT) {                                         \
+        uint32_t d = 0, v = t < 256u ? t : t - 256u;                                             \
+        if (t < 256u)                                                                            \
+            for (int k = 0; k < 5; k++, v /= 3u) d |= (v % 3u) << (2 * k);                       \
+        else                                                                                     \
+            for (int k = 0; k < 3; k++, v /= 5u) d |= (v % 5u) << (3 * k);                       \
+        digits_s[t] = (uint16_t)d;                                                               \
+    }                                                                                            \
+    __syncthreads();
+
+// Render screen tile (txi, tyi) of views v0 .. v0 + nf - 1 (cameras cams[v],
+// output out[v][3][ho][wo]).  Every thread of the workgroup calls it; LDS
+// contents do not carry over between calls.
+template <bool INLINE_FALLBACK>
+__device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
+                              int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
+{
+    uint4* desc = S.desc;
+    uint32_t* rgba = S.rgba;
+    int16_t* sval = S.sval;
+    uint32_t* red = rgba;  // phase-0 reduction scratch [FMAX][4][NT/64], before any sample is staged
+    uint32_t (*fbox)[4] = S.fbox;
+    GroupPlan& gp = *S.gpp;
+    int8_t (*nodemap)[LMAX] = S.nodemap;
+    uint8_t (*nodelist)[LMAX] = S.nodelist;
+    uint32_t* slotinfo = S.slotinfo;
+    const uint16_t* digits = S.digits;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int i = txi * TW + lx, j = tyi * TH + ly;
+    const bool live = i < wo && j < ho;
+    const int ii = live ? i : txi * TW, jj = live ? j : tyi * TH;  // dead lanes repeat the tile origin
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // phase 0: footprint box of every view of the group (packed 16-bit reductions)
+    for (int f = 0; f < nf; f++) {
+        const Ray r = lf_ray_setup(g, cams + 18 * (v0 + f), ii, jj);
+        const uint32_t m0 = wave_pk_min((uint32_t)r.a0 | ((uint32_t)r.b0 << 16));
+        const uint32_t m1 = wave_pk_max((uint32_t)r.a1 | ((uint32_t)r.b1 << 16));
+        const uint32_t m2 = wave_pk_min((uint32_t)r.x0 | ((uint32_t)r.y0 << 16));
+        const uint32_t m3 = wave_pk_max((uint32_t)r.x1 | ((uint32_t)r.y1 << 16));
+        if (lane == 0) {
+            red[(f * 4 + 0) * (NT / 64) + wid] = m0;
+            red[(f * 4 + 1) * (NT / 64) + wid] = m1;
+            red[(f * 4 + 2) * (NT / 64) + wid] = m2;
+            red[(f * 4 + 3) * (NT / 64) + wid] = m3;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nf * 4) {
+        const int k = threadIdx.x & 3;
+        uint32_t v = red[threadIdx.x * (NT / 64)];
+#pragma unroll
+        for (int w = 1; w < NT / 64; w++) v = (k & 1) ? pk_max(v, red[threadIdx.x * (NT / 64) + w]) : pk_min(v, red[threadIdx.x * (NT / 64) + w]);
+        fbox[threadIdx.x >> 2][k] = v;
+    }
+    __syncthreads();
+
+    const int64_t npix_out = (int64_t)wo * ho;
+    int f = 0, n = nf;
+    while (f < nf) {
+        n = min(n, nf - f);
+        // plan the group [f, f + n): wave 0 marks the used nodes of every level
+        if (wid == 0) {
+            uint32_t lo_ab = 0xFFFFFFFFu, hi_ab = 0u, lo_xy = 0xFFFFFFFFu, hi_xy = 0u;
+            for (int q = f; q < f + n; q++) {
+                lo_ab = pk_min(lo_ab, fbox[q][0]);
+                hi_ab = pk_max(hi_ab, fbox[q][1]);
+                lo_xy = pk_min(lo_xy, fbox[q][2]);
+                hi_xy = pk_max(hi_xy, fbox[q][3]);
+            }
+            const int amin = (int)(lo_ab & 0xFFFFu), bmin = (int)(lo_ab >> 16);
+            const int amax = (int)(hi_ab & 0xFFFFu), bmax = (int)(hi_ab >> 16);
+            const int xmin = (int)(lo_xy & 0xFFFFu), ymin = (int)(lo_xy >> 16);
+            const int xmax = (int)(hi_xy & 0xFFFFu), ymax = (int)(hi_xy >> 16);
+            const int xq0 = xmin & ~3, nq = (xmax >> 2) - (xmin >> 2) + 1, sxp = 4 * nq;
+            const int sy = ymax - ymin + 1, npix = sxp * sy;
+            const int bkx0 = xmin >> g.bsl, bky0 = ymin >> g.bsl;
+            const int nbkx = (xmax >> g.bsl) - bkx0 + 1, nbk = nbkx * ((ymax >> g.bsl) - bky0 + 1);
+            int ok = 1, ns = 0, nd = 0;
+            for (int l = 0; l <= g.H; l++) {
+                const int B0 = bmin >> l, A0 = amin >> l;
+                const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
+                const bool in_rect = nB * nA <= LMAX && lane < nB * nA;
+                bool used = false;
+                if (in_rect) {
+                    // node (B, A) covers views [B << l, (B + 1) << l) x [A << l, (A + 1) << l)
+                    const int B = B0 + lane / nA, A = A0 + lane % nA;
+                    const int vb0 = B << l, vb1 = ((B + 1) << l) - 1, va0 = A << l, va1 = ((A + 1) << l) - 1;
+                    for (int q = f; q < f + n && !used; q++) {
+                        const int qa0 = (int)(fbox[q][0] & 0xFFFFu), qb0 = (int)(fbox[q][0] >> 16);
+                        const int qa1 = (int)(fbox[q][1] & 0xFFFFu), qb1 = (int)(fbox[q][1] >> 16);
+                        used = qb0 <= vb1 && qb1 >= vb0 && qa0 <= va1 && qa1 >= va0;
+                    }
+                }
+                const uint64_t bal = __ballot(used);
+                const int cnt = __popcll(bal);
+                if (nB * nA > LMAX) ok = 0;
+                if (lane < LMAX) {
+                    const int idx = used ? __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+                    nodemap[l][lane] = (int8_t)idx;
+                    if (used) nodelist[l][idx] = (uint8_t)lane;
+                }
+                if (lane == 0) {
+                    gp.B0[l] = B0;
+                    gp.A0[l] = A0;
+                    gp.nA[l] = nA;
+                    gp.nused[l] = cnt;
+                    gp.sbase[l] = ns;
+                    if (l < g.H) gp.dbase[l] = nd;
+                }
+                if (l >= 1) ns += 3 * cnt;
+                if (l < g.H) nd += 3 * cnt * nbk;
+            }
+            ok = ok && gp.nused[0] * npix <= B_RGBA && ns * npix <= B_SVAL && nd <= B_DESC && ns <= SLOT_MAX;
+            if (lane == 0) {
+                gp.ok = ok;
+                gp.xq0 = xq0;
+                gp.ymin = ymin;
+                gp.sy = sy;
+                gp.nq = nq;
+                gp.sxp = sxp;
+                gp.npix = npix;
+                gp.bkx0 = bkx0;
+                gp.bky0 = bky0;
+                gp.nbkx = nbkx;
+                gp.nbk = nbk;
+                gp.nslots = ns;
+                gp.ndesc = nd;
+                gp.m_rowq = lf_magic((uint32_t)(sy * nq));
+                gp.m_nq = lf_magic((uint32_t)nq);
+                gp.m_nbk = lf_magic((uint32_t)nbk);
+            }
+        }
+        __syncthreads();
+        if (!gp.ok) {
+            if (n > 1) {
+                n = (n + 1) / 2;  // try half the group
+                __syncthreads();
+                continue;
+            }
+            if (INLINE_FALLBACK) {
+                // one view whose footprint exceeds the budget: per-ray decoding here
+                float o[3];
+                lf_render_one(g, p, cams + 18 * (v0 + f), ii, jj, o);
+                if (live)
+#pragma unroll
+                    for (int c = 0; c < 3; c++) out[((int64_t)(v0 + f) * 3 + c) * npix_out + (int64_t)j * wo + i] = o[c];
+            } else if (threadIdx.x == 0) {
+                // one view whose footprint exceeds the budget: leave a marker for the per-ray pass
+                out[((int64_t)(v0 + f) * 3) * npix_out + (int64_t)(tyi * TH) * wo + txi * TW] =
+                    __uint_as_float(FALLBACK_MARK);
+            }
+            f += 1;
+            n = nf;
+            __syncthreads();
+            continue;
+        }
+        const int npix = gp.npix, sxp = gp.sxp, nq = gp.nq, nbk = gp.nbk, nbkx = gp.nbkx;
+        const int xq0 = gp.xq0, ymin = gp.ymin, bkx0 = gp.bkx0, bky0 = gp.bky0;
+        const int rowq = gp.sy * nq;  // quads per staged plane
+        const uint32_t m_rowq = gp.m_rowq, m_nq = gp.m_nq, m_nbk = gp.m_nbk;
+        // phase 1a: block descriptors of the used nodes of levels 0..H-1, and
+        // the slot table of the staged values (levels 1..H)
+        for (int d = threadIdx.x; d < gp.ndesc; d += NT) {
+            int l = 0;
+            while (l + 1 < g.H && d >= gp.dbase[l + 1]) l++;
+            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // c * nused + u
+            const int kb = d - gp.dbase[l] - row * nbk;
+            const int nu = gp.nused[l];
+            const int c = row / nu, u = row - c * nu;
+            const int e = nodelist[l][u];
+            const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
+            const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
+            desc[d] = lf_make_desc(g, p, c, l, B, A, blk);
+        }
+        for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
+            int l = 1;
+            while (l < g.H && sl >= gp.sbase[l + 1]) l++;
+            const int row = sl - gp.sbase[l];  // c * nused + u
+            const int nu = gp.nused[l];
+            const int c = row / nu, u = row - c * nu;
+            uint32_t info;
+            if (l == g.H) {
+                const int e = nodelist[l][u];
+                const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
+                info = 0x80000000u | (uint32_t)((c * g.root_nb + B) * g.root_na + A);
+            } else {
+                info = (uint32_t)(gp.dbase[l] + row * nbk);
+            }
+            slotinfo[sl] = info;
+        }
+        __syncthreads();
+        // phase 1b: values shared by several views, once per node and pixel quad:
+        // SRVs of levels 1..H-1 and the root RKV (level H)
+        for (int it = threadIdx.x; it < gp.nslots * rowq; it += NT) {
+            const int sl = lf_qdiv(it, m_rowq), rq = it - sl * rowq;
+            const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
+            const int y = ymin + yl, x0 = xq0 + 4 * qi;
+            const uint32_t info = slotinfo[sl];
+            uint2 packed;
+            if (info & 0x80000000u) {
+                packed = *reinterpret_cast<const uint2*>(p.root + (size_t)(info & 0x7FFFFFFFu) * (size_t)(g.w * g.h) +
+                                                         (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
+            } else {
+                const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
+                const Quad q = lf_srv_quad(g, p, desc[info + kb], y, x0, digits);
+                packed.x = ((uint32_t)q.v[0] & 0xFFFFu) | ((uint32_t)q.v[1] << 16);
+                packed.y = ((uint32_t)q.v[2] & 0xFFFFu) | ((uint32_t)q.v[3] << 16);
+            }
+            *reinterpret_cast<uint2*>(sval + (size_t)it * 4) = packed;
+        }
+        __syncthreads();
+        // phase 2: every used (view, pixel quad) sample: level-0 SRV + staged ancestors and root
+        const int nu0 = gp.nused[0];
+        for (int it = threadIdx.x; it < nu0 * rowq; it += NT) {
+            const int u = lf_qdiv(it, m_rowq), rq = it - u * rowq;
+            const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
+            const int e = nodelist[0][u];
+            const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
+            const int y = ymin + yl, x0 = xq0 + 4 * qi;
+            const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
+            Quad ch[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) ch[c] = lf_srv_quad(g, p, desc[__mul24(c * nu0 + u, nbk) + kb], y, x0, digits);
+            for (int l = 1; l <= g.H; l++) {
+                const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
+                const int node = gp.sbase[l] + nodemap[l][el];
+                const int nu = gp.nused[l];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const uint2 s4 = *reinterpret_cast<const uint2*>(sval + (size_t)(__mul24(node + c * nu, rowq) + rq) * 4);
+                    ch[c].v[0] += (int)(int16_t)(s4.x & 0xFFFFu);
+                    ch[c].v[1] += (int)(int16_t)(s4.x >> 16);
+                    ch[c].v[2] += (int)(int16_t)(s4.y & 0xFFFFu);
+                    ch[c].v[3] += (int)(int16_t)(s4.y >> 16);
+                }
+            }
+            uint4 px4;
+            uint32_t* pp = reinterpret_cast<uint32_t*>(&px4);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                int R, G, B;
+                lf_ycocg_to_rgb(ch[0].v[k], ch[1].v[k], ch[2].v[k], R, G, B);
+                pp[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+            }
+            *reinterpret_cast<uint4*>(rgba + (size_t)it * 4) = px4;
+        }
+        __syncthreads();
+        // phase 3: blend every ray of the group's views
+        for (int q = f; q < f + n; q++) {
+            const Ray r = lf_ray_setup(g, cams + 18 * (v0 + q), ii, jj);
+            const int pix = __mul24(r.y0 - ymin, sxp) + (r.x0 - xq0);
+            const int ox = r.x1 - r.x0, oy = __mul24(r.y1 - r.y0, sxp);
+            int vb[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int b = (k & 2) ? r.b1 : r.b0, a = (k & 1) ? r.a1 : r.a0;
+                vb[k] = __mul24(nodemap[0][__mul24(b - gp.B0[0], gp.nA[0]) + (a - gp.A0[0])], npix) + pix;
+            }
+            uint32_t s16[16];
+#pragma unroll
+            for (int k = 0; k < 16; k++) s16[k] = rgba[vb[k >> 2] + ((k & 2) ? oy : 0) + ((k & 1) ? ox : 0)];
+            if (live) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    float sm[16];
+#pragma unroll
+                    for (int k = 0; k < 16; k++) sm[k] = (float)((s16[k] >> (8 * c)) & 255u);
+                    out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, r);
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next group of views
+        f += n;
+        n = nf;
+    }
+}
+

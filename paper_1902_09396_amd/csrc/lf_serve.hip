@@ -1,0 +1,526 @@
+// Serving loop: several compressed light fields resident on the device, view
+// requests of mixed resolution admitted by output memory and request slots,
+// continuously batched into launches of a persistent tile kernel.
+//
+// A request is cut into 32x8 screen tiles.  The scheduler thread keeps up to
+// `max_slots` requests on the device; every launch takes up to `chunk_tiles`
+// tiles from each active request in turn (round robin, so a 2048x2048 view
+// does not hold back a 256x256 one) until `max_tiles` tiles are queued.  Up to
+// `n_streams` launches are in flight at once on separate streams; requests
+// that arrive meanwhile are admitted as soon as a slot and output memory are
+// free, and their tiles join the next launch.  Each launch replays a graph
+// captured once per stream (work-list upload + kernel); the kernel reads the
+// work count from the uploaded list, so the graph never changes.
+//
+// Tiles are rendered by the same routine as lf_render_views (one view per
+// tile), so a request's pixels do not depend on what else is in flight.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lf_render_tile.h"
+
+namespace {
+
+struct ServeSlot {  // device copy, one per request slot
+    float cam[18];
+    int32_t field, wo, ho, tiles_x;
+    uint64_t out_off;  // byte offset of the [3][ho][wo] output in the pool
+};
+
+struct ServeWork {  // one tile of one request
+    int32_t slot, tx, ty;
+};
+
+}  // namespace
+
+__global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ geoms, const LfPtrs* __restrict__ ptrs,
+                                                    const ServeSlot* __restrict__ slots,
+                                                    const int32_t* __restrict__ work /* [0] = count, then items */,
+                                                    uint8_t* __restrict__ pool)
+{
+    TILE_LDS_DECL
+    __shared__ LfGeom sg;
+    __shared__ LfPtrs sp;
+    __shared__ int cur_field;
+    const int n = work[0];
+    const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
+    if (threadIdx.x == 0) cur_field = -1;
+    __syncthreads();
+    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+        const ServeWork it = items[w];
+        const ServeSlot* sl = slots + it.slot;
+        const int field = sl->field;
+        if (field != cur_field) {
+            // stage the light field's geometry in LDS (uniform branch)
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(geoms + field);
+            uint32_t* dst = reinterpret_cast<uint32_t*>(&sg);
+            for (int k = threadIdx.x; k < (int)(sizeof(LfGeom) / 4); k += NT) dst[k] = src[k];
+            if (threadIdx.x == 0) {
+                sp = ptrs[field];
+                cur_field = field;
+            }
+            __syncthreads();
+        }
+        lf_tile_views<true>(sg, sp, sl->cam, 0, 1, sl->wo, sl->ho, it.tx, it.ty,
+                            reinterpret_cast<float*>(pool + sl->out_off), S);
+    }
+}
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    int64_t id;
+    int field, wo, ho;
+    float cam[18];
+    int64_t out_bytes, out_off = -1;
+    int slot = -1;
+    int tiles_x = 0, tiles_total = 0, next_tile = 0, tiles_done = 0;
+    Clock::time_point t_submit, t_done;
+    bool done = false;
+    bool auto_release = false;
+};
+
+// first-fit allocator over [0, size), 256-byte granules
+struct PoolAlloc {
+    std::map<int64_t, int64_t> free_;  // offset -> size
+    explicit PoolAlloc(int64_t size) { free_[0] = size & ~(int64_t)255; }
+    int64_t alloc(int64_t n)
+    {
+        n = (n + 255) & ~(int64_t)255;
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                int64_t off = it->first, rest = it->second - n;
+                free_.erase(it);
+                if (rest) free_[off + n] = rest;
+                return off;
+            }
+        return -1;
+    }
+    void release(int64_t off, int64_t n)
+    {
+        n = (n + 255) & ~(int64_t)255;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct StreamCtx {
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    int32_t* h_work = nullptr;  // pinned: count + items
+    int32_t* d_work = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool busy = false;
+    std::vector<std::pair<int64_t, int>> credits;  // (request id, tiles) of the launch in flight
+};
+
+}  // namespace
+
+struct lf_server {
+    std::vector<LfGeom> geoms;
+    std::vector<LfPtrs> ptrs;
+    LfGeom* d_geoms = nullptr;
+    LfPtrs* d_ptrs = nullptr;
+    ServeSlot* d_slots = nullptr;
+    ServeSlot* h_slots = nullptr;  // pinned staging
+    uint8_t* pool = nullptr;
+    int64_t pool_bytes = 0;
+    lf_server_config cfg{};
+    int grid = 0;
+    std::vector<StreamCtx> streams;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<int64_t> pending;
+    std::unordered_map<int64_t, Request> reqs;
+    std::vector<int64_t> slot_owner;  // request id per slot, -1 free
+    std::vector<int64_t> active;      // admitted, tiles remaining or in flight
+    PoolAlloc alloc{0};
+    int64_t next_id = 1;
+    std::atomic<bool> stop{false};
+    std::thread worker;
+    std::string error;
+    lf_server_stats stats{};
+
+    void run();
+    bool launch(StreamCtx& sc);
+};
+
+static lf_status capture_graph(lf_server* S, StreamCtx& sc)
+{
+    const size_t wbytes = sizeof(int32_t) * (1 + 3 * (size_t)S->cfg.max_tiles);
+    if (hipStreamBeginCapture(sc.s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return lf_fail(LF_EDEVICE, "stream capture failed");
+    hipMemcpyAsync(sc.d_work, sc.h_work, wbytes, hipMemcpyHostToDevice, sc.s);
+    hipLaunchKernelGGL(k_serve_tiles, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs, S->d_slots,
+                       sc.d_work, S->pool);
+    if (hipStreamEndCapture(sc.s, &sc.graph) != hipSuccess) return lf_fail(LF_EDEVICE, "end capture failed");
+    if (hipGraphInstantiate(&sc.exec, sc.graph, nullptr, nullptr, 0) != hipSuccess)
+        return lf_fail(LF_EDEVICE, "graph instantiate failed");
+    return LF_OK;
+}
+
+bool lf_server::launch(StreamCtx& sc)
+{
+    // caller holds mu
+    int n = 0;
+    sc.credits.clear();
+    ServeWork* items = reinterpret_cast<ServeWork*>(sc.h_work + 1);
+    bool progress = true;
+    while (n < cfg.max_tiles && progress) {
+        progress = false;
+        for (int64_t id : active) {
+            Request& r = reqs[id];
+            int take = std::min({cfg.chunk_tiles, r.tiles_total - r.next_tile, cfg.max_tiles - n});
+            if (take <= 0) continue;
+            for (int k = 0; k < take; k++) {
+                const int t = r.next_tile + k;
+                items[n + k] = ServeWork{r.slot, t % r.tiles_x, t / r.tiles_x};
+            }
+            r.next_tile += take;
+            n += take;
+            sc.credits.emplace_back(id, take);
+            progress = true;
+            if (n >= cfg.max_tiles) break;
+        }
+    }
+    if (n == 0) return false;
+    sc.h_work[0] = n;
+    if (cfg.use_graphs) {
+        hipGraphLaunch(sc.exec, sc.s);
+    } else {
+        hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
+        hipLaunchKernelGGL(k_serve_tiles, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs, d_slots,
+                           sc.d_work, pool);
+    }
+    hipEventRecord(sc.ev, sc.s);
+    sc.busy = true;
+    stats.launches++;
+    stats.tiles += n;
+    return true;
+}
+
+void lf_server::run()
+{
+    std::unique_lock<std::mutex> lk(mu);
+    while (!stop.load()) {
+        // completions
+        for (StreamCtx& sc : streams) {
+            if (!sc.busy || hipEventQuery(sc.ev) != hipSuccess) continue;
+            sc.busy = false;
+            const auto now = Clock::now();
+            for (auto& cr : sc.credits) {
+                Request& r = reqs[cr.first];
+                r.tiles_done += cr.second;
+                if (r.tiles_done == r.tiles_total) {
+                    r.done = true;
+                    r.t_done = now;
+                    slot_owner[r.slot] = -1;
+                    active.erase(std::find(active.begin(), active.end(), r.id));
+                    stats.completed++;
+                    if (r.auto_release) {
+                        alloc.release(r.out_off, r.out_bytes);
+                    }
+                }
+            }
+            sc.credits.clear();
+            cv_done.notify_all();
+        }
+        // admission (FIFO: the head waits until it fits)
+        while (!pending.empty()) {
+            Request& r = reqs[pending.front()];
+            int slot = -1;
+            for (int k = 0; k < cfg.max_slots; k++)
+                if (slot_owner[k] < 0) {
+                    slot = k;
+                    break;
+                }
+            if (slot < 0) break;
+            const int64_t off = alloc.alloc(r.out_bytes);
+            if (off < 0) break;
+            r.out_off = off;
+            r.slot = slot;
+            slot_owner[slot] = r.id;
+            ServeSlot& hs = h_slots[slot];
+            memcpy(hs.cam, r.cam, sizeof hs.cam);
+            hs.field = r.field;
+            hs.wo = r.wo;
+            hs.ho = r.ho;
+            hs.tiles_x = r.tiles_x;
+            hs.out_off = (uint64_t)off;
+            // ordered before every launch that uses the slot: all streams wait on it
+            hipMemcpy(d_slots + slot, &hs, sizeof(ServeSlot), hipMemcpyHostToDevice);
+            active.push_back(r.id);
+            pending.pop_front();
+            stats.admitted++;
+        }
+        // new launches on free streams
+        bool launched = false;
+        for (StreamCtx& sc : streams)
+            if (!sc.busy && launch(sc)) launched = true;
+        bool inflight = false;
+        for (StreamCtx& sc : streams) inflight |= sc.busy;
+        if (!launched) {
+            if (inflight) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv_work.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+    }
+}
+
+extern "C" lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields, void* d_pool, int64_t pool_bytes,
+                                      const lf_server_config* cfg, lf_server** out)
+{
+    if (!fields || n_fields < 1 || !d_pool || pool_bytes < 256 || !cfg || !out) return lf_fail(LF_EINVAL, "bad argument");
+    if (cfg->max_slots < 1 || cfg->max_tiles < 1 || cfg->chunk_tiles < 1 || cfg->n_streams < 1 || cfg->n_streams > 4)
+        return lf_fail(LF_EINVAL, "bad server configuration");
+    for (int k = 0; k < n_fields; k++)
+        if (!fields[k] || fields[k]->L.g.bs < 4) return lf_fail(LF_EINVAL, "field %d cannot be served (block size < 4)", k);
+    lf_server* S = new lf_server();
+    S->cfg = *cfg;
+    S->pool = (uint8_t*)d_pool;
+    S->pool_bytes = pool_bytes;
+    S->alloc = PoolAlloc(pool_bytes);
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    S->grid = cfg->grid > 0 ? cfg->grid : 3 * std::max(cus, 1);
+    for (int k = 0; k < n_fields; k++) {
+        S->geoms.push_back(fields[k]->L.g);
+        S->ptrs.push_back(fields[k]->p);
+    }
+    S->slot_owner.assign(cfg->max_slots, -1);
+    bool ok = hipMalloc(&S->d_geoms, sizeof(LfGeom) * n_fields) == hipSuccess &&
+              hipMalloc(&S->d_ptrs, sizeof(LfPtrs) * n_fields) == hipSuccess &&
+              hipMalloc(&S->d_slots, sizeof(ServeSlot) * cfg->max_slots) == hipSuccess &&
+              hipHostMalloc(&S->h_slots, sizeof(ServeSlot) * cfg->max_slots, hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+        hipMemcpy(S->d_geoms, S->geoms.data(), sizeof(LfGeom) * n_fields, hipMemcpyHostToDevice);
+        hipMemcpy(S->d_ptrs, S->ptrs.data(), sizeof(LfPtrs) * n_fields, hipMemcpyHostToDevice);
+    }
+    const size_t wbytes = sizeof(int32_t) * (1 + 3 * (size_t)cfg->max_tiles);
+    S->streams.resize(cfg->n_streams);
+    for (StreamCtx& sc : S->streams) {
+        if (!ok) break;
+        ok = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&sc.ev, hipEventDisableTiming) == hipSuccess &&
+             hipHostMalloc(&sc.h_work, wbytes, hipHostMallocDefault) == hipSuccess &&
+             hipMalloc(&sc.d_work, wbytes) == hipSuccess;
+        if (ok) {
+            memset(sc.h_work, 0, wbytes);
+            if (cfg->use_graphs) ok = capture_graph(S, sc) == LF_OK;
+        }
+    }
+    if (!ok) {
+        lf_server_destroy(S);
+        return lf_fail(LF_EDEVICE, "server setup failed");
+    }
+    S->worker = std::thread([S] { S->run(); });
+    *out = S;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_server_submit(lf_server* S, int32_t field, const float* host_cam, int32_t width,
+                                      int32_t height, int32_t auto_release, int64_t* id)
+{
+    if (!S || !host_cam || !id || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (field < 0 || field >= (int)S->geoms.size()) return lf_fail(LF_EINVAL, "no field %d", field);
+    Request r;
+    r.field = field;
+    r.wo = width;
+    r.ho = height;
+    memcpy(r.cam, host_cam, sizeof r.cam);
+    r.out_bytes = (int64_t)3 * width * height * 4;
+    if (((r.out_bytes + 255) & ~(int64_t)255) > (S->pool_bytes & ~(int64_t)255))
+        return lf_fail(LF_ENOMEM, "output of %lld bytes can never fit the %lld-byte pool", (long long)r.out_bytes,
+                       (long long)S->pool_bytes);
+    r.tiles_x = (width + TW - 1) / TW;
+    r.tiles_total = r.tiles_x * ((height + TH - 1) / TH);
+    r.auto_release = auto_release != 0;
+    r.t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        r.id = S->next_id++;
+        *id = r.id;
+        S->reqs.emplace(r.id, r);
+        S->pending.push_back(r.id);
+        S->stats.submitted++;
+    }
+    S->cv_work.notify_one();
+    return LF_OK;
+}
+
+extern "C" lf_status lf_server_wait(lf_server* S, int64_t id, double timeout_s, int64_t* out_offset, double* latency_ms)
+{
+    if (!S) return lf_fail(LF_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return lf_fail(LF_EINVAL, "unknown request %lld", (long long)id);
+    const auto deadline = Clock::now() + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(timeout_s));
+    while (!S->reqs[id].done)
+        if (S->cv_done.wait_until(lk, deadline) == std::cv_status::timeout && !S->reqs[id].done)
+            return lf_fail(LF_EDEVICE, "request %lld timed out", (long long)id);
+    const Request& r = S->reqs[id];
+    if (out_offset) *out_offset = r.out_off;
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count();
+    return LF_OK;
+}
+
+extern "C" lf_status lf_server_release(lf_server* S, int64_t id)
+{
+    if (!S) return lf_fail(LF_EINVAL, "null server");
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->reqs.find(id);
+        if (it == S->reqs.end() || !it->second.done) return lf_fail(LF_EINVAL, "request %lld is not complete", (long long)id);
+        if (!it->second.auto_release) S->alloc.release(it->second.out_off, it->second.out_bytes);
+        S->reqs.erase(it);
+    }
+    S->cv_work.notify_one();
+    return LF_OK;
+}
+
+extern "C" lf_status lf_server_get_stats(lf_server* S, lf_server_stats* out)
+{
+    if (!S || !out) return lf_fail(LF_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->stats;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_server_destroy(lf_server* S)
+{
+    if (!S) return LF_OK;
+    S->stop = true;
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    for (StreamCtx& sc : S->streams) {
+        if (sc.s) hipStreamSynchronize(sc.s);
+        if (sc.exec) hipGraphExecDestroy(sc.exec);
+        if (sc.graph) hipGraphDestroy(sc.graph);
+        if (sc.ev) hipEventDestroy(sc.ev);
+        if (sc.h_work) hipHostFree(sc.h_work);
+        if (sc.d_work) hipFree(sc.d_work);
+        if (sc.s) hipStreamDestroy(sc.s);
+    }
+    if (S->d_geoms) hipFree(S->d_geoms);
+    if (S->d_ptrs) hipFree(S->d_ptrs);
+    if (S->d_slots) hipFree(S->d_slots);
+    if (S->h_slots) hipHostFree(S->h_slots);
+    delete S;
+    return LF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Open-loop replay of a request schedule, and the one-launch-per-request
+// baseline on the same schedule (both measure latency from arrival).
+// ---------------------------------------------------------------------------
+
+extern "C" lf_status lf_server_replay(lf_server* S, int64_t n, const int32_t* field, const float* cams,
+                                      const int32_t* wh, const double* arrival_s, double* latency_ms,
+                                      double* makespan_s)
+{
+    if (!S || n < 0 || (n > 0 && (!field || !cams || !wh || !arrival_s || !latency_ms))) return lf_fail(LF_EINVAL, "bad argument");
+    std::vector<std::atomic<int64_t>> ids((size_t)n);
+    for (auto& x : ids) x.store(0);
+    std::atomic<int> submit_err{0};
+    const auto t0 = Clock::now();
+    std::thread sub([&] {
+        for (int64_t k = 0; k < n; k++) {
+            std::this_thread::sleep_until(t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[k])));
+            int64_t id = 0;
+            if (lf_server_submit(S, field[k], cams + 18 * k, wh[2 * k], wh[2 * k + 1], 1, &id) != LF_OK) {
+                submit_err = 1;
+                id = -1;
+            }
+            ids[(size_t)k].store(id);
+        }
+    });
+    lf_status st = LF_OK;
+    Clock::time_point last = t0;
+    for (int64_t k = 0; k < n; k++) {
+        int64_t id;
+        while ((id = ids[(size_t)k].load()) == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        if (id < 0) {
+            st = LF_EINVAL;
+            latency_ms[k] = -1.0;
+            continue;
+        }
+        if (lf_server_wait(S, id, 600.0, nullptr, &latency_ms[k]) != LF_OK) st = LF_EDEVICE;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            last = std::max(last, S->reqs[id].t_done);
+        }
+        lf_server_release(S, id);
+    }
+    sub.join();
+    if (makespan_s) *makespan_s = std::chrono::duration<double>(last - t0).count();
+    if (submit_err) return lf_fail(LF_EINVAL, "a request was rejected at submission");
+    return st == LF_OK ? LF_OK : lf_fail(st, "replay failed");
+}
+
+extern "C" lf_status lf_serve_baseline(lf_handle* const* fields, int32_t n_fields, int64_t n, const int32_t* field,
+                                       const float* cams, const int32_t* wh, const double* arrival_s, void* d_out,
+                                       int64_t out_bytes, double* latency_ms, double* makespan_s)
+{
+    if (!fields || n_fields < 1 || n < 0 || !d_out || (n > 0 && (!field || !cams || !wh || !arrival_s || !latency_ms)))
+        return lf_fail(LF_EINVAL, "bad argument");
+    hipStream_t s;
+    float* d_cam = nullptr;
+    float* h_cam = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return lf_fail(LF_EDEVICE, "stream");
+    if (hipMalloc(&d_cam, 18 * sizeof(float)) != hipSuccess || hipHostMalloc(&h_cam, 18 * sizeof(float), 0) != hipSuccess) {
+        hipStreamDestroy(s);
+        return lf_fail(LF_EDEVICE, "baseline buffers");
+    }
+    lf_status st = LF_OK;
+    const auto t0 = Clock::now();
+    Clock::time_point last = t0;
+    for (int64_t k = 0; k < n && st == LF_OK; k++) {
+        const auto arrive = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[k]));
+        std::this_thread::sleep_until(arrive);
+        if (field[k] < 0 || field[k] >= n_fields || (int64_t)3 * wh[2 * k] * wh[2 * k + 1] * 4 > out_bytes) {
+            st = lf_fail(LF_EINVAL, "request %lld does not fit", (long long)k);
+            break;
+        }
+        memcpy(h_cam, cams + 18 * k, 18 * sizeof(float));
+        hipMemcpyAsync(d_cam, h_cam, 18 * sizeof(float), hipMemcpyHostToDevice, s);
+        st = lf_render_views(fields[field[k]], d_cam, 1, wh[2 * k], wh[2 * k + 1], (float*)d_out, s);
+        if (hipStreamSynchronize(s) != hipSuccess) st = lf_fail(LF_EDEVICE, "baseline launch failed");
+        last = Clock::now();
+        latency_ms[k] = std::chrono::duration<double, std::milli>(last - arrive).count();
+    }
+    if (makespan_s) *makespan_s = std::chrono::duration<double>(last - t0).count();
+    hipFree(d_cam);
+    hipHostFree(h_cam);
+    hipStreamDestroy(s);
+    return st;
+}
