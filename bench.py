@@ -32,7 +32,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "render_path512_traffic.json")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lf_geom.h", "lf_render.hip"):
+    for f in ("lf_geom.h", "lf_render_tile.h", "lf_render.hip"):
         with open(os.path.join(ROOT, "paper_1902_09396_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
