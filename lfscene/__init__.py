@@ -18,6 +18,7 @@ from .cameras import (
     camera_path_orbit,
     random_fixed_uv_cameras,
     random_pinhole_cameras,
+    projective_warp,
 )
 from .configs import CONFIGS, get_config, make_views
 
@@ -30,6 +31,7 @@ __all__ = [
     "camera_path_orbit",
     "random_fixed_uv_cameras",
     "random_pinhole_cameras",
+    "projective_warp",
     "CONFIGS",
     "get_config",
     "make_views",

@@ -94,3 +94,19 @@ def random_pinhole_cameras(n: int, na: int, nb: int, w: int, h: int, wo: int, ho
         st = np.array([[win_w / wo, 0.0, ox - 0.5], [0.0, win_h / ho, oy - 0.5], [0.0, 0.0, 1.0]])
         cams.append(pinhole_camera(eu, ev, ez, rho, st))
     return np.stack(cams)
+
+
+def projective_warp(cams: np.ndarray, px: float, py: float) -> np.ndarray:
+    """Compose every camera with the pixel-plane homography ``[[1,0,0],[0,1,0],[px,py,1]]``.
+
+    Both homographies get a non-trivial third row (a tilted image plane), so
+    rays go through the divisions of the projective path.  Keep
+    ``1 + px*i + py*j`` positive over the output image.
+    """
+    P = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [px, py, 1.0]])
+    out = []
+    for c in np.asarray(cams, dtype=np.float64).reshape(-1, 18):
+        h_uv = c[:9].reshape(3, 3) @ P
+        h_st = c[9:].reshape(3, 3) @ P
+        out.append(np.concatenate([h_uv.reshape(-1), h_st.reshape(-1)]))
+    return np.stack(out).astype(np.float32)

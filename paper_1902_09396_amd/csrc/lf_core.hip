@@ -163,13 +163,16 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
             rec += expect;
         }
     L->n_rec = rec;
-    // arena: [root][table][payload][mv][refs], 256-byte aligned
+    // arena: [root][table][payload][mv][refs][status], 256-byte aligned; the
+    // 256-byte status tail also keeps the multi-word loads at the end of the
+    // reference planes inside the arena
     L->a_root = 0;
     L->a_table = align256(L->a_root + (int64_t)L->root_bytes);
     L->a_payload = align256(L->a_table + (int64_t)L->table_bytes);
     L->a_mv = align256(L->a_payload + (int64_t)L->payload_bytes);
     L->a_refs = align256(L->a_mv + (int64_t)L->mv_bytes);
-    L->arena = align256(L->a_refs + 3 * refs * plane * 2);
+    L->a_status = align256(L->a_refs + 3 * refs * plane * 2);
+    L->arena = L->a_status + 256;
     L->stream_bytes = (int64_t)n;
     return LF_OK;
 }
@@ -188,8 +191,14 @@ extern "C" lf_status lf_query_arena(const void* host_stream, size_t nbytes, int6
 // reference planes (Decompression Memory Overhead)
 // ---------------------------------------------------------------------------
 
-__global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs)
+// Reference SRVs must satisfy |v| <= LF_REF_LIMIT: the tile renderer forms
+// 16-weighted prediction sums of them in 16-bit lanes.  SRVs of 8-bit
+// content stay near +-520; a larger value flags the stream as malformed.
+#define LF_REF_LIMIT 2047
+
+__global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int* __restrict__ status)
 {
+    bool bad = false;
     const int64_t plane = (int64_t)g.w * g.h;
     const int64_t total = 3 * (int64_t)g.n_refs * plane;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
@@ -204,8 +213,11 @@ __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs)
         int y = (int)(px / g.w), x = (int)(px % g.w);
         int blk = (y / g.bs) * g.nbx + x / g.bs;
         int i = (y % g.bs) * g.bs + x % g.bs;
-        refs[t] = (int16_t)lf_residual(g, p, c, l, node, blk, i);
+        const int v = lf_residual(g, p, c, l, node, blk, i);
+        bad |= v < -LF_REF_LIMIT || v > LF_REF_LIMIT;
+        refs[t] = (int16_t)v;
     }
+    if (bad) atomicOr(status, 1);
 }
 
 extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
@@ -244,8 +256,14 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
     const int64_t total = 3 * (int64_t)L.g.n_refs * L.g.w * L.g.h;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
+    int* status = (int*)(A + L.a_status);
+    if (hipMemsetAsync(status, 0, 256, s) != hipSuccess) {
+        delete h;
+        return lf_fail(LF_EDEVICE, "status clear failed");
+    }
     if (total > 0) {
-        hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs);
+        hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs,
+                           status);
         st = lf_check_launch("load_refs");
         if (st != LF_OK) {
             delete h;
@@ -253,9 +271,15 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
         }
     }
     // the caller may free host_stream on return: finish the copies
-    if (hipStreamSynchronize(s) != hipSuccess) {
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, status, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
         delete h;
         return lf_fail(LF_EDEVICE, "stream synchronise failed");
+    }
+    if (flag) {
+        delete h;
+        return lf_fail(LF_EFORMAT, "reference residual magnitude above %d", LF_REF_LIMIT);
     }
     *out = h;
     return LF_OK;

@@ -154,60 +154,143 @@ __device__ __forceinline__ uint32_t lf_bise_any(const uint32_t* __restrict__ w, 
     return (hi << b) | lo;
 }
 
+// Packed 16-bit lanes.  Decoded values of a valid stream stay far inside
+// int16 (reference SRVs are checked to |v| <= 2047 at load, so even the
+// 16x-weighted prediction sums fit), so pairs of pixels are carried in one
+// register and added, scaled and shifted two at a time.
+typedef short lf_i16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ lf_i16x2 lf_as_i16x2(uint32_t v) { return __builtin_bit_cast(lf_i16x2, v); }
+__device__ __forceinline__ uint32_t lf_as_u32(lf_i16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ lf_i16x2 lf_splat(int v) { return (lf_i16x2)(short)v; }
+// low halves of a and b as one pair (a in the low half)
+__device__ __forceinline__ uint32_t lf_pack_lo(uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_perm(b, a, 0x05040100u);
+}
+
+// n-bit field at bit o of a 96-bit window (o + n <= 96)
+__device__ __forceinline__ uint32_t lf_win_field(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t o, uint32_t n)
+{
+    const bool c1 = o >= 32u, c2 = o >= 64u;
+    const uint32_t lo = c2 ? w2 : (c1 ? w1 : w0);
+    const uint32_t hi = c1 ? w2 : w1;
+    return __builtin_amdgcn_alignbit(hi, lo, o & 31u) & ((1u << n) - 1u);
+}
+
+// Values i0 .. i0 + 3 of a block (i0 a multiple of 4).  They lie in at most
+// two groups; when those fit in one 96-bit window of the payload (always for
+// b <= 8 bits per value), it is read once and every field is cut from it,
+// else each value is read on its own.
+__device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i0,
+                                             const uint16_t* __restrict__ digits, uint32_t (&v)[4])
+{
+    const uint32_t fam = mode >> 5, b = mode & 31u;
+    const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
+    const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
+    const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
+    const uint32_t gl = hb + gs * b;                             // bits per group
+    const uint32_t g0 = fam == 0u ? i0 : __umulhi(i0, mg);
+    const uint32_t g1 = fam == 0u ? i0 + 3u : __umulhi(i0 + 3u, mg);
+    const uint32_t first = __umul24(g0, gl);
+    const uint32_t wb = first & ~31u;
+    if (__umul24(g1 + 1u, gl) - wb <= 96u) {
+        const uint32_t* q = w + (first >> 5);
+        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
+        const uint32_t tab = fam == 2u ? 256u : 0u;
+        const uint32_t o0 = first - wb, o1 = __umul24(g1, gl) - wb;
+        const uint32_t d0 = digits[tab + lf_win_field(w0, w1, w2, o0, hb)];
+        const uint32_t d1 = digits[tab + lf_win_field(w0, w1, w2, o1, hb)];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const uint32_t i = i0 + (uint32_t)k;
+            const uint32_t gi = fam == 0u ? i : __umulhi(i, mg);
+            const uint32_t kk = i - __umul24(gi, gs);
+            const uint32_t lo = lf_win_field(w0, w1, w2, __umul24(gi, gl) - wb + hb + __umul24(kk, b), b);
+            const uint32_t dig = gi == g0 ? d0 : d1;
+            const uint32_t hi = fam == 2u ? (dig >> (3u * kk)) & 7u : (dig >> (2u * kk)) & 3u;
+            v[k] = (hi << b) | lo;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = lf_bise_any(w, mode, i0 + (uint32_t)k, digits);
+    }
+}
+
 // SRV values at (y, x0 .. x0 + 3) of the node a descriptor belongs to (x0 a
 // multiple of 4, so the quad lies in one block: one descriptor, one motion
-// vector, shared prediction taps and weights).
-struct Quad {
-    int v[4];
-};
-
-__device__ __forceinline__ Quad lf_srv_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
-                                            const uint16_t* __restrict__ digits)
+// vector, shared prediction taps and weights), as two int16 pairs
+// (x = pixels 0, 1; y = pixels 2, 3).
+__device__ __forceinline__ uint2 lf_srv_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
+                                             const uint16_t* __restrict__ digits)
 {
-    Quad r;
     const uint32_t mode = d.z >> 24;
-    if (mode == MODE_PLANE) {
-        // reference node: 4 int16 of its resident plane, 8-byte aligned
-        const uint2 w2 = *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
-        r.v[0] = (int)(int16_t)(w2.x & 0xFFFFu);
-        r.v[1] = (int)(int16_t)(w2.x >> 16);
-        r.v[2] = (int)(int16_t)(w2.y & 0xFFFFu);
-        r.v[3] = (int)(int16_t)(w2.y >> 16);
-        return r;
-    }
-#pragma unroll
-    for (int k = 0; k < 4; k++) r.v[k] = 0;
+    if (mode == MODE_PLANE)  // reference node: 4 int16 of its resident plane, 8-byte aligned
+        return *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
+    lf_i16x2 r01 = lf_splat(0), r23 = lf_splat(0);
     if (mode != LF_MODE_ZERO) {
         const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
-        const int mn = (int)(int16_t)(d.y & 0xFFFFu);
-        const int step = (int)((d.y >> 16) & 0x1FFFu);
-        const uint32_t* w = p.payload + d.x;
-#pragma unroll
-        for (int k = 0; k < 4; k++) r.v[k] = __mul24(mn + (int)lf_bise_any(w, mode, i0 + (uint32_t)k, digits), step);
+        uint32_t v[4];
+        lf_bise_quad(p.payload + d.x, mode, i0, digits, v);
+        const lf_i16x2 mn = lf_splat((int)(int16_t)(d.y & 0xFFFFu));
+        const lf_i16x2 step = lf_splat((int)((d.y >> 16) & 0x1FFFu));
+        r01 = (lf_as_i16x2(lf_pack_lo(v[0], v[1])) + mn) * step;
+        r23 = (lf_as_i16x2(lf_pack_lo(v[2], v[3])) + mn) * step;
     }
     const uint32_t code = d.y >> 29;
     if (code < 2u) {
         const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
-        const int16_t* R = p.refs + d.w;
         const int xb = x0 + (mx >> 2), fx = mx & 3;
         const int Y = 4 * y + my, y0 = Y >> 2, fy = Y & 3;
-        const int ra = __mul24(lf_clampi(y0, 0, g.h - 1), g.w), rb = __mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w);
-        int ta[5], tb[5];
+        // taps t0..t4 of rows y0 and y0 + 1 as pairs (t0,t1) (t1,t2) (t2,t3) (t3,t4)
+        uint32_t A[4], B[4];
+        if (xb >= 0 && xb + 5 <= g.w && y0 >= 0 && y0 + 1 < g.h) {
+            // interior: three aligned words per row hold the five taps
+            const uint32_t e = d.w + (uint32_t)__mul24(y0, g.w) + (uint32_t)xb;
+            const uint32_t* ra = reinterpret_cast<const uint32_t*>(p.refs) + (e >> 1);
+            const uint32_t* rb = reinterpret_cast<const uint32_t*>(p.refs) + ((e + (uint32_t)g.w) >> 1);
+            const uint32_t sh = (e & 1u) << 4;
+            const uint32_t a0 = ra[0], a1 = ra[1], a2 = ra[2], b0 = rb[0], b1 = rb[1], b2 = rb[2];
+            A[0] = __builtin_amdgcn_alignbit(a1, a0, sh);
+            A[2] = __builtin_amdgcn_alignbit(a2, a1, sh);
+            const uint32_t a4 = a2 >> sh;
+            A[1] = __builtin_amdgcn_alignbit(A[2], A[0], 16);
+            A[3] = __builtin_amdgcn_alignbit(a4, A[2], 16);
+            B[0] = __builtin_amdgcn_alignbit(b1, b0, sh);
+            B[2] = __builtin_amdgcn_alignbit(b2, b1, sh);
+            const uint32_t b4 = b2 >> sh;
+            B[1] = __builtin_amdgcn_alignbit(B[2], B[0], 16);
+            B[3] = __builtin_amdgcn_alignbit(b4, B[2], 16);
+        } else {
+            // border: clamped taps one by one
+            const uint16_t* R = reinterpret_cast<const uint16_t*>(p.refs) + d.w;
+            const int ra = __mul24(lf_clampi(y0, 0, g.h - 1), g.w), rb = __mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w);
+            uint32_t ta[5], tb[5];
 #pragma unroll
-        for (int c = 0; c < 5; c++) {
-            const int xc = lf_clampi(xb + c, 0, g.w - 1);
-            ta[c] = R[ra + xc];
-            tb[c] = R[rb + xc];
-        }
+            for (int c = 0; c < 5; c++) {
+                const int xc = lf_clampi(xb + c, 0, g.w - 1);
+                ta[c] = R[ra + xc];
+                tb[c] = R[rb + xc];
+            }
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int top = (4 - fx) * ta[k] + fx * ta[k + 1];
-            const int bot = (4 - fx) * tb[k] + fx * tb[k + 1];
-            const int q = ((4 - fy) * top + fy * bot + 8) >> 4;
-            r.v[k] += code == 0u ? q : -q;
+            for (int c = 0; c < 4; c++) {
+                A[c] = ta[c] | (ta[c + 1] << 16);
+                B[c] = tb[c] | (tb[c + 1] << 16);
+            }
         }
+        const lf_i16x2 wx0 = lf_splat(4 - fx), wx1 = lf_splat(fx), wy0 = lf_splat(4 - fy), wy1 = lf_splat(fy);
+        // (t_k, t_{k+1}) pairs for outputs (0,1) are A[0], A[1]; for (2,3) A[2], A[3]
+        const lf_i16x2 top01 = wx0 * lf_as_i16x2(A[0]) + wx1 * lf_as_i16x2(A[1]);
+        const lf_i16x2 top23 = wx0 * lf_as_i16x2(A[2]) + wx1 * lf_as_i16x2(A[3]);
+        const lf_i16x2 bot01 = wx0 * lf_as_i16x2(B[0]) + wx1 * lf_as_i16x2(B[1]);
+        const lf_i16x2 bot23 = wx0 * lf_as_i16x2(B[2]) + wx1 * lf_as_i16x2(B[3]);
+        const lf_i16x2 q01 = (wy0 * top01 + wy1 * bot01 + lf_splat(8)) >> lf_splat(4);
+        const lf_i16x2 q23 = (wy0 * top23 + wy1 * bot23 + lf_splat(8)) >> lf_splat(4);
+        const lf_i16x2 sg = lf_splat(code == 0u ? 1 : -1);
+        r01 = r01 + sg * q01;
+        r23 = r23 + sg * q23;
     }
-    return r;
+    return make_uint2(lf_as_u32(r01), lf_as_u32(r23));
 }
 
 // floor(n / d) for n, d < 2^16: m = ceil(2^32 / d) for d >= 2 (exact in that
@@ -293,29 +376,72 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
     const bool live = i < wo && j < ho;
     const int ii = live ? i : txi * TW, jj = live ? j : tyi * TH;  // dead lanes repeat the tile origin
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // phase 0: footprint box of every view of the group (packed 16-bit reductions)
+    // phase 0: footprint box of every view of the group (packed 16-bit
+    // min/max of a0|b0<<16, a1|b1<<16, x0|y0<<16, x1|y1<<16).  For an affine
+    // camera (third rows 0 0 1) each computed coordinate is, without
+    // contraction, a product by a constant, a sum and a rounding of monotone
+    // terms, so it is monotone in i for fixed j and in j for fixed i, and so
+    // are the clamp and the floor: the four corner rays of the tile bound
+    // every ray of it.  Four lanes per view compute them; a view whose camera
+    // is not affine (or whose corner coordinates are not finite) reduces
+    // over every pixel of the tile instead.
+    if ((int)threadIdx.x < 4 * nf) {
+        const int f = threadIdx.x >> 2, k = threadIdx.x & 3;
+        const float* cam = cams + 18 * (v0 + f);
+        const int ci = (k & 1) ? min(txi * TW + TW - 1, wo - 1) : txi * TW;
+        const int cj = (k & 2) ? min(tyi * TH + TH - 1, ho - 1) : tyi * TH;
+        float u, v, s, t;
+        lf_ray(cam, ci, cj, u, v, s, t);
+        Ray r;
+        lf_axis(u, g.na, r.a0, r.a1, r.fu);
+        lf_axis(v, g.nb, r.b0, r.b1, r.fv);
+        lf_axis(s, g.w, r.x0, r.x1, r.fs);
+        lf_axis(t, g.h, r.y0, r.y1, r.ft);
+        const bool exact = cam[6] == 0.0f && cam[7] == 0.0f && cam[8] == 1.0f && cam[15] == 0.0f &&
+                           cam[16] == 0.0f && cam[17] == 1.0f && __builtin_isfinite(u) && __builtin_isfinite(v) &&
+                           __builtin_isfinite(s) && __builtin_isfinite(t);
+        uint32_t m0 = (uint32_t)r.a0 | ((uint32_t)r.b0 << 16), m1 = (uint32_t)r.a1 | ((uint32_t)r.b1 << 16);
+        uint32_t m2 = (uint32_t)r.x0 | ((uint32_t)r.y0 << 16), m3 = (uint32_t)r.x1 | ((uint32_t)r.y1 << 16);
+        int all = exact;
+#pragma unroll
+        for (int o = 1; o < 4; o <<= 1) {
+            m0 = pk_min(m0, (uint32_t)__shfl_xor((int)m0, o, 64));
+            m1 = pk_max(m1, (uint32_t)__shfl_xor((int)m1, o, 64));
+            m2 = pk_min(m2, (uint32_t)__shfl_xor((int)m2, o, 64));
+            m3 = pk_max(m3, (uint32_t)__shfl_xor((int)m3, o, 64));
+            all &= __shfl_xor(all, o, 64);
+        }
+        if (k == 0) {
+            fbox[f][0] = all ? m0 : 0xFFFFFFFFu;  // all ones: not bounded by the corners
+            fbox[f][1] = m1;
+            fbox[f][2] = m2;
+            fbox[f][3] = m3;
+        }
+    }
+    __syncthreads();
     for (int f = 0; f < nf; f++) {
+        if (fbox[f][0] != 0xFFFFFFFFu) continue;  // uniform
         const Ray r = lf_ray_setup(g, cams + 18 * (v0 + f), ii, jj);
         const uint32_t m0 = wave_pk_min((uint32_t)r.a0 | ((uint32_t)r.b0 << 16));
         const uint32_t m1 = wave_pk_max((uint32_t)r.a1 | ((uint32_t)r.b1 << 16));
         const uint32_t m2 = wave_pk_min((uint32_t)r.x0 | ((uint32_t)r.y0 << 16));
         const uint32_t m3 = wave_pk_max((uint32_t)r.x1 | ((uint32_t)r.y1 << 16));
         if (lane == 0) {
-            red[(f * 4 + 0) * (NT / 64) + wid] = m0;
-            red[(f * 4 + 1) * (NT / 64) + wid] = m1;
-            red[(f * 4 + 2) * (NT / 64) + wid] = m2;
-            red[(f * 4 + 3) * (NT / 64) + wid] = m3;
+            red[0 * (NT / 64) + wid] = m0;
+            red[1 * (NT / 64) + wid] = m1;
+            red[2 * (NT / 64) + wid] = m2;
+            red[3 * (NT / 64) + wid] = m3;
         }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nf * 4) {
-        const int k = threadIdx.x & 3;
-        uint32_t v = red[threadIdx.x * (NT / 64)];
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            const int k = threadIdx.x;
+            uint32_t v = red[k * (NT / 64)];
 #pragma unroll
-        for (int w = 1; w < NT / 64; w++) v = (k & 1) ? pk_max(v, red[threadIdx.x * (NT / 64) + w]) : pk_min(v, red[threadIdx.x * (NT / 64) + w]);
-        fbox[threadIdx.x >> 2][k] = v;
+            for (int w = 1; w < NT / 64; w++) v = (k & 1) ? pk_max(v, red[k * (NT / 64) + w]) : pk_min(v, red[k * (NT / 64) + w]);
+            fbox[f][k] = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     const int64_t npix_out = (int64_t)wo * ho;
     int f = 0, n = nf;
@@ -465,9 +591,7 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                                                          (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
             } else {
                 const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
-                const Quad q = lf_srv_quad(g, p, desc[info + kb], y, x0, digits);
-                packed.x = ((uint32_t)q.v[0] & 0xFFFFu) | ((uint32_t)q.v[1] << 16);
-                packed.y = ((uint32_t)q.v[2] & 0xFFFFu) | ((uint32_t)q.v[3] << 16);
+                packed = lf_srv_quad(g, p, desc[info + kb], y, x0, digits);
             }
             *reinterpret_cast<uint2*>(sval + (size_t)it * 4) = packed;
         }
@@ -481,9 +605,13 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
             const int y = ymin + yl, x0 = xq0 + 4 * qi;
             const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
-            Quad ch[3];
+            lf_i16x2 ch[3][2];
 #pragma unroll
-            for (int c = 0; c < 3; c++) ch[c] = lf_srv_quad(g, p, desc[__mul24(c * nu0 + u, nbk) + kb], y, x0, digits);
+            for (int c = 0; c < 3; c++) {
+                const uint2 q = lf_srv_quad(g, p, desc[__mul24(c * nu0 + u, nbk) + kb], y, x0, digits);
+                ch[c][0] = lf_as_i16x2(q.x);
+                ch[c][1] = lf_as_i16x2(q.y);
+            }
             for (int l = 1; l <= g.H; l++) {
                 const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
                 const int node = gp.sbase[l] + nodemap[l][el];
@@ -491,19 +619,34 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     const uint2 s4 = *reinterpret_cast<const uint2*>(sval + (size_t)(__mul24(node + c * nu, rowq) + rq) * 4);
-                    ch[c].v[0] += (int)(int16_t)(s4.x & 0xFFFFu);
-                    ch[c].v[1] += (int)(int16_t)(s4.x >> 16);
-                    ch[c].v[2] += (int)(int16_t)(s4.y & 0xFFFFu);
-                    ch[c].v[3] += (int)(int16_t)(s4.y >> 16);
+                    ch[c][0] += lf_as_i16x2(s4.x);
+                    ch[c][1] += lf_as_i16x2(s4.y);
                 }
             }
+            // inverse YCoCg-R on pixel pairs, clamped to [0, 255], packed as RGBA8
             uint4 px4;
-            uint32_t* pp = reinterpret_cast<uint32_t*>(&px4);
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                int R, G, B;
-                lf_ycocg_to_rgb(ch[0].v[k], ch[1].v[k], ch[2].v[k], R, G, B);
-                pp[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+            for (int h = 0; h < 2; h++) {
+                const lf_i16x2 Yv = ch[0][h], Co = ch[1][h], Cg = ch[2][h];
+                const lf_i16x2 t = Yv - (Cg >> lf_splat(1));
+                const lf_i16x2 G = Cg + t;
+                const lf_i16x2 Bv = t - (Co >> lf_splat(1));
+                const lf_i16x2 R = Bv + Co;
+                const lf_i16x2 z = lf_splat(0), m = lf_splat(255);
+                const uint32_t r2 = lf_as_u32(__builtin_elementwise_min(__builtin_elementwise_max(R, z), m));
+                const uint32_t g2 = lf_as_u32(__builtin_elementwise_min(__builtin_elementwise_max(G, z), m));
+                const uint32_t b2 = lf_as_u32(__builtin_elementwise_min(__builtin_elementwise_max(Bv, z), m));
+                const uint32_t rg = r2 | (g2 << 8);  // bytes R0 G0 R1 G1
+                // pixel 2h: R0 G0 B0 0; pixel 2h+1: R1 G1 B1 0
+                const uint32_t p0 = __builtin_amdgcn_perm(b2, rg, 0x0C040100u);
+                const uint32_t p1 = __builtin_amdgcn_perm(b2, rg, 0x0C060302u);
+                if (h == 0) {
+                    px4.x = p0;
+                    px4.y = p1;
+                } else {
+                    px4.z = p0;
+                    px4.w = p1;
+                }
             }
             *reinterpret_cast<uint4*>(rgba + (size_t)it * 4) = px4;
         }

@@ -149,6 +149,45 @@ def test_tiled_equals_per_ray(torch_mod, lfmod, mid_stream, tiny_stream, tiny_ca
     assert np.array_equal(a, b)
 
 
+def test_render_projective_cameras(torch_mod, lfmod, tiny_stream, tiny_oracle, tiny_cams_ez, mid_stream):
+    """Cameras with a tilted image plane: the footprint boxes come from every
+    pixel of a tile instead of its four corners."""
+    torch = torch_mod
+    cams = lfscene.projective_warp(tiny_cams_ez, 2e-3, -3e-3)
+    assert np.all(cams[:, 8] == 1.0) and np.any(cams[:, 6] != 0.0)
+    L = lfmod.LightField(tiny_stream)
+    got = L.render_views(_cams_dev(torch, cams), 64, 64).cpu().numpy().astype(np.float64)
+    expect = tiny_oracle.render(cams, 64, 64)
+    assert np.abs(got - expect).max() <= RENDER_TOL
+    # mixed group: affine and projective views in one launch, tiled = per-ray
+    M = lfmod.LightField(mid_stream)
+    orbit = lfscene.camera_path_orbit(8, 17, 17, 128, 128, 100, 70)
+    mixed = orbit.copy()
+    mixed[1::2] = lfscene.projective_warp(orbit[1::2], 1e-3, 2e-3)
+    a = M.render_views(_cams_dev(torch, mixed), 100, 70).cpu().numpy()
+    b = M.render_views(_cams_dev(torch, mixed), 100, 70, per_ray=True).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_load_rejects_large_reference_values(torch_mod, lfmod, tiny_stream):
+    """A reference SRV beyond +-2047 (impossible for 8-bit content) is a format error."""
+    table_off = int(np.frombuffer(tiny_stream[128:136].tobytes(), np.uint64)[0])
+    bad = tiny_stream.copy()
+    # BFS node 0 is the (0, 0) reference node of level H-1; raise the minimum of
+    # its first significant block of channel 0
+    for e in range(64):
+        o = table_off + 8 * e
+        if bad[o + 6] != 0xFF:
+            bad[o + 4:o + 6] = np.frombuffer(np.int16(2000).tobytes(), np.uint8)
+            break
+    else:
+        pytest.skip("no significant reference block in node 0")
+    with pytest.raises(lfmod.LFError) as e:
+        lfmod.LightField(bad)
+    assert e.value.status == lfmod.LF_EFORMAT
+    lfmod.LightField(tiny_stream)  # the unmodified stream still loads
+
+
 def test_render_deterministic(torch_mod, lfmod, mid_stream):
     torch = torch_mod
     cams = _cams_dev(torch, lfscene.camera_path_orbit(8, 17, 17, 128, 128, 96, 80))
