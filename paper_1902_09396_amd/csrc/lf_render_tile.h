@@ -134,24 +134,53 @@ __device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, 
 // Bounded-integer value i of a block, one code path for the three families
 // (no divergence between neighbouring blocks of different families): a value
 // is (high digit << b) | b-bit low part, where the group of G values (G = 1,
-// 5 or 3) starts with an hb-bit header (hb = 0, 8 or 7) whose digit k is read
-// from a table: digits[t] packs the base-3 digits of t (2 bits each) and
-// digits[256 + q] the base-5 digits of q (3 bits each); digits[0] = 0.
+// 5 or 3) starts with an hb-bit header (hb = 0, 8 or 7).  Table entries
+// tab[t] hold the base-3 digits of t and tab[256 + q] the base-5 digits of q,
+// one per 4-bit nibble (tab[0] = 0, so the empty header of plain bits reads
+// digit 0); tab[LF_TAB_QUAD + 5 fam + r] describes a quad (below).
+#define LF_TAB_QUAD 384
+#define LF_TAB_SIZE (LF_TAB_QUAD + 15)
+
 __device__ __forceinline__ uint32_t lf_bise_any(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i,
-                                                const uint16_t* __restrict__ digits)
+                                                const uint32_t* __restrict__ tab)
 {
     const uint32_t fam = mode >> 5, b = mode & 31u;
     const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
     const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
     const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
     const uint32_t grp = fam == 0u ? i : __umulhi(i, mg);
-    const uint32_t k = i - grp * gs;
+    const uint32_t k = i - __umul24(grp, gs);
     const uint32_t base = __umul24(grp, hb + gs * b);
     const uint32_t head = lf_field(w, base, (int)hb);
     const uint32_t lo = lf_field(w, base + hb + __umul24(k, b), (int)b);
-    const uint32_t dig = digits[(fam == 2u ? 256u : 0u) + head];
-    const uint32_t hi = fam == 2u ? (dig >> (3u * k)) & 7u : (dig >> (2u * k)) & 3u;
-    return (hi << b) | lo;
+    const uint32_t dig = tab[(fam == 2u ? 256u : 0u) + head];
+    return (((dig >> (4u * k)) & 15u) << b) | lo;
+}
+
+// Fill the shared decode table (every thread of the workgroup calls it).
+__device__ __forceinline__ void lf_fill_tab(uint32_t* tab)
+{
+    for (uint32_t t = threadIdx.x; t < LF_TAB_SIZE; t += blockDim.x) {
+        uint32_t d = 0;
+        if (t < 256u) {
+            uint32_t v = t;
+            for (int k = 0; k < 5; k++, v /= 3u) d |= (v % 3u) << (4 * k);
+        } else if (t < LF_TAB_QUAD) {
+            uint32_t v = t - 256u;
+            for (int k = 0; k < 3; k++, v /= 5u) d |= (v % 5u) << (4 * k);
+        } else {
+            // quad starting at position r of its group, family fam: for value
+            // k, 5 bits = group step from the quad's first group (2) | digit
+            // index inside the group (3) << 2
+            const uint32_t fam = (t - LF_TAB_QUAD) / 5u, r = (t - LF_TAB_QUAD) % 5u;
+            const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t q = (fam == 0u ? 0u : r) + k;
+                d |= ((q / gs) | ((q % gs) << 2)) << (5 * k);
+            }
+        }
+        tab[t] = d;
+    }
 }
 
 // Packed 16-bit lanes.  Decoded values of a valid stream stay far inside
@@ -179,11 +208,11 @@ __device__ __forceinline__ uint32_t lf_win_field(uint32_t w0, uint32_t w1, uint3
 }
 
 // Values i0 .. i0 + 3 of a block (i0 a multiple of 4).  They lie in at most
-// two groups; when those fit in one 96-bit window of the payload (always for
-// b <= 8 bits per value), it is read once and every field is cut from it,
-// else each value is read on its own.
+// two groups (plain bits: four one-value groups); when those fit in one
+// 96-bit window of the payload (always for b <= 8 bits per value), it is read
+// once and every field is cut from it, else each value is read on its own.
 __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i0,
-                                             const uint16_t* __restrict__ digits, uint32_t (&v)[4])
+                                             const uint32_t* __restrict__ tab, uint32_t (&v)[4])
 {
     const uint32_t fam = mode >> 5, b = mode & 31u;
     const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
@@ -191,29 +220,27 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
     const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
     const uint32_t gl = hb + gs * b;                             // bits per group
     const uint32_t g0 = fam == 0u ? i0 : __umulhi(i0, mg);
-    const uint32_t g1 = fam == 0u ? i0 + 3u : __umulhi(i0 + 3u, mg);
+    const uint32_t pat = tab[LF_TAB_QUAD + 5u * fam + (i0 - __umul24(g0, gs))];
     const uint32_t first = __umul24(g0, gl);
     const uint32_t wb = first & ~31u;
-    if (__umul24(g1 + 1u, gl) - wb <= 96u) {
+    const uint32_t o0 = first - wb;
+    if (o0 + __umul24(((pat >> 15) & 3u) + 1u, gl) <= 96u) {  // end of the last value's group
         const uint32_t* q = w + (first >> 5);
         const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
-        const uint32_t tab = fam == 2u ? 256u : 0u;
-        const uint32_t o0 = first - wb, o1 = __umul24(g1, gl) - wb;
-        const uint32_t d0 = digits[tab + lf_win_field(w0, w1, w2, o0, hb)];
-        const uint32_t d1 = digits[tab + lf_win_field(w0, w1, w2, o1, hb)];
+        const uint32_t tb = fam == 2u ? 256u : 0u;
+        const uint32_t d0 = tab[tb + lf_win_field(w0, w1, w2, o0, hb)];
+        const uint32_t d1 = tab[tb + lf_win_field(w0, w1, w2, o0 + gl, hb)];
+        const uint32_t base = o0 + hb;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const uint32_t i = i0 + (uint32_t)k;
-            const uint32_t gi = fam == 0u ? i : __umulhi(i, mg);
-            const uint32_t kk = i - __umul24(gi, gs);
-            const uint32_t lo = lf_win_field(w0, w1, w2, __umul24(gi, gl) - wb + hb + __umul24(kk, b), b);
-            const uint32_t dig = gi == g0 ? d0 : d1;
-            const uint32_t hi = fam == 2u ? (dig >> (3u * kk)) & 7u : (dig >> (2u * kk)) & 3u;
-            v[k] = (hi << b) | lo;
+            const uint32_t dk = (pat >> (5 * k)) & 3u, kk = (pat >> (5 * k + 2)) & 7u;
+            const uint32_t lo = lf_win_field(w0, w1, w2, base + __umul24(dk, gl) + __umul24(kk, b), b);
+            const uint32_t dig = dk != 0u ? d1 : d0;
+            v[k] = (((dig >> (4u * kk)) & 15u) << b) | lo;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = lf_bise_any(w, mode, i0 + (uint32_t)k, digits);
+        for (int k = 0; k < 4; k++) v[k] = lf_bise_any(w, mode, i0 + (uint32_t)k, tab);
     }
 }
 
@@ -222,7 +249,7 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
 // vector, shared prediction taps and weights), as two int16 pairs
 // (x = pixels 0, 1; y = pixels 2, 3).
 __device__ __forceinline__ uint2 lf_srv_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
-                                             const uint16_t* __restrict__ digits)
+                                             const uint32_t* __restrict__ digits)
 {
     const uint32_t mode = d.z >> 24;
     if (mode == MODE_PLANE)  // reference node: 4 int16 of its resident plane, 8-byte aligned
@@ -297,7 +324,7 @@ __device__ __forceinline__ uint2 lf_srv_quad(const LfGeom& g, const LfPtrs& p, u
 // range); d = 1 would need m = 2^32, so it is encoded as m = 0 (identity)
 __device__ __forceinline__ uint32_t lf_magic(uint32_t d)
 {
-    return d <= 1u ? 0u : (uint32_t)((0x100000000ull + d - 1) / d);
+    return d <= 1u ? 0u : 0xFFFFFFFFu / d + 1u;  // ceil(2^32 / d), also for powers of two
 }
 __device__ __forceinline__ int lf_qdiv(int n, uint32_t m) { return m ? (int)__umulhi((uint32_t)n, m) : n; }
 
@@ -311,8 +338,8 @@ struct GroupPlan {
     int bkx0, bky0, nbkx, nbk;
     int B0[LF_MAX_LEVELS + 1], A0[LF_MAX_LEVELS + 1], nA[LF_MAX_LEVELS + 1];
     int nused[LF_MAX_LEVELS + 1];
-    int sbase[LF_MAX_LEVELS + 1];  // first staged slot of each level (levels 1..H)
-    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (levels 0..H-1)
+    int sbase[LF_MAX_LEVELS + 1];  // first staged slot of each level (levels 1..H); slot = sbase + 3 u + c
+    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (levels 0..H-1); + (3 u + c) nbk + block
     int nslots, ndesc;
     uint32_t m_rowq, m_nq, m_nbk;  // reciprocals of sy * nq, nq and nbk
 };
@@ -328,8 +355,9 @@ struct TileLds {
     GroupPlan* gpp;
     int8_t (*nodemap)[LMAX];
     uint8_t (*nodelist)[LMAX];
+    uint8_t (*ancs)[LF_MAX_LEVELS];  // per used leaf view: staged slot (channel 0) of its ancestor at level 1 + k
     uint32_t* slotinfo;
-    const uint16_t* digits;
+    const uint32_t* digits;  // decode table (lf_fill_tab)
 };
 
 #define TILE_LDS_DECL                                                                            \
@@ -338,20 +366,14 @@ struct TileLds {
     __shared__ GroupPlan gp_s;                                                                   \
     __shared__ int8_t nodemap_s[LF_MAX_LEVELS + 1][LMAX];                                        \
     __shared__ uint8_t nodelist_s[LF_MAX_LEVELS + 1][LMAX];                                      \
+    __shared__ __align__(8) uint8_t ancs_s[LMAX][LF_MAX_LEVELS];                                 \
     __shared__ uint32_t slotinfo_s[SLOT_MAX];                                                    \
-    __shared__ uint16_t digits_s[384];                                                           \
+    __shared__ uint32_t digits_s[LF_TAB_SIZE];                                                   \
     const TileLds S{lds_dyn,                                                                     \
                     reinterpret_cast<uint32_t*>(lds_dyn + B_DESC),                               \
                     reinterpret_cast<int16_t*>(reinterpret_cast<uint32_t*>(lds_dyn + B_DESC) + B_RGBA), \
-                    fbox_s, &gp_s, nodemap_s, nodelist_s, slotinfo_s, digits_s};                 \
-    for (uint32_t t = threadIdx.x; t < 384u; t += NT) {                                         \
-        uint32_t d = 0, v = t < 256u ? t : t - 256u;                                             \
-        if (t < 256u)                                                                            \
-            for (int k = 0; k < 5; k++, v /= 3u) d |= (v % 3u) << (2 * k);                       \
-        else                                                                                     \
-            for (int k = 0; k < 3; k++, v /= 5u) d |= (v % 5u) << (3 * k);                       \
-        digits_s[t] = (uint16_t)d;                                                               \
-    }                                                                                            \
+                    fbox_s, &gp_s, nodemap_s, nodelist_s, ancs_s, slotinfo_s, digits_s};                 \
+    lf_fill_tab(digits_s);                                                                       \
     __syncthreads();
 
 // Render screen tile (txi, tyi) of views v0 .. v0 + nf - 1 (cameras cams[v],
@@ -369,8 +391,9 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
     GroupPlan& gp = *S.gpp;
     int8_t (*nodemap)[LMAX] = S.nodemap;
     uint8_t (*nodelist)[LMAX] = S.nodelist;
+    uint8_t (*ancs)[LF_MAX_LEVELS] = S.ancs;
     uint32_t* slotinfo = S.slotinfo;
-    const uint16_t* digits = S.digits;
+    const uint32_t* digits = S.digits;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int i = txi * TW + lx, j = tyi * TH + ly;
     const bool live = i < wo && j < ho;
@@ -552,10 +575,9 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         for (int d = threadIdx.x; d < gp.ndesc; d += NT) {
             int l = 0;
             while (l + 1 < g.H && d >= gp.dbase[l + 1]) l++;
-            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // c * nused + u
+            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // 3 u + c
             const int kb = d - gp.dbase[l] - row * nbk;
-            const int nu = gp.nused[l];
-            const int c = row / nu, u = row - c * nu;
+            const int u = row / 3, c = row - 3 * u;
             const int e = nodelist[l][u];
             const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
             const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
@@ -564,9 +586,8 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
             int l = 1;
             while (l < g.H && sl >= gp.sbase[l + 1]) l++;
-            const int row = sl - gp.sbase[l];  // c * nused + u
-            const int nu = gp.nused[l];
-            const int c = row / nu, u = row - c * nu;
+            const int row = sl - gp.sbase[l];  // 3 u + c
+            const int u = row / 3, c = row - 3 * u;
             uint32_t info;
             if (l == g.H) {
                 const int e = nodelist[l][u];
@@ -576,6 +597,14 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 info = (uint32_t)(gp.dbase[l] + row * nbk);
             }
             slotinfo[sl] = info;
+        }
+        for (int u = threadIdx.x; u < gp.nused[0]; u += NT) {
+            const int e = nodelist[0][u];
+            const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
+            for (int l = 1; l <= g.H; l++) {
+                const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
+                ancs[u][l - 1] = (uint8_t)(gp.sbase[l] + 3 * nodemap[l][el]);
+            }
         }
         __syncthreads();
         // phase 1b: values shared by several views, once per node and pixel quad:
@@ -601,24 +630,23 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         for (int it = threadIdx.x; it < nu0 * rowq; it += NT) {
             const int u = lf_qdiv(it, m_rowq), rq = it - u * rowq;
             const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
-            const int e = nodelist[0][u];
-            const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
             const int y = ymin + yl, x0 = xq0 + 4 * qi;
             const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
+            const uint4* dq = desc + __mul24(3 * u, nbk) + kb;
             lf_i16x2 ch[3][2];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const uint2 q = lf_srv_quad(g, p, desc[__mul24(c * nu0 + u, nbk) + kb], y, x0, digits);
+                const uint2 q = lf_srv_quad(g, p, dq[c * nbk], y, x0, digits);
                 ch[c][0] = lf_as_i16x2(q.x);
                 ch[c][1] = lf_as_i16x2(q.y);
             }
+            const uint2 an = *reinterpret_cast<const uint2*>(ancs[u]);
             for (int l = 1; l <= g.H; l++) {
-                const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
-                const int node = gp.sbase[l] + nodemap[l][el];
-                const int nu = gp.nused[l];
+                const uint32_t sl = ((l <= 4 ? an.x : an.y) >> (8 * ((l - 1) & 3))) & 0xFFu;
+                const uint2* sv = reinterpret_cast<const uint2*>(sval) + __mul24(sl, rowq) + rq;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    const uint2 s4 = *reinterpret_cast<const uint2*>(sval + (size_t)(__mul24(node + c * nu, rowq) + rq) * 4);
+                    const uint2 s4 = sv[c * rowq];
                     ch[c][0] += lf_as_i16x2(s4.x);
                     ch[c][1] += lf_as_i16x2(s4.y);
                 }
@@ -654,17 +682,20 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         // phase 3: blend every ray of the group's views
         for (int q = f; q < f + n; q++) {
             const Ray r = lf_ray_setup(g, cams + 18 * (v0 + q), ii, jj);
+            // x1 = x0 + 1 and y1 = y0 + 1: the captured views are at least one
+            // 4-pixel block wide and high on this path
             const int pix = __mul24(r.y0 - ymin, sxp) + (r.x0 - xq0);
-            const int ox = r.x1 - r.x0, oy = __mul24(r.y1 - r.y0, sxp);
-            int vb[4];
+            uint32_t s16[16];
 #pragma unroll
             for (int k = 0; k < 4; k++) {
                 const int b = (k & 2) ? r.b1 : r.b0, a = (k & 1) ? r.a1 : r.a0;
-                vb[k] = __mul24(nodemap[0][__mul24(b - gp.B0[0], gp.nA[0]) + (a - gp.A0[0])], npix) + pix;
+                const uint32_t* q0 = rgba + __mul24(nodemap[0][__mul24(b - gp.B0[0], gp.nA[0]) + (a - gp.A0[0])], npix) + pix;
+                const uint32_t* q1 = q0 + sxp;
+                s16[4 * k + 0] = q0[0];
+                s16[4 * k + 1] = q0[1];
+                s16[4 * k + 2] = q1[0];
+                s16[4 * k + 3] = q1[1];
             }
-            uint32_t s16[16];
-#pragma unroll
-            for (int k = 0; k < 16; k++) s16[k] = rgba[vb[k >> 2] + ((k & 2) ? oy : 0) + ((k & 1) ? ox : 0)];
             if (live) {
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
