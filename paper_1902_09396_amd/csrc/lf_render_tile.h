@@ -125,9 +125,10 @@ __device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, 
     const uint2 e = p.table[((size_t)c * g.n_nodes + node) * g.nblk + blk];
     int mx, my, sg;
     lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
-    const uint32_t mode = (e.y >> 16) & 0xFFu;
+    uint32_t mode = (e.y >> 16) & 0xFFu, word = e.x, mn = e.y & 0xFFFFu;
+    if (mode == LF_MODE_ZERO) mode = word = mn = 0u;  // insignificant: zero-bit values, minimum 0
     const uint32_t code = sg == 1 ? 0u : (sg == -1 ? 1u : 2u);
-    return make_uint4(e.x, (e.y & 0xFFFFu) | ((uint32_t)g.step[l] << 16) | (code << 29),
+    return make_uint4(word, mn | ((uint32_t)g.step[l] << 16) | (code << 29),
                       ((uint32_t)mx & 0xFFFu) | (((uint32_t)my & 0xFFFu) << 12) | (mode << 24), ref);
 }
 
@@ -224,9 +225,9 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
     const uint32_t first = __umul24(g0, gl);
     const uint32_t wb = first & ~31u;
     const uint32_t o0 = first - wb;
+    const uint32_t* q = w + (first >> 5);
+    const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
     if (o0 + __umul24(((pat >> 15) & 3u) + 1u, gl) <= 96u) {  // end of the last value's group
-        const uint32_t* q = w + (first >> 5);
-        const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
         const uint32_t tb = fam == 2u ? 256u : 0u;
         const uint32_t d0 = tab[tb + lf_win_field(w0, w1, w2, o0, hb)];
         const uint32_t d1 = tab[tb + lf_win_field(w0, w1, w2, o0 + gl, hb)];
@@ -248,76 +249,76 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
 // multiple of 4, so the quad lies in one block: one descriptor, one motion
 // vector, shared prediction taps and weights), as two int16 pairs
 // (x = pixels 0, 1; y = pixels 2, 3).
-__device__ __forceinline__ uint2 lf_srv_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
-                                             const uint32_t* __restrict__ digits)
+//
+// Reference node: 4 int16 of its resident plane, 8-byte aligned.
+__device__ __forceinline__ uint2 lf_ref_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0)
+{
+    return *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
+}
+
+// Predictive node: residual plus the signed quarter-pel prediction.  Every
+// load is unconditional (an insignificant block reads zero-bit values, a
+// block without prediction reads taps it then weighs by 0), so the loads of
+// several calls can be issued together.
+__device__ __forceinline__ uint2 lf_pred_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
+                                              const uint32_t* __restrict__ digits)
 {
     const uint32_t mode = d.z >> 24;
-    if (mode == MODE_PLANE)  // reference node: 4 int16 of its resident plane, 8-byte aligned
-        return *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
-    lf_i16x2 r01 = lf_splat(0), r23 = lf_splat(0);
-    if (mode != LF_MODE_ZERO) {
-        const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
-        uint32_t v[4];
-        lf_bise_quad(p.payload + d.x, mode, i0, digits, v);
-        const lf_i16x2 mn = lf_splat((int)(int16_t)(d.y & 0xFFFFu));
-        const lf_i16x2 step = lf_splat((int)((d.y >> 16) & 0x1FFFu));
-        r01 = (lf_as_i16x2(lf_pack_lo(v[0], v[1])) + mn) * step;
-        r23 = (lf_as_i16x2(lf_pack_lo(v[2], v[3])) + mn) * step;
-    }
+    const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
+    uint32_t v[4];
+    lf_bise_quad(p.payload + d.x, mode, i0, digits, v);
+    const lf_i16x2 mn = lf_splat((int)(int16_t)(d.y & 0xFFFFu));
+    const lf_i16x2 step = lf_splat((int)((d.y >> 16) & 0x1FFFu));
+    const lf_i16x2 r01 = (lf_as_i16x2(lf_pack_lo(v[0], v[1])) + mn) * step;
+    const lf_i16x2 r23 = (lf_as_i16x2(lf_pack_lo(v[2], v[3])) + mn) * step;
     const uint32_t code = d.y >> 29;
-    if (code < 2u) {
-        const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
-        const int xb = x0 + (mx >> 2), fx = mx & 3;
-        const int Y = 4 * y + my, y0 = Y >> 2, fy = Y & 3;
-        // taps t0..t4 of rows y0 and y0 + 1 as pairs (t0,t1) (t1,t2) (t2,t3) (t3,t4)
-        uint32_t A[4], B[4];
-        if (xb >= 0 && xb + 5 <= g.w && y0 >= 0 && y0 + 1 < g.h) {
-            // interior: three aligned words per row hold the five taps
-            const uint32_t e = d.w + (uint32_t)__mul24(y0, g.w) + (uint32_t)xb;
-            const uint32_t* ra = reinterpret_cast<const uint32_t*>(p.refs) + (e >> 1);
-            const uint32_t* rb = reinterpret_cast<const uint32_t*>(p.refs) + ((e + (uint32_t)g.w) >> 1);
-            const uint32_t sh = (e & 1u) << 4;
-            const uint32_t a0 = ra[0], a1 = ra[1], a2 = ra[2], b0 = rb[0], b1 = rb[1], b2 = rb[2];
-            A[0] = __builtin_amdgcn_alignbit(a1, a0, sh);
-            A[2] = __builtin_amdgcn_alignbit(a2, a1, sh);
-            const uint32_t a4 = a2 >> sh;
-            A[1] = __builtin_amdgcn_alignbit(A[2], A[0], 16);
-            A[3] = __builtin_amdgcn_alignbit(a4, A[2], 16);
-            B[0] = __builtin_amdgcn_alignbit(b1, b0, sh);
-            B[2] = __builtin_amdgcn_alignbit(b2, b1, sh);
-            const uint32_t b4 = b2 >> sh;
-            B[1] = __builtin_amdgcn_alignbit(B[2], B[0], 16);
-            B[3] = __builtin_amdgcn_alignbit(b4, B[2], 16);
-        } else {
-            // border: clamped taps one by one
-            const uint16_t* R = reinterpret_cast<const uint16_t*>(p.refs) + d.w;
-            const int ra = __mul24(lf_clampi(y0, 0, g.h - 1), g.w), rb = __mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w);
-            uint32_t ta[5], tb[5];
+    const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
+    const int xb = x0 + (mx >> 2), fx = mx & 3;
+    const int Y = 4 * y + my, y0 = Y >> 2, fy = Y & 3;
+    // five taps from xb in rows y0, y0 + 1 (clamped): read the aligned words
+    // holding columns xs .. xs + 4, xs = xb clamped into the row
+    const int xs = max(min(xb, g.w - 5), 0);
+    const uint32_t ea = d.w + (uint32_t)__mul24(lf_clampi(y0, 0, g.h - 1), g.w) + (uint32_t)xs;
+    const uint32_t eb = d.w + (uint32_t)__mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w) + (uint32_t)xs;
+    const uint32_t* ra = reinterpret_cast<const uint32_t*>(p.refs) + (ea >> 1);
+    const uint32_t* rb = reinterpret_cast<const uint32_t*>(p.refs) + (eb >> 1);
+    const uint32_t a0 = ra[0], a1 = ra[1], a2 = ra[2], b0 = rb[0], b1 = rb[1], b2 = rb[2];
+    const uint32_t sh = (ea & 1u) << 4;  // the width is a multiple of 4: both rows share the parity
+    // pairs (t0,t1) (t1,t2) (t2,t3) (t3,t4) of each row
+    uint32_t A[4], B[4];
+    A[0] = __builtin_amdgcn_alignbit(a1, a0, sh);
+    A[2] = __builtin_amdgcn_alignbit(a2, a1, sh);
+    A[1] = __builtin_amdgcn_alignbit(A[2], A[0], 16);
+    A[3] = __builtin_amdgcn_alignbit(a2 >> sh, A[2], 16);
+    B[0] = __builtin_amdgcn_alignbit(b1, b0, sh);
+    B[2] = __builtin_amdgcn_alignbit(b2, b1, sh);
+    B[1] = __builtin_amdgcn_alignbit(B[2], B[0], 16);
+    B[3] = __builtin_amdgcn_alignbit(b2 >> sh, B[2], 16);
+    if (xs != xb) {
+        // image border: tap c is column clamp(xb + c) = xs + k of the window
+        uint32_t ta[5], tb[5];
 #pragma unroll
-            for (int c = 0; c < 5; c++) {
-                const int xc = lf_clampi(xb + c, 0, g.w - 1);
-                ta[c] = R[ra + xc];
-                tb[c] = R[rb + xc];
-            }
-#pragma unroll
-            for (int c = 0; c < 4; c++) {
-                A[c] = ta[c] | (ta[c + 1] << 16);
-                B[c] = tb[c] | (tb[c + 1] << 16);
-            }
+        for (int c = 0; c < 5; c++) {
+            const int k = lf_clampi(xb + c, 0, g.w - 1) - xs;  // 0 .. 4
+            const uint32_t pa = k < 2 ? A[0] : A[2], pb = k < 2 ? B[0] : B[2];
+            ta[c] = k == 4 ? A[3] >> 16 : (k & 1 ? pa >> 16 : pa & 0xFFFFu);
+            tb[c] = k == 4 ? B[3] >> 16 : (k & 1 ? pb >> 16 : pb & 0xFFFFu);
         }
-        const lf_i16x2 wx0 = lf_splat(4 - fx), wx1 = lf_splat(fx), wy0 = lf_splat(4 - fy), wy1 = lf_splat(fy);
-        // (t_k, t_{k+1}) pairs for outputs (0,1) are A[0], A[1]; for (2,3) A[2], A[3]
-        const lf_i16x2 top01 = wx0 * lf_as_i16x2(A[0]) + wx1 * lf_as_i16x2(A[1]);
-        const lf_i16x2 top23 = wx0 * lf_as_i16x2(A[2]) + wx1 * lf_as_i16x2(A[3]);
-        const lf_i16x2 bot01 = wx0 * lf_as_i16x2(B[0]) + wx1 * lf_as_i16x2(B[1]);
-        const lf_i16x2 bot23 = wx0 * lf_as_i16x2(B[2]) + wx1 * lf_as_i16x2(B[3]);
-        const lf_i16x2 q01 = (wy0 * top01 + wy1 * bot01 + lf_splat(8)) >> lf_splat(4);
-        const lf_i16x2 q23 = (wy0 * top23 + wy1 * bot23 + lf_splat(8)) >> lf_splat(4);
-        const lf_i16x2 sg = lf_splat(code == 0u ? 1 : -1);
-        r01 = r01 + sg * q01;
-        r23 = r23 + sg * q23;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            A[c] = ta[c] | (ta[c + 1] << 16);
+            B[c] = tb[c] | (tb[c + 1] << 16);
+        }
     }
-    return make_uint2(lf_as_u32(r01), lf_as_u32(r23));
+    const lf_i16x2 wx0 = lf_splat(4 - fx), wx1 = lf_splat(fx), wy0 = lf_splat(4 - fy), wy1 = lf_splat(fy);
+    const lf_i16x2 top01 = wx0 * lf_as_i16x2(A[0]) + wx1 * lf_as_i16x2(A[1]);
+    const lf_i16x2 top23 = wx0 * lf_as_i16x2(A[2]) + wx1 * lf_as_i16x2(A[3]);
+    const lf_i16x2 bot01 = wx0 * lf_as_i16x2(B[0]) + wx1 * lf_as_i16x2(B[1]);
+    const lf_i16x2 bot23 = wx0 * lf_as_i16x2(B[2]) + wx1 * lf_as_i16x2(B[3]);
+    const lf_i16x2 q01 = (wy0 * top01 + wy1 * bot01 + lf_splat(8)) >> lf_splat(4);
+    const lf_i16x2 q23 = (wy0 * top23 + wy1 * bot23 + lf_splat(8)) >> lf_splat(4);
+    const lf_i16x2 sg = lf_splat(code == 0u ? 1 : (code == 1u ? -1 : 0));  // phase sign; 0: no prediction
+    return make_uint2(lf_as_u32(r01 + sg * q01), lf_as_u32(r23 + sg * q23));
 }
 
 // floor(n / d) for n, d < 2^16: m = ceil(2^32 / d) for d >= 2 (exact in that
@@ -620,7 +621,8 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                                                          (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
             } else {
                 const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
-                packed = lf_srv_quad(g, p, desc[info + kb], y, x0, digits);
+                const uint4 d = desc[info + kb];
+                packed = (d.z >> 24) == MODE_PLANE ? lf_ref_quad(g, p, d, y, x0) : lf_pred_quad(g, p, d, y, x0, digits);
             }
             *reinterpret_cast<uint2*>(sval + (size_t)it * 4) = packed;
         }
@@ -633,12 +635,23 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int y = ymin + yl, x0 = xq0 + 4 * qi;
             const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
             const uint4* dq = desc + __mul24(3 * u, nbk) + kb;
+            // the node is a reference (resident planes) or predictive in all three channels
+            uint4 dc[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) dc[c] = dq[c * nbk];
+            uint2 qc[3];
+            if ((dc[0].z >> 24) == MODE_PLANE) {
+#pragma unroll
+                for (int c = 0; c < 3; c++) qc[c] = lf_ref_quad(g, p, dc[c], y, x0);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; c++) qc[c] = lf_pred_quad(g, p, dc[c], y, x0, digits);
+            }
             lf_i16x2 ch[3][2];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const uint2 q = lf_srv_quad(g, p, dq[c * nbk], y, x0, digits);
-                ch[c][0] = lf_as_i16x2(q.x);
-                ch[c][1] = lf_as_i16x2(q.y);
+                ch[c][0] = lf_as_i16x2(qc[c].x);
+                ch[c][1] = lf_as_i16x2(qc[c].y);
             }
             const uint2 an = *reinterpret_cast<const uint2*>(ancs[u]);
             for (int l = 1; l <= g.H; l++) {
