@@ -45,23 +45,25 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
 }
 
 __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
-                                                     int wo, int ho, int tiles_x, int tiles_y, int fpg,
+                                                     int wo, int ho, int tiles_x, int tiles_y, int chunk, int fpg,
                                                      float* __restrict__ out)
 {
+    // A workgroup renders one screen tile for a chunk of consecutive views
+    // (groups of fpg views, decoded values cached between the groups).
     // XCD-aware order: workgroup ids go round-robin over the 8 XCDs, so give
-    // each XCD a contiguous range of (view group, tile) work: consecutive
+    // each XCD a contiguous range of (view chunk, tile) work: consecutive
     // views and neighbouring tiles share stream data in that XCD's L2.
-    const int n_groups_v = (nv + fpg - 1) / fpg;
-    const int64_t n_work = (int64_t)tiles_x * tiles_y * n_groups_v;
+    const int n_chunks = (nv + chunk - 1) / chunk;
+    const int64_t n_work = (int64_t)tiles_x * tiles_y * n_chunks;
     const int64_t per_xcd = (n_work + 7) / 8;
     const int64_t work = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (work >= n_work) return;  // uniform per workgroup
     TILE_LDS_DECL
-    const int vg = (int)(work / ((int64_t)tiles_x * tiles_y));
-    const int tt = (int)(work - (int64_t)vg * tiles_x * tiles_y);
+    const int vc = (int)(work / ((int64_t)tiles_x * tiles_y));
+    const int tt = (int)(work - (int64_t)vc * tiles_x * tiles_y);
     const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
-    const int v0 = vg * fpg, nf = min(fpg, nv - v0);
-    lf_tile_views<false>(g, p, cams, v0, nf, wo, ho, txi, tyi, out, S);
+    const int v0 = vc * chunk, nf = min(chunk, nv - v0);
+    lf_tile_views<false>(g, p, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
 }
 
 // Per-ray rendering of the (view, tile) pairs the batched kernel marked.
@@ -114,22 +116,32 @@ __global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, cons
     }
 }
 
+static int env_int(const char* name, int dflt, int lo, int hi)
+{
+    const char* e = getenv(name);
+    int v = e ? atoi(e) : dflt;
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// views per group (decoded together) and per chunk (one workgroup, values
+// cached between its groups)
 static int frames_per_group()
 {
-    static int fpg = [] {
-        const char* e = getenv("HMLFC_VIEWS_PER_GROUP");
-        int v = e ? atoi(e) : 8;
-        return v < 1 ? 1 : (v > FMAX ? FMAX : v);
-    }();
-    return fpg;
+    static int v = env_int("HMLFC_VIEWS_PER_GROUP", 8, 1, FMAX);
+    return v;
+}
+static int frames_per_chunk()
+{
+    static int v = env_int("HMLFC_VIEWS_PER_CHUNK", 24, 1, FMAX);
+    return v;
 }
 
 lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,
                                  hipStream_t s)
 {
     const int tx = (wo + TW - 1) / TW, ty = (ho + TH - 1) / TH;
-    const int fpg = frames_per_group();
-    const int64_t n_work = (int64_t)tx * ty * ((nv + fpg - 1) / fpg);
+    const int fpg = frames_per_group(), chunk = max(frames_per_chunk(), fpg);
+    const int64_t n_work = (int64_t)tx * ty * ((nv + chunk - 1) / chunk);
     const int64_t grid = ((n_work + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
     const size_t lds = LDS_DYN_BYTES;
@@ -141,7 +153,7 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
         attr_set = true;
     }
     hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
-                       d_cams, nv, wo, ho, tx, ty, fpg, d_out);
+                       d_cams, nv, wo, ho, tx, ty, chunk, fpg, d_out);
     const int64_t pairs = (int64_t)tx * ty * nv;
     hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)((pairs + NT - 1) / NT)), dim3(NT), 0, s, h->L.g, h->p, d_cams,
                        nv, wo, ho, tx, ty, d_out);

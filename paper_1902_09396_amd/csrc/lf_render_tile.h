@@ -74,7 +74,9 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
 #define FMAX 32          // views per workgroup (upper bound of the group size)
 #define LMAX 64          // nodes of one level inside a group's bounding rectangle
 #define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
-#define SLOT_MAX 160
+#define SLOT_MAX 192  // staged channel planes decoded for one group (3 x CMAX)
+#define CMAX 64       // cache entries per kind (leaf views, ancestor nodes)
+#define CKEY_EMPTY 0xFFFFFFFFu
 
 // LDS staging budgets (entries): descriptors (16 B), assembled samples (4 B),
 // staged ancestor/root values (2 B).  About 46 KiB plus 6 KiB of tables keeps
@@ -331,19 +333,49 @@ __device__ __forceinline__ int lf_qdiv(int n, uint32_t m) { return m ? (int)__um
 
 // Plan of one group of views: the footprint's pixel box, and per level l
 // (0 = leaf views .. H = root) the bounding rectangle of the nodes the group
-// reaches, which of them some ray actually reaches ("used"), and their
-// compact numbering.  Only used nodes are staged.
+// reaches.  Decoded values stay in LDS across the groups of one call while
+// the box stays the same: assembled leaf-view samples (RGBA8, one entry per
+// view) and staged ancestor values (one entry per node, three channel
+// planes) are kept in entries keyed by (level, node).  A group decodes only
+// the leaf views some ray needs that no entry holds, and only the ancestors
+// of those views that no entry holds ("new" nodes).
 struct GroupPlan {
     int ok;
     int xq0, ymin, sy, nq, sxp, npix;  // quad-aligned rows: x from xq0, nq quads per row, stride sxp = 4 nq
     int bkx0, bky0, nbkx, nbk;
     int B0[LF_MAX_LEVELS + 1], A0[LF_MAX_LEVELS + 1], nA[LF_MAX_LEVELS + 1];
-    int nused[LF_MAX_LEVELS + 1];
-    int sbase[LF_MAX_LEVELS + 1];  // first staged slot of each level (levels 1..H); slot = sbase + 3 u + c
-    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (levels 0..H-1); + (3 u + c) nbk + block
+    int nnew[LF_MAX_LEVELS + 1];   // new nodes of each level
+    int sbase[LF_MAX_LEVELS + 1];  // first new staged slot of each level (1..H); slot = sbase + 3 k + c
+    int dbase[LF_MAX_LEVELS];      // first descriptor of each level (0..H-1); + (3 k + c) nbk + block
     int nslots, ndesc;
     uint32_t m_rowq, m_nq, m_nbk;  // reciprocals of sy * nq, nq and nbk
+    uint32_t cbox0, cbox1;         // box the cache entries hold values of (all ones: none)
 };
+
+// Key of node (B, A) of level l (B, A < 2^14)
+__device__ __forceinline__ uint32_t lf_node_key(int l, int B, int A)
+{
+    return ((uint32_t)l << 28) | ((uint32_t)B << 14) | (uint32_t)A;
+}
+
+// Position of the q-th (from 0) set bit of m (q < popcount(m))
+__device__ __forceinline__ int lf_nth_bit(uint64_t m, int q)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = (1ull << w) - 1ull;
+        const int c = __popcll(m & low);
+        if (q >= c) {
+            q -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m &= low;
+        }
+    }
+    return pos;
+}
 
 #define FALLBACK_MARK 0x7FC0DEADu  // NaN payload: "this tile of this view needs per-ray decoding"
 
@@ -354,10 +386,12 @@ struct TileLds {
     int16_t* sval;     // [B_SVAL]
     uint32_t (*fbox)[4];
     GroupPlan* gpp;
-    int8_t (*nodemap)[LMAX];
-    uint8_t (*nodelist)[LMAX];
-    uint8_t (*ancs)[LF_MAX_LEVELS];  // per used leaf view: staged slot (channel 0) of its ancestor at level 1 + k
-    uint32_t* slotinfo;
+    int8_t (*nodemap)[LMAX];         // cache entry of each used node of the level rectangles, -1: unused
+    uint16_t (*nodelist)[LMAX];      // k-th new node of a level: rectangle lane | entry << 8
+    uint8_t (*ancs)[LF_MAX_LEVELS];  // per new leaf view: staged slot (channel 0) of its ancestor at level 1 + k
+    uint32_t* slotinfo;              // per new staged slot: descriptor base, or root plane | 1 << 31
+    uint8_t* slotdst;                // per new staged slot: destination slot (3 entry + channel)
+    uint32_t (*ckey)[CMAX];          // cache keys: [0] leaf views, [1] ancestor nodes
     const uint32_t* digits;  // decode table (lf_fill_tab)
 };
 
@@ -366,23 +400,26 @@ struct TileLds {
     __shared__ uint32_t fbox_s[FMAX][4];                                                         \
     __shared__ GroupPlan gp_s;                                                                   \
     __shared__ int8_t nodemap_s[LF_MAX_LEVELS + 1][LMAX];                                        \
-    __shared__ uint8_t nodelist_s[LF_MAX_LEVELS + 1][LMAX];                                      \
+    __shared__ uint16_t nodelist_s[LF_MAX_LEVELS + 1][LMAX];                                     \
     __shared__ __align__(8) uint8_t ancs_s[LMAX][LF_MAX_LEVELS];                                 \
     __shared__ uint32_t slotinfo_s[SLOT_MAX];                                                    \
+    __shared__ uint8_t slotdst_s[SLOT_MAX];                                                      \
+    __shared__ uint32_t ckey_s[2][CMAX];                                                         \
     __shared__ uint32_t digits_s[LF_TAB_SIZE];                                                   \
     const TileLds S{lds_dyn,                                                                     \
                     reinterpret_cast<uint32_t*>(lds_dyn + B_DESC),                               \
                     reinterpret_cast<int16_t*>(reinterpret_cast<uint32_t*>(lds_dyn + B_DESC) + B_RGBA), \
-                    fbox_s, &gp_s, nodemap_s, nodelist_s, ancs_s, slotinfo_s, digits_s};                 \
+                    fbox_s, &gp_s, nodemap_s, nodelist_s, ancs_s, slotinfo_s, slotdst_s, ckey_s, digits_s};                 \
     lf_fill_tab(digits_s);                                                                       \
     __syncthreads();
 
 // Render screen tile (txi, tyi) of views v0 .. v0 + nf - 1 (cameras cams[v],
-// output out[v][3][ho][wo]).  Every thread of the workgroup calls it; LDS
-// contents do not carry over between calls.
+// output out[v][3][ho][wo]; nf <= FMAX), in groups of at most gmax
+// consecutive views.  Every thread of the workgroup calls it; LDS contents do
+// not carry over between calls.
 template <bool INLINE_FALLBACK>
 __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
-                              int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
+                              int gmax, int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
 {
     uint4* desc = S.desc;
     uint32_t* rgba = S.rgba;
@@ -391,15 +428,18 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
     uint32_t (*fbox)[4] = S.fbox;
     GroupPlan& gp = *S.gpp;
     int8_t (*nodemap)[LMAX] = S.nodemap;
-    uint8_t (*nodelist)[LMAX] = S.nodelist;
+    uint16_t (*nodelist)[LMAX] = S.nodelist;
     uint8_t (*ancs)[LF_MAX_LEVELS] = S.ancs;
     uint32_t* slotinfo = S.slotinfo;
+    uint8_t* slotdst = S.slotdst;
+    uint32_t (*ckey)[CMAX] = S.ckey;
     const uint32_t* digits = S.digits;
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int i = txi * TW + lx, j = tyi * TH + ly;
     const bool live = i < wo && j < ho;
     const int ii = live ? i : txi * TW, jj = live ? j : tyi * TH;  // dead lanes repeat the tile origin
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) gp.cbox0 = gp.cbox1 = CKEY_EMPTY;  // nothing cached yet
     // phase 0: footprint box of every view of the group (packed 16-bit
     // min/max of a0|b0<<16, a1|b1<<16, x0|y0<<16, x1|y1<<16).  For an affine
     // camera (third rows 0 0 1) each computed coordinate is, without
@@ -468,10 +508,10 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
     }
 
     const int64_t npix_out = (int64_t)wo * ho;
-    int f = 0, n = nf;
+    int f = 0, n = gmax;
     while (f < nf) {
         n = min(n, nf - f);
-        // plan the group [f, f + n): wave 0 marks the used nodes of every level
+        // plan the group [f, f + n) (wave 0)
         if (wid == 0) {
             uint32_t lo_ab = 0xFFFFFFFFu, hi_ab = 0u, lo_xy = 0xFFFFFFFFu, hi_xy = 0u;
             for (int q = f; q < f + n; q++) {
@@ -488,59 +528,163 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int sy = ymax - ymin + 1, npix = sxp * sy;
             const int bkx0 = xmin >> g.bsl, bky0 = ymin >> g.bsl;
             const int nbkx = (xmax >> g.bsl) - bkx0 + 1, nbk = nbkx * ((ymax >> g.bsl) - bky0 + 1);
-            int ok = 1, ns = 0, nd = 0;
-            for (int l = 0; l <= g.H; l++) {
+            const uint32_t bx0 = (uint32_t)xq0 | ((uint32_t)ymin << 16), bx1 = (uint32_t)nq | ((uint32_t)sy << 16);
+            const bool same = gp.cbox0 == bx0 && gp.cbox1 == bx1;  // cached entries hold this box
+            const int cap0 = min(CMAX, B_RGBA / npix), cap1 = min(CMAX, B_SVAL / (3 * npix));
+            const int nA0 = amax - amin + 1, nB0 = bmax - bmin + 1;
+            int ok = nA0 * nB0 <= LMAX;
+            // level 0: leaf views some ray of the group reaches
+            bool use0 = false;
+            if (ok && lane < nA0 * nB0) {
+                const int b = bmin + lane / nA0, a = amin + lane % nA0;
+                for (int q = f; q < f + n && !use0; q++) {
+                    const int qa0 = (int)(fbox[q][0] & 0xFFFFu), qb0 = (int)(fbox[q][0] >> 16);
+                    const int qa1 = (int)(fbox[q][1] & 0xFFFFu), qb1 = (int)(fbox[q][1] >> 16);
+                    use0 = qb0 <= b && qb1 >= b && qa0 <= a && qa1 >= a;
+                }
+            }
+            const uint64_t used0 = __ballot(use0);
+            // cache entries of leaf views: hit by a used view? (entry side, lane = entry)
+            bool keep = false;
+            if (same && lane < cap0) {
+                const uint32_t k = ckey[0][lane];
+                if (k != CKEY_EMPTY) {
+                    const int b = (int)((k >> 14) & 0x3FFFu) - bmin, a = (int)(k & 0x3FFFu) - amin;
+                    keep = b >= 0 && b < nB0 && a >= 0 && a < nA0 && ((used0 >> (b * nA0 + a)) & 1ull);
+                }
+            }
+            const uint64_t free0 = ~__ballot(keep) & (cap0 >= 64 ? ~0ull : ((1ull << cap0) - 1ull));
+            // node side: entry of a used view, or new
+            int ent0 = -1;
+            if (use0 && same) {
+                const uint32_t key = lf_node_key(0, bmin + lane / nA0, amin + lane % nA0);
+                for (int e = 0; e < cap0; e++)
+                    if (ckey[0][e] == key) ent0 = e;
+            }
+            const bool new0 = use0 && ent0 < 0;
+            const uint64_t newm0 = __ballot(new0);
+            const int nnew0 = __popcll(newm0);
+            ok = ok && nnew0 <= __popcll(free0);
+            if (new0 && ok) ent0 = lf_nth_bit(free0, __popcll(newm0 & ((1ull << lane) - 1ull)));
+            // levels 1..H: ancestors of the new leaf views
+            int entl[LF_MAX_LEVELS + 1];
+            bool newl[LF_MAX_LEVELS + 1];
+            uint64_t keep1 = 0;
+            int nnew1 = 0, nd = 3 * nbk * nnew0, ns = 0;
+            int cnt[LF_MAX_LEVELS + 1];
+            cnt[0] = nnew0;
+#pragma unroll
+            for (int l = 1; l <= LF_MAX_LEVELS; l++) {
+                entl[l] = -1;
+                newl[l] = false;
+                cnt[l] = 0;
+                if (l > g.H) continue;
                 const int B0 = bmin >> l, A0 = amin >> l;
                 const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
-                const bool in_rect = nB * nA <= LMAX && lane < nB * nA;
-                bool used = false;
-                if (in_rect) {
-                    // node (B, A) covers views [B << l, (B + 1) << l) x [A << l, (A + 1) << l)
+                if (nB * nA > LMAX) ok = 0;
+                // node (B, A) of the rectangle: does a new leaf view descend from it?
+                bool need = false;
+                if (lane < nB * nA && nB * nA <= LMAX) {
                     const int B = B0 + lane / nA, A = A0 + lane % nA;
-                    const int vb0 = B << l, vb1 = ((B + 1) << l) - 1, va0 = A << l, va1 = ((A + 1) << l) - 1;
-                    for (int q = f; q < f + n && !used; q++) {
-                        const int qa0 = (int)(fbox[q][0] & 0xFFFFu), qb0 = (int)(fbox[q][0] >> 16);
-                        const int qa1 = (int)(fbox[q][1] & 0xFFFFu), qb1 = (int)(fbox[q][1] >> 16);
-                        used = qb0 <= vb1 && qb1 >= vb0 && qa0 <= va1 && qa1 >= va0;
+                    const int rb0 = max(B << l, bmin) - bmin, rb1 = min(((B + 1) << l) - 1, bmax) - bmin;
+                    const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
+                    for (int r = rb0; r <= rb1 && !need; r++)
+                        need = ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
+                    if (need && same) {
+                        const uint32_t key = lf_node_key(l, B, A);
+                        for (int e = 0; e < cap1; e++)
+                            if (ckey[1][e] == key) entl[l] = e;
                     }
                 }
-                const uint64_t bal = __ballot(used);
-                const int cnt = __popcll(bal);
-                if (nB * nA > LMAX) ok = 0;
-                if (lane < LMAX) {
-                    const int idx = used ? __popcll(bal & ((1ull << lane) - 1ull)) : -1;
-                    nodemap[l][lane] = (int8_t)idx;
-                    if (used) nodelist[l][idx] = (uint8_t)lane;
+                // entries of this level that a needed node hits (entry side)
+                bool kp = false;
+                if (same && lane < cap1) {
+                    const uint32_t k = ckey[1][lane];
+                    if (k != CKEY_EMPTY && (int)(k >> 28) == l) {
+                        const int B = (int)((k >> 14) & 0x3FFFu), A = (int)(k & 0x3FFFu);
+                        const int eb = B - B0, ea = A - A0;
+                        if (eb >= 0 && eb < nB && ea >= 0 && ea < nA) {
+                            const int rb0 = max(B << l, bmin) - bmin, rb1 = min(((B + 1) << l) - 1, bmax) - bmin;
+                            const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
+                            for (int r = rb0; r <= rb1 && !kp; r++)
+                                kp = ra0 <= ra1 && ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
+                        }
+                    }
                 }
-                if (lane == 0) {
-                    gp.B0[l] = B0;
-                    gp.A0[l] = A0;
-                    gp.nA[l] = nA;
-                    gp.nused[l] = cnt;
-                    gp.sbase[l] = ns;
-                    if (l < g.H) gp.dbase[l] = nd;
-                }
-                if (l >= 1) ns += 3 * cnt;
-                if (l < g.H) nd += 3 * cnt * nbk;
+                keep1 |= __ballot(kp);
+                newl[l] = need && entl[l] < 0;
+                cnt[l] = __popcll(__ballot(newl[l]));
+                nnew1 += cnt[l];
+                ns += 3 * cnt[l];
+                if (l < g.H) nd += 3 * nbk * cnt[l];
             }
-            ok = ok && gp.nused[0] * npix <= B_RGBA && ns * npix <= B_SVAL && nd <= B_DESC && ns <= SLOT_MAX;
+            const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
+            ok = ok && nnew1 <= __popcll(free1) && nd <= B_DESC && ns <= SLOT_MAX;
+            if (ok) {
+                // commit: entries of the new nodes, node maps, new-node lists, keys
+                if (!same && lane < CMAX) {
+                    ckey[0][lane] = CKEY_EMPTY;
+                    ckey[1][lane] = CKEY_EMPTY;
+                }
+                if (lane < LMAX) nodemap[0][lane] = (int8_t)(use0 ? ent0 : -1);
+                if (new0) {
+                    const int k = __popcll(newm0 & ((1ull << lane) - 1ull));
+                    nodelist[0][k] = (uint16_t)(lane | (ent0 << 8));
+                    ckey[0][ent0] = lf_node_key(0, bmin + lane / nA0, amin + lane % nA0);
+                }
+                int q0 = 0, sb = 0, db = 3 * nbk * nnew0;
+                if (lane == 0) gp.dbase[0] = 0;
+#pragma unroll
+                for (int l = 1; l <= LF_MAX_LEVELS; l++) {
+                    if (l > g.H) continue;
+                    const int B0 = bmin >> l, A0 = amin >> l, nA = (amax >> l) - A0 + 1;
+                    const uint64_t nm = __ballot(newl[l]);
+                    int e = entl[l];
+                    if (newl[l]) {
+                        const int k = __popcll(nm & ((1ull << lane) - 1ull));
+                        e = lf_nth_bit(free1, q0 + k);
+                        nodelist[l][k] = (uint16_t)(lane | (e << 8));
+                        ckey[1][e] = lf_node_key(l, B0 + lane / nA, A0 + lane % nA);
+                    }
+                    if (lane < LMAX) nodemap[l][lane] = (int8_t)e;
+                    if (lane == 0) {
+                        gp.sbase[l] = sb;
+                        if (l < g.H) gp.dbase[l] = db;
+                    }
+                    q0 += cnt[l];
+                    sb += 3 * cnt[l];
+                    if (l < g.H) db += 3 * nbk * cnt[l];
+                }
+            }
             if (lane == 0) {
                 gp.ok = ok;
-                gp.xq0 = xq0;
-                gp.ymin = ymin;
-                gp.sy = sy;
-                gp.nq = nq;
-                gp.sxp = sxp;
-                gp.npix = npix;
-                gp.bkx0 = bkx0;
-                gp.bky0 = bky0;
-                gp.nbkx = nbkx;
-                gp.nbk = nbk;
-                gp.nslots = ns;
-                gp.ndesc = nd;
-                gp.m_rowq = lf_magic((uint32_t)(sy * nq));
-                gp.m_nq = lf_magic((uint32_t)nq);
-                gp.m_nbk = lf_magic((uint32_t)nbk);
+                if (ok) {
+#pragma unroll
+                    for (int l = 0; l <= LF_MAX_LEVELS; l++) {
+                        if (l > g.H) continue;
+                        gp.B0[l] = bmin >> l;
+                        gp.A0[l] = amin >> l;
+                        gp.nA[l] = (amax >> l) - (amin >> l) + 1;
+                        gp.nnew[l] = cnt[l];
+                    }
+                    gp.xq0 = xq0;
+                    gp.ymin = ymin;
+                    gp.sy = sy;
+                    gp.nq = nq;
+                    gp.sxp = sxp;
+                    gp.npix = npix;
+                    gp.bkx0 = bkx0;
+                    gp.bky0 = bky0;
+                    gp.nbkx = nbkx;
+                    gp.nbk = nbk;
+                    gp.nslots = ns;
+                    gp.ndesc = nd;
+                    gp.m_rowq = lf_magic((uint32_t)(sy * nq));
+                    gp.m_nq = lf_magic((uint32_t)nq);
+                    gp.m_nbk = lf_magic((uint32_t)nbk);
+                    gp.cbox0 = bx0;
+                    gp.cbox1 = bx1;
+                }
             }
         }
         __syncthreads();
@@ -563,7 +707,7 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     __uint_as_float(FALLBACK_MARK);
             }
             f += 1;
-            n = nf;
+            n = gmax;
             __syncthreads();
             continue;
         }
@@ -571,15 +715,16 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         const int xq0 = gp.xq0, ymin = gp.ymin, bkx0 = gp.bkx0, bky0 = gp.bky0;
         const int rowq = gp.sy * nq;  // quads per staged plane
         const uint32_t m_rowq = gp.m_rowq, m_nq = gp.m_nq, m_nbk = gp.m_nbk;
-        // phase 1a: block descriptors of the used nodes of levels 0..H-1, and
-        // the slot table of the staged values (levels 1..H)
+        // phase 1a: block descriptors of the new nodes of levels 0..H-1, the
+        // slot table of the new staged values (levels 1..H), and the
+        // ancestor slots of the new leaf views
         for (int d = threadIdx.x; d < gp.ndesc; d += NT) {
             int l = 0;
             while (l + 1 < g.H && d >= gp.dbase[l + 1]) l++;
-            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // 3 u + c
+            const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // 3 k + c
             const int kb = d - gp.dbase[l] - row * nbk;
-            const int u = row / 3, c = row - 3 * u;
-            const int e = nodelist[l][u];
+            const int k = row / 3, c = row - 3 * k;
+            const int e = nodelist[l][k] & 0xFF;
             const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
             const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
             desc[d] = lf_make_desc(g, p, c, l, B, A, blk);
@@ -587,29 +732,31 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
             int l = 1;
             while (l < g.H && sl >= gp.sbase[l + 1]) l++;
-            const int row = sl - gp.sbase[l];  // 3 u + c
-            const int u = row / 3, c = row - 3 * u;
+            const int row = sl - gp.sbase[l];  // 3 k + c
+            const int k = row / 3, c = row - 3 * k;
+            const uint32_t nl = nodelist[l][k];
             uint32_t info;
             if (l == g.H) {
-                const int e = nodelist[l][u];
+                const int e = nl & 0xFF;
                 const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
                 info = 0x80000000u | (uint32_t)((c * g.root_nb + B) * g.root_na + A);
             } else {
                 info = (uint32_t)(gp.dbase[l] + row * nbk);
             }
             slotinfo[sl] = info;
+            slotdst[sl] = (uint8_t)(3 * (nl >> 8) + c);
         }
-        for (int u = threadIdx.x; u < gp.nused[0]; u += NT) {
-            const int e = nodelist[0][u];
+        for (int k = threadIdx.x; k < gp.nnew[0]; k += NT) {
+            const int e = nodelist[0][k] & 0xFF;
             const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
             for (int l = 1; l <= g.H; l++) {
                 const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
-                ancs[u][l - 1] = (uint8_t)(gp.sbase[l] + 3 * nodemap[l][el]);
+                ancs[k][l - 1] = (uint8_t)(3 * nodemap[l][el]);
             }
         }
         __syncthreads();
-        // phase 1b: values shared by several views, once per node and pixel quad:
-        // SRVs of levels 1..H-1 and the root RKV (level H)
+        // phase 1b: new values shared by several views, once per node and pixel
+        // quad: SRVs of levels 1..H-1 and the root RKV (level H)
         for (int it = threadIdx.x; it < gp.nslots * rowq; it += NT) {
             const int sl = lf_qdiv(it, m_rowq), rq = it - sl * rowq;
             const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
@@ -624,17 +771,16 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 const uint4 d = desc[info + kb];
                 packed = (d.z >> 24) == MODE_PLANE ? lf_ref_quad(g, p, d, y, x0) : lf_pred_quad(g, p, d, y, x0, digits);
             }
-            *reinterpret_cast<uint2*>(sval + (size_t)it * 4) = packed;
+            reinterpret_cast<uint2*>(sval)[__mul24((int)slotdst[sl], rowq) + rq] = packed;
         }
         __syncthreads();
-        // phase 2: every used (view, pixel quad) sample: level-0 SRV + staged ancestors and root
-        const int nu0 = gp.nused[0];
-        for (int it = threadIdx.x; it < nu0 * rowq; it += NT) {
-            const int u = lf_qdiv(it, m_rowq), rq = it - u * rowq;
+        // phase 2: every new (view, pixel quad) sample: level-0 SRV + staged ancestors and root
+        for (int it = threadIdx.x; it < gp.nnew[0] * rowq; it += NT) {
+            const int k = lf_qdiv(it, m_rowq), rq = it - k * rowq;
             const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
             const int y = ymin + yl, x0 = xq0 + 4 * qi;
             const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
-            const uint4* dq = desc + __mul24(3 * u, nbk) + kb;
+            const uint4* dq = desc + __mul24(3 * k, nbk) + kb;
             // the node is a reference (resident planes) or predictive in all three channels
             uint4 dc[3];
 #pragma unroll
@@ -653,7 +799,7 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 ch[c][0] = lf_as_i16x2(qc[c].x);
                 ch[c][1] = lf_as_i16x2(qc[c].y);
             }
-            const uint2 an = *reinterpret_cast<const uint2*>(ancs[u]);
+            const uint2 an = *reinterpret_cast<const uint2*>(ancs[k]);
             for (int l = 1; l <= g.H; l++) {
                 const uint32_t sl = ((l <= 4 ? an.x : an.y) >> (8 * ((l - 1) & 3))) & 0xFFu;
                 const uint2* sv = reinterpret_cast<const uint2*>(sval) + __mul24(sl, rowq) + rq;
@@ -689,7 +835,7 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     px4.w = p1;
                 }
             }
-            *reinterpret_cast<uint4*>(rgba + (size_t)it * 4) = px4;
+            reinterpret_cast<uint4*>(rgba)[__mul24((int)(nodelist[0][k] >> 8), rowq) + rq] = px4;
         }
         __syncthreads();
         // phase 3: blend every ray of the group's views
@@ -719,9 +865,9 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 }
             }
         }
-        __syncthreads();  // LDS is reused by the next group of views
+        __syncthreads();  // the next group's plan rewrites the node maps
         f += n;
-        n = nf;
+        n = gmax;
     }
 }
 

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ g
             }
             __syncthreads();
         }
-        lf_tile_views<true>(sg, sp, sl->cam, 0, 1, sl->wo, sl->ho, it.tx, it.ty,
+        lf_tile_views<true>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
                             reinterpret_cast<float*>(pool + sl->out_off), S);
     }
 }
