@@ -533,43 +533,62 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int cap0 = min(CMAX, B_RGBA / npix), cap1 = min(CMAX, B_SVAL / (3 * npix));
             const int nA0 = amax - amin + 1, nB0 = bmax - bmin + 1;
             int ok = nA0 * nB0 <= LMAX;
+            // node maps start empty; cache entries that a node of this group
+            // keeps write their index into the node's map (entry side), and
+            // each node then reads its map (node side; same wave, LDS in order)
+#pragma unroll
+            for (int l = 0; l <= LF_MAX_LEVELS; l++)
+                if (l <= g.H) nodemap[l][lane] = -1;
             // level 0: leaf views some ray of the group reaches
             bool use0 = false;
             if (ok && lane < nA0 * nB0) {
                 const int b = bmin + lane / nA0, a = amin + lane % nA0;
                 for (int q = f; q < f + n && !use0; q++) {
-                    const int qa0 = (int)(fbox[q][0] & 0xFFFFu), qb0 = (int)(fbox[q][0] >> 16);
-                    const int qa1 = (int)(fbox[q][1] & 0xFFFFu), qb1 = (int)(fbox[q][1] >> 16);
-                    use0 = qb0 <= b && qb1 >= b && qa0 <= a && qa1 >= a;
+                    const uint32_t q0 = fbox[q][0], q1 = fbox[q][1];
+                    use0 = (int)(q0 >> 16) <= b && (int)(q1 >> 16) >= b && (int)(q0 & 0xFFFFu) <= a &&
+                           (int)(q1 & 0xFFFFu) >= a;
                 }
             }
             const uint64_t used0 = __ballot(use0);
-            // cache entries of leaf views: hit by a used view? (entry side, lane = entry)
+            const uint32_t key0 = same && lane < cap0 ? ckey[0][lane] : CKEY_EMPTY;
+            const uint32_t key1 = same && lane < cap1 ? ckey[1][lane] : CKEY_EMPTY;
             bool keep = false;
-            if (same && lane < cap0) {
-                const uint32_t k = ckey[0][lane];
-                if (k != CKEY_EMPTY) {
-                    const int b = (int)((k >> 14) & 0x3FFFu) - bmin, a = (int)(k & 0x3FFFu) - amin;
-                    keep = b >= 0 && b < nB0 && a >= 0 && a < nA0 && ((used0 >> (b * nA0 + a)) & 1ull);
-                }
+            if (key0 != CKEY_EMPTY) {
+                const int b = (int)((key0 >> 14) & 0x3FFFu) - bmin, a = (int)(key0 & 0x3FFFu) - amin;
+                keep = ok && b >= 0 && b < nB0 && a >= 0 && a < nA0 && ((used0 >> (b * nA0 + a)) & 1ull);
+                if (keep) nodemap[0][b * nA0 + a] = (int8_t)lane;
             }
             const uint64_t free0 = ~__ballot(keep) & (cap0 >= 64 ? ~0ull : ((1ull << cap0) - 1ull));
-            // node side: entry of a used view, or new
-            int ent0 = -1;
-            if (use0 && same) {
-                const uint32_t key = lf_node_key(0, bmin + lane / nA0, amin + lane % nA0);
-                for (int e = 0; e < cap0; e++)
-                    if (ckey[0][e] == key) ent0 = e;
-            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            int ent0 = nodemap[0][lane];
             const bool new0 = use0 && ent0 < 0;
             const uint64_t newm0 = __ballot(new0);
             const int nnew0 = __popcll(newm0);
             ok = ok && nnew0 <= __popcll(free0);
             if (new0 && ok) ent0 = lf_nth_bit(free0, __popcll(newm0 & ((1ull << lane) - 1ull)));
-            // levels 1..H: ancestors of the new leaf views
+            // levels 1..H: ancestors of the new leaf views.  A node (B, A) of
+            // level l covers leaf rows [B << l, (B + 1) << l) and columns
+            // [A << l, (A + 1) << l); it is needed when one of the new leaf
+            // views lies there.
+            const int kl = key1 != CKEY_EMPTY ? (int)(key1 >> 28) : 0;
+            bool kneed = false;
+            if (kl >= 1 && kl <= g.H) {
+                const int B = (int)((key1 >> 14) & 0x3FFFu), A = (int)(key1 & 0x3FFFu);
+                if (B >= (bmin >> kl) && B <= (bmax >> kl) && A >= (amin >> kl) && A <= (amax >> kl)) {
+                    const int rb0 = max(B << kl, bmin) - bmin, rb1 = min(((B + 1) << kl) - 1, bmax) - bmin;
+                    const int ra0 = max(A << kl, amin) - amin, ra1 = min(((A + 1) << kl) - 1, amax) - amin;
+                    for (int r = rb0; r <= rb1 && !kneed; r++)
+                        kneed = ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
+                    const int nA = (amax >> kl) - (amin >> kl) + 1;
+                    const int el = (B - (bmin >> kl)) * nA + (A - (amin >> kl));
+                    kneed = kneed && el < LMAX;
+                    if (kneed) nodemap[kl][el] = (int8_t)lane;
+                }
+            }
+            const uint64_t keep1 = __ballot(kneed);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             int entl[LF_MAX_LEVELS + 1];
             bool newl[LF_MAX_LEVELS + 1];
-            uint64_t keep1 = 0;
             int nnew1 = 0, nd = 3 * nbk * nnew0, ns = 0;
             int cnt[LF_MAX_LEVELS + 1];
             cnt[0] = nnew0;
@@ -582,7 +601,6 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 const int B0 = bmin >> l, A0 = amin >> l;
                 const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
                 if (nB * nA > LMAX) ok = 0;
-                // node (B, A) of the rectangle: does a new leaf view descend from it?
                 bool need = false;
                 if (lane < nB * nA && nB * nA <= LMAX) {
                     const int B = B0 + lane / nA, A = A0 + lane % nA;
@@ -590,28 +608,8 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
                     for (int r = rb0; r <= rb1 && !need; r++)
                         need = ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
-                    if (need && same) {
-                        const uint32_t key = lf_node_key(l, B, A);
-                        for (int e = 0; e < cap1; e++)
-                            if (ckey[1][e] == key) entl[l] = e;
-                    }
+                    entl[l] = nodemap[l][lane];
                 }
-                // entries of this level that a needed node hits (entry side)
-                bool kp = false;
-                if (same && lane < cap1) {
-                    const uint32_t k = ckey[1][lane];
-                    if (k != CKEY_EMPTY && (int)(k >> 28) == l) {
-                        const int B = (int)((k >> 14) & 0x3FFFu), A = (int)(k & 0x3FFFu);
-                        const int eb = B - B0, ea = A - A0;
-                        if (eb >= 0 && eb < nB && ea >= 0 && ea < nA) {
-                            const int rb0 = max(B << l, bmin) - bmin, rb1 = min(((B + 1) << l) - 1, bmax) - bmin;
-                            const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
-                            for (int r = rb0; r <= rb1 && !kp; r++)
-                                kp = ra0 <= ra1 && ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
-                        }
-                    }
-                }
-                keep1 |= __ballot(kp);
                 newl[l] = need && entl[l] < 0;
                 cnt[l] = __popcll(__ballot(newl[l]));
                 nnew1 += cnt[l];
@@ -626,8 +624,8 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     ckey[0][lane] = CKEY_EMPTY;
                     ckey[1][lane] = CKEY_EMPTY;
                 }
-                if (lane < LMAX) nodemap[0][lane] = (int8_t)(use0 ? ent0 : -1);
                 if (new0) {
+                    nodemap[0][lane] = (int8_t)ent0;
                     const int k = __popcll(newm0 & ((1ull << lane) - 1ull));
                     nodelist[0][k] = (uint16_t)(lane | (ent0 << 8));
                     ckey[0][ent0] = lf_node_key(0, bmin + lane / nA0, amin + lane % nA0);
@@ -645,8 +643,8 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                         e = lf_nth_bit(free1, q0 + k);
                         nodelist[l][k] = (uint16_t)(lane | (e << 8));
                         ckey[1][e] = lf_node_key(l, B0 + lane / nA, A0 + lane % nA);
+                        nodemap[l][lane] = (int8_t)e;
                     }
-                    if (lane < LMAX) nodemap[l][lane] = (int8_t)e;
                     if (lane == 0) {
                         gp.sbase[l] = sb;
                         if (l < g.H) gp.dbase[l] = db;
