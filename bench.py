@@ -152,7 +152,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32+f32",
-        "views_per_group": int(os.environ.get("HMLFC_VIEWS_PER_GROUP", "8")),
+        "views_per_group": lf.render_config()[0],
+        "views_per_chunk": lf.render_config()[1],
         "data": "synthetic",
         "config": {
             "workload": "%dx%d views of %dx%d RGB, %d-level tree, %dx%d blocks, step %d, quarter-pel MVs; "

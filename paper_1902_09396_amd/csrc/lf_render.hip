@@ -127,13 +127,20 @@ static int env_int(const char* name, int dflt, int lo, int hi)
 // cached between its groups)
 static int frames_per_group()
 {
-    static int v = env_int("HMLFC_VIEWS_PER_GROUP", 8, 1, FMAX);
+    static int v = env_int("HMLFC_VIEWS_PER_GROUP", 10, 1, FMAX);
     return v;
 }
 static int frames_per_chunk()
 {
-    static int v = env_int("HMLFC_VIEWS_PER_CHUNK", 24, 1, FMAX);
+    static int v = env_int("HMLFC_VIEWS_PER_CHUNK", 30, 1, FMAX);
     return v;
+}
+
+extern "C" lf_status lf_get_render_config(int32_t* views_per_group, int32_t* views_per_chunk)
+{
+    if (views_per_group) *views_per_group = frames_per_group();
+    if (views_per_chunk) *views_per_chunk = max(frames_per_chunk(), frames_per_group());
+    return LF_OK;
 }
 
 lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,

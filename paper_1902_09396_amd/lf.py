@@ -45,6 +45,7 @@ SIGNATURES = {
     "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
     "lf_render_views": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_render_views_per_ray": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_get_render_config": (C.c_int, [_P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_export_params": (C.c_int, [_P, _P, _P, _P]),
@@ -208,6 +209,13 @@ class LightField:
         check(lib().lf_footprint_bytes(self._h, _ptr(cams), cams.shape[0], width, height,
                                        out.ctypes.data_as(C.c_void_p), _stream()))
         return out
+
+
+def render_config() -> tuple[int, int]:
+    """(views decoded per group, views per workgroup chunk) of render_views."""
+    g, c = C.c_int32(), C.c_int32()
+    check(lib().lf_get_render_config(C.byref(g), C.byref(c)))
+    return g.value, c.value
 
 
 def ray_coords(cams: torch.Tensor, width: int, height: int) -> torch.Tensor:

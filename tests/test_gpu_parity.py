@@ -188,6 +188,25 @@ def test_load_rejects_large_reference_values(torch_mod, lfmod, tiny_stream):
     lfmod.LightField(tiny_stream)  # the unmodified stream still loads
 
 
+def test_cached_groups_equal_per_ray(torch_mod, lfmod, mid_stream):
+    """Long view sequences: a workgroup renders a chunk of views in several
+    groups and keeps decoded leaf views and ancestors between them.  The
+    staged renderer must match the unstaged per-ray kernel bit for bit when
+    entries are kept, evicted, and invalidated (footprint box changes)."""
+    torch = torch_mod
+    M = lfmod.LightField(mid_stream)
+    orbit = lfscene.camera_path_orbit(48, 17, 17, 128, 128, 128, 96, radius=6.0)
+    back = orbit[::-1].copy()
+    mixed = np.empty_like(orbit)
+    mixed[0::2], mixed[1::2] = orbit[0::2], back[0::2]  # jumps back and forth across the grid
+    zoom = lfscene.random_pinhole_cameras(40, 17, 17, 128, 128, 128, 96, seed=21, rho=1.0 / 16.0)
+    for cams in (orbit, mixed, zoom):
+        c = _cams_dev(torch, cams)
+        a = M.render_views(c, 128, 96).cpu().numpy()
+        b = M.render_views(c, 128, 96, per_ray=True).cpu().numpy()
+        assert np.array_equal(a, b)
+
+
 def test_render_deterministic(torch_mod, lfmod, mid_stream):
     torch = torch_mod
     cams = _cams_dev(torch, lfscene.camera_path_orbit(8, 17, 17, 128, 128, 96, 80))
