@@ -62,8 +62,12 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="serving workload instead: resident light fields, Poisson view requests")
     ap.add_argument("--serve-fields", default="serve256,path512,serve1024,batch1080")
+    ap.add_argument("--grad", action="store_true",
+                    help="differentiation workload instead: relaxed render + adjoint of 16 views")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-sweep", default="", help="more request rates (comma list) for a saturation sweep")
+    ap.add_argument("--serve-sweep-seconds", type=float, default=2.0)
     return ap.parse_args()
 
 
@@ -88,6 +92,9 @@ def main():
     torch.cuda.set_device(0)
     if args.serve:
         serve_bench(args)
+        return
+    if args.grad:
+        grad_bench(args)
         return
     cfg = lfscene.get_config(args.workload)
     L = cfg["lf"]
@@ -199,47 +206,121 @@ def serve_bench(args):
     from paper_1902_09396_amd.serve import Server, baseline
 
     fields, shapes = [], []
+    os.environ.setdefault("HMLFC_ENCODE_PROGRESS", "1")
+    os.environ.setdefault("HMLFC_SERVE_PROGRESS", "1")
     for name in args.serve_fields.split(","):
         cfg = lfscene.get_config(name)
         L = cfg["lf"]
         t0 = time.time()
-        light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+        light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"],
+                                progress=lambda d, t, nm=name: log("field %s: %d of %d views generated" % (nm, d, t)))
         stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
         del light
         fields.append(lf.LightField(stream, device="cuda:0"))
         shapes.append((L["na"], L["nb"], L["w"], L["h"]))
         log("field %s: %d bytes, %.1fs" % (name, stream.size, time.time() - t0))
-    rng = np.random.default_rng(55)
-    n = int(args.serve_rate * args.serve_seconds)
-    arrival = np.cumsum(rng.exponential(1.0 / args.serve_rate, size=n))
-    res = np.array([[256, 256], [512, 512], [1920, 1080], [2048, 2048]])
-    wh = res[rng.integers(0, 4, size=n)]
-    field = rng.integers(0, len(fields), size=n).astype(np.int32)
-    cams = np.zeros((n, 18), dtype=np.float32)
-    for k in range(n):
-        na, nb, w, h = shapes[field[k]]
-        cams[k] = lfscene.random_pinhole_cameras(1, na, nb, w, h, int(wh[k, 0]), int(wh[k, 1]),
-                                                 seed=int(rng.integers(1 << 30)))[0]
-    rays = float((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
-    srv = Server(fields, pool_bytes=4 << 30, max_slots=64, max_tiles=16384, chunk_tiles=1024, n_streams=2)
-    lat, mk = srv.replay(field, cams, wh, arrival)
-    stats = srv.stats()
-    srv.close()
-    lat_b, mk_b = baseline(fields, field, cams, wh, arrival)
+    def schedule(rate, seconds, seed):
+        rng = np.random.default_rng(seed)
+        n = int(rate * seconds)
+        arrival = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        res = np.array([[256, 256], [512, 512], [1920, 1080], [2048, 2048]])
+        wh = res[rng.integers(0, 4, size=n)]
+        field = rng.integers(0, len(fields), size=n).astype(np.int32)
+        cams = np.zeros((n, 18), dtype=np.float32)
+        for k in range(n):
+            na, nb, w, h = shapes[field[k]]
+            cams[k] = lfscene.random_pinhole_cameras(1, na, nb, w, h, int(wh[k, 0]), int(wh[k, 1]),
+                                                     seed=int(rng.integers(1 << 30)))[0]
+        return field, cams, wh, arrival
 
-    def summary(l, m):
+    def summary(l, m, rays):
         return {"p50_ms": round(float(np.percentile(l, 50)), 3), "p99_ms": round(float(np.percentile(l, 99)), 3),
                 "mean_ms": round(float(l.mean()), 3), "grays_per_s": round(rays / m / 1e9, 4), "makespan_s": round(m, 3)}
 
-    srv_sum, base_sum = summary(lat, mk), summary(lat_b, mk_b)
+    def run(rate, seconds, seed):
+        field, cams, wh, arrival = schedule(rate, seconds, seed)
+        rays = float((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
+        log("%.0f req/s: %d requests, %.2f Grays offered over %.1f s" % (rate, field.size, rays / 1e9, arrival[-1]))
+        srv = Server(fields, pool_bytes=4 << 30, max_slots=64, max_tiles=16384, chunk_tiles=1024, n_streams=2)
+        t0 = time.time()
+        lat, mk = srv.replay(field, cams, wh, arrival)
+        stats = srv.stats()
+        srv.close()
+        log("server replay %.1fs: %s" % (time.time() - t0, stats))
+        t0 = time.time()
+        lat_b, mk_b = baseline(fields, field, cams, wh, arrival)
+        log("baseline %.1fs" % (time.time() - t0))
+        return {"rate": rate, "requests": int(field.size), "offered_grays_per_s": round(rays / arrival[-1] / 1e9, 4),
+                "server": summary(lat, mk, rays), "per_request_launches": summary(lat_b, mk_b, rays),
+                "server_stats": stats}
+
+    main_run = run(args.serve_rate, args.serve_seconds, 55)
+    sweep = [run(float(r), args.serve_sweep_seconds, 56 + k)
+             for k, r in enumerate(x for x in args.serve_sweep.split(",") if x)]
     print(json.dumps({
         "metric": "serving: p50/p99 request latency and rays/s",
-        "value": srv_sum["p99_ms"], "unit": "ms (p99)", "higher_is_better": False, "n_gpus": 1,
+        "value": main_run["server"]["p99_ms"], "unit": "ms (p99)", "higher_is_better": False, "n_gpus": 1,
         "data": "synthetic",
         "config": {"workload": "%d resident light fields (%s); %d Poisson requests at %.0f/s; resolutions "
-                               "256^2/512^2/1920x1080/2048^2" % (len(fields), args.serve_fields, n, args.serve_rate),
-                   "offered_grays_per_s": round(rays / arrival[-1] / 1e9, 4)},
-        "server": srv_sum, "per_request_launches": base_sum, "server_stats": stats,
+                               "256^2/512^2/1920x1080/2048^2" % (len(fields), args.serve_fields, main_run["requests"],
+                                                                 args.serve_rate),
+                   "offered_grays_per_s": main_run["offered_grays_per_s"]},
+        "server": main_run["server"], "per_request_launches": main_run["per_request_launches"],
+        "server_stats": main_run["server_stats"], "sweep": sweep,
+    }), flush=True)
+
+
+def grad_bench(args):
+    """Relaxed forward render and its adjoint (gradients w.r.t. every residual
+    value and every block shift) for the 16-view 512x512 differentiation
+    workload; the loss gradient is 2 (render - target) against the integer
+    decoder's render of the same views."""
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+
+    cfg = lfscene.get_config("grad512")
+    L = cfg["lf"]
+    t0 = time.time()
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+    del light
+    log("grad field: %d bytes, %.1fs" % (stream.size, time.time() - t0))
+    field = lf.LightField(stream, device="cuda:0")
+    cams_np = lfscene.make_views(cfg)
+    V, wo, ho = cams_np.shape[0], cfg["views"]["wo"], cfg["views"]["ho"]
+    cams = torch.from_numpy(cams_np).cuda()
+    res, sh = field.export_params()
+    sh = torch.floor(sh * 4.0) / 4.0 + 0.125
+    target = field.render_views(cams, wo, ho)
+    s = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        for _ in range(args.steps):
+            r = fn()
+        b.record(s)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / args.steps, r
+
+    fwd_ms, out = timed(lambda: field.render_relaxed(res, sh, cams, wo, ho))
+    g = 2.0 * (out - target)
+    bwd_ms, (g_res, g_sh) = timed(lambda: field.render_backward(res, sh, cams, wo, ho, g))
+    rays = V * wo * ho
+    print(json.dumps({
+        "metric": "relaxed render + adjoint: rays/s through forward and backward",
+        "value": round(rays / ((fwd_ms + bwd_ms) * 1e-3) / 1e9, 4), "unit": "Grays/s", "higher_is_better": True,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "17x17x512x512 field, 16 orbit views of 512x512; gradients w.r.t. %d residual "
+                               "values and %d block shifts" % (res.numel(), sh.shape[0])},
+        "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
+        "gradient_bytes": int((res.numel() + sh.numel()) * 4),
+        "nonzero_residual_grads": int((g_res != 0).sum().item()),
     }), flush=True)
 
 

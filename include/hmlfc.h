@@ -270,7 +270,9 @@ typedef struct {
 
 /* host_lf: host uint8 [nb][na][height][width][3] RGB.  On success
  * *out_stream is a malloc'ed stream of *out_bytes bytes, released with
- * lf_encode_free.  threads <= 0 uses the OpenMP default.  Errors: LF_EINVAL
+ * lf_encode_free.  threads <= 0 uses the OpenMP default.  With the
+ * environment variable HMLFC_ENCODE_PROGRESS=1 it prints a line on stderr
+ * after every tenth of each level's predictive blocks.  Errors: LF_EINVAL
  * (geometry, parameters, or values outside the stream's integer ranges). */
 lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
                     const lf_encode_params* params, int32_t threads, uint8_t** out_stream, size_t* out_bytes);

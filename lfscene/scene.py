@@ -199,10 +199,13 @@ def render_view(scene: dict, b: int, a: int, h: int, w: int) -> np.ndarray:
     return img
 
 
-def make_lf(na: int, nb: int, h: int, w: int, spec: dict, seed: int) -> np.ndarray:
-    """Seeded light field ``uint8[nb][na][h][w][3]``; colour quantised as floor(c + 1/2)."""
+def make_lf(na: int, nb: int, h: int, w: int, spec: dict, seed: int, progress=None) -> np.ndarray:
+    """Seeded light field ``uint8[nb][na][h][w][3]``; colour quantised as floor(c + 1/2).
+
+    ``progress(done, total)``, if given, is called after every tenth of the views."""
     scene = make_scene_layers(spec, h, w, na, nb, seed)
     out = np.empty((nb, na, h, w, 3), dtype=np.uint8)
+    total = nb * na
 
     def one(idx):
         b, a = divmod(idx, na)
@@ -212,5 +215,7 @@ def make_lf(na: int, nb: int, h: int, w: int, spec: dict, seed: int) -> np.ndarr
     # Views are independent; numpy releases the GIL inside its kernels.
     workers = min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(max_workers=workers) as ex:
-        list(ex.map(one, range(nb * na)))
+        for k, _ in enumerate(ex.map(one, range(total))):
+            if progress is not None and (k + 1) % max(1, total // 10) == 0:
+                progress(k + 1, total)
     return out

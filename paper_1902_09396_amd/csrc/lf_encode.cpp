@@ -23,6 +23,7 @@
 
 #include <atomic>
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -238,6 +239,9 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
         if (prm->step[l] < 1 || prm->step[l] > 4096 || prm->win[l] < 0 || prm->win[l] > 255)
             return lf_fail(LF_EINVAL, "bad step/window");
     if (threads > 0) omp_set_num_threads(threads);
+    // HMLFC_ENCODE_PROGRESS=1: a line on stderr after every tenth of a level's predictive blocks
+    const char* pe = getenv("HMLFC_ENCODE_PROGRESS");
+    const bool progress = pe && atoi(pe) != 0;
     int na_l[LF_MAX_LEVELS + 1], nb_l[LF_MAX_LEVELS + 1];
     na_l[0] = na;
     nb_l[0] = nb;
@@ -364,8 +368,14 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
             for (int A = 0; A < nal; A++)
                 if ((A | B) & 1) pnodes.push_back(B * nal + A);
         const int64_t items = 3 * npred[l];
+        std::atomic<int64_t> done{0};
 #pragma omp parallel for schedule(dynamic, 8)
         for (int64_t it = 0; it < items; it++) {
+            if (progress && items >= 10) {
+                const int64_t d = done.fetch_add(1) + 1;
+                if (d % (items / 10) == 0)
+                    fprintf(stderr, "encode: level %d, %lld of %lld predictive blocks\n", l, (long long)d, (long long)items);
+            }
             const int c = (int)(it / npred[l]);
             const int64_t j = it % npred[l];
             const int v = pnodes[(size_t)(j / nblk)];

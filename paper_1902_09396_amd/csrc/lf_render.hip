@@ -14,6 +14,7 @@
 // Blending works on unscaled 8-bit values and scales by 1/255 at the end.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "lf_render_tile.h"
@@ -67,52 +68,55 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
 }
 
 // Per-ray rendering of the (view, tile) pairs the batched kernel marked.
-// Each thread checks one pair; the workgroup then renders its marked pairs.
+// Workgroup b owns pairs [b * per_wg, (b + 1) * per_wg): it checks up to NT
+// of them at once (one per thread), compacts the marked ones, and renders
+// them one tile at a time, so a launch whose views are mostly marked (tiles
+// far minified) still spreads them over the whole grid.
 __global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
-                                                        int wo, int ho, int tiles_x, int tiles_y,
+                                                        int wo, int ho, int tiles_x, int tiles_y, int per_wg,
                                                         float* __restrict__ out)
 {
     __shared__ int marked[NT];
-    __shared__ int n_marked;
+    __shared__ int wcount[NT / 64];
     const int64_t n_pairs = (int64_t)nv * tiles_x * tiles_y;
     const int64_t npix = (int64_t)wo * ho;
-    const int64_t pr = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (threadIdx.x == 0) n_marked = 0;
-    __syncthreads();
-    int mine = 0;
-    if (pr < n_pairs) {
-        const int v = (int)(pr / ((int64_t)tiles_x * tiles_y));
-        const int tt = (int)(pr - (int64_t)v * tiles_x * tiles_y);
-        const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
-        mine = __float_as_uint(out[(int64_t)v * 3 * npix + (int64_t)(tyi * TH) * wo + txi * TW]) == FALLBACK_MARK;
-    }
-    // compact the marked pairs of this workgroup in thread order
-    const uint64_t bal = __ballot(mine);
+    const int64_t begin = (int64_t)blockIdx.x * per_wg;
+    const int64_t end = min(begin + per_wg, n_pairs);
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __shared__ int wcount[NT / 64];
-    if (lane == 0) wcount[wid] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int w = 0; w < wid; w++) off += wcount[w];
-    if (mine) marked[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)threadIdx.x;
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < NT / 64; w++) t += wcount[w];
-        n_marked = t;
-    }
-    __syncthreads();
-    for (int k = 0; k < n_marked; k++) {
-        const int64_t q = (int64_t)blockIdx.x * NT + marked[k];
-        const int v = (int)(q / ((int64_t)tiles_x * tiles_y));
-        const int tt = (int)(q - (int64_t)v * tiles_x * tiles_y);
-        const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
-        const int i = txi * TW + (int)threadIdx.x % TW, j = tyi * TH + (int)threadIdx.x / TW;
-        if (i < wo && j < ho) {
-            float o[3];
-            lf_render_one(g, p, cams + 18 * v, i, j, o);
-#pragma unroll
-            for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + (int64_t)j * wo + i] = o[c];
+    for (int64_t base = begin; base < end; base += NT) {
+        const int64_t pr = base + threadIdx.x;
+        int mine = 0;
+        if (pr < end) {
+            const int v = (int)(pr / ((int64_t)tiles_x * tiles_y));
+            const int tt = (int)(pr - (int64_t)v * tiles_x * tiles_y);
+            const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
+            mine = __float_as_uint(out[(int64_t)v * 3 * npix + (int64_t)(tyi * TH) * wo + txi * TW]) == FALLBACK_MARK;
         }
+        // compact the marked pairs in thread order
+        const uint64_t bal = __ballot(mine);
+        if (lane == 0) wcount[wid] = __popcll(bal);
+        __syncthreads();
+        int off = 0, total = 0;
+        for (int w = 0; w < NT / 64; w++) {
+            off += w < wid ? wcount[w] : 0;
+            total += wcount[w];
+        }
+        if (mine) marked[off + __popcll(bal & ((1ull << lane) - 1ull))] = (int)threadIdx.x;
+        __syncthreads();
+        for (int k = 0; k < total; k++) {
+            const int64_t q = base + marked[k];
+            const int v = (int)(q / ((int64_t)tiles_x * tiles_y));
+            const int tt = (int)(q - (int64_t)v * tiles_x * tiles_y);
+            const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
+            const int i = txi * TW + (int)threadIdx.x % TW, j = tyi * TH + (int)threadIdx.x / TW;
+            if (i < wo && j < ho) {
+                float o[3];
+                lf_render_one(g, p, cams + 18 * v, i, j, o);
+#pragma unroll
+                for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + (int64_t)j * wo + i] = o[c];
+            }
+        }
+        __syncthreads();  // marked[] and wcount[] are rewritten by the next round
     }
 }
 
@@ -161,9 +165,13 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     }
     hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
                        d_cams, nv, wo, ho, tx, ty, chunk, fpg, d_out);
+    // marked pairs: at most 8192 workgroups, each checking a contiguous range
     const int64_t pairs = (int64_t)tx * ty * nv;
-    hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)((pairs + NT - 1) / NT)), dim3(NT), 0, s, h->L.g, h->p, d_cams,
-                       nv, wo, ho, tx, ty, d_out);
+    const int64_t fb_grid = std::min<int64_t>(pairs, 8192);
+    const int64_t per_wg = (pairs + fb_grid - 1) / fb_grid;
+    if (per_wg > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
+    hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)fb_grid), dim3(NT), 0, s, h->L.g, h->p, d_cams, nv, wo, ho, tx,
+                       ty, (int)per_wg, d_out);
     return lf_check_launch("render_batch");
 }
 

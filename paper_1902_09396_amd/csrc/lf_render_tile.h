@@ -415,10 +415,13 @@ struct TileLds {
 
 // Render screen tile (txi, tyi) of views v0 .. v0 + nf - 1 (cameras cams[v],
 // output out[v][3][ho][wo]; nf <= FMAX), in groups of at most gmax
-// consecutive views.  Every thread of the workgroup calls it; LDS contents do
-// not carry over between calls.
+// consecutive views.  A single view whose tile footprint exceeds the LDS
+// budget is rendered ray by ray here (INLINE_FALLBACK) or left with
+// FALLBACK_MARK at the tile origin for a per-ray pass; the return value says
+// whether any view was left so (the same in every thread).  Every thread of
+// the workgroup calls it; LDS contents do not carry over between calls.
 template <bool INLINE_FALLBACK>
-__device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
+__device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
                               int gmax, int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
 {
     uint4* desc = S.desc;
@@ -508,6 +511,7 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
     }
 
     const int64_t npix_out = (int64_t)wo * ho;
+    bool left = false;
     int f = 0, n = gmax;
     while (f < nf) {
         n = min(n, nf - f);
@@ -699,10 +703,12 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 if (live)
 #pragma unroll
                     for (int c = 0; c < 3; c++) out[((int64_t)(v0 + f) * 3 + c) * npix_out + (int64_t)j * wo + i] = o[c];
-            } else if (threadIdx.x == 0) {
+            } else {
                 // one view whose footprint exceeds the budget: leave a marker for the per-ray pass
-                out[((int64_t)(v0 + f) * 3) * npix_out + (int64_t)(tyi * TH) * wo + txi * TW] =
-                    __uint_as_float(FALLBACK_MARK);
+                left = true;
+                if (threadIdx.x == 0)
+                    out[((int64_t)(v0 + f) * 3) * npix_out + (int64_t)(tyi * TH) * wo + txi * TW] =
+                        __uint_as_float(FALLBACK_MARK);
             }
             f += 1;
             n = gmax;
@@ -867,5 +873,6 @@ __device__ void lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         f += n;
         n = gmax;
     }
+    return left;
 }
 

@@ -20,6 +20,8 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -44,10 +46,14 @@ struct ServeWork {  // one tile of one request
 
 }  // namespace
 
+// Work buffer of one launch (int32): [0] = item count n, [1 .. 1 + 3 max)
+// = items, [1 + 3 max] = count of tiles left for the per-ray pass, then
+// their item indices.
+__host__ __device__ inline size_t serve_fb_off(int max_tiles) { return 1 + 3 * (size_t)max_tiles; }
+
 __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ geoms, const LfPtrs* __restrict__ ptrs,
-                                                    const ServeSlot* __restrict__ slots,
-                                                    const int32_t* __restrict__ work /* [0] = count, then items */,
-                                                    uint8_t* __restrict__ pool)
+                                                    const ServeSlot* __restrict__ slots, int32_t* __restrict__ work,
+                                                    int max_tiles, uint8_t* __restrict__ pool)
 {
     TILE_LDS_DECL
     __shared__ LfGeom sg;
@@ -61,7 +67,9 @@ __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ g
         const ServeWork it = items[w];
         const ServeSlot* sl = slots + it.slot;
         const int field = sl->field;
-        if (field != cur_field) {
+        const bool change = field != cur_field;  // uniform: cur_field only changes after the barrier below
+        __syncthreads();
+        if (change) {
             // stage the light field's geometry in LDS (uniform branch)
             const uint32_t* src = reinterpret_cast<const uint32_t*>(geoms + field);
             uint32_t* dst = reinterpret_cast<uint32_t*>(&sg);
@@ -72,8 +80,38 @@ __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ g
             }
             __syncthreads();
         }
-        lf_tile_views<true>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
-                            reinterpret_cast<float*>(pool + sl->out_off), S);
+        const bool left = lf_tile_views<false>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
+                                               reinterpret_cast<float*>(pool + sl->out_off), S);
+        if (left && threadIdx.x == 0) {
+            int32_t* fb = work + serve_fb_off(max_tiles);
+            fb[1 + atomicAdd(fb, 1)] = w;
+        }
+    }
+}
+
+// Per-ray rendering of the tiles the tile kernel left (footprint beyond the
+// LDS budget): one workgroup per tile, one thread per ray.
+__global__ void __launch_bounds__(NT) k_serve_fallback(const LfGeom* __restrict__ geoms,
+                                                       const LfPtrs* __restrict__ ptrs,
+                                                       const ServeSlot* __restrict__ slots,
+                                                       const int32_t* __restrict__ work, int max_tiles,
+                                                       uint8_t* __restrict__ pool)
+{
+    const int32_t* fb = work + serve_fb_off(max_tiles);
+    const int nfb = fb[0];
+    const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
+    for (int k = blockIdx.x; k < nfb; k += gridDim.x) {
+        const ServeWork it = items[fb[1 + k]];
+        const ServeSlot* sl = slots + it.slot;
+        const int i = it.tx * TW + (int)threadIdx.x % TW, j = it.ty * TH + (int)threadIdx.x / TW;
+        if (i < sl->wo && j < sl->ho) {
+            float o[3];
+            lf_render_one(geoms[sl->field], ptrs[sl->field], sl->cam, i, j, o);
+            float* out = reinterpret_cast<float*>(pool + sl->out_off);
+            const int64_t npix = (int64_t)sl->wo * sl->ho;
+#pragma unroll
+            for (int c = 0; c < 3; c++) out[c * npix + (int64_t)j * sl->wo + i] = o[c];
+        }
     }
 }
 
@@ -131,7 +169,7 @@ struct PoolAlloc {
 struct StreamCtx {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
-    int32_t* h_work = nullptr;  // pinned: count + items
+    int32_t* h_work = nullptr;  // pinned: count + items + zero fallback count (serve_fb_off)
     int32_t* d_work = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -172,12 +210,15 @@ struct lf_server {
 
 static lf_status capture_graph(lf_server* S, StreamCtx& sc)
 {
-    const size_t wbytes = sizeof(int32_t) * (1 + 3 * (size_t)S->cfg.max_tiles);
+    // upload the whole list and the zero fallback count (no memset node in the graph)
+    const size_t wbytes = sizeof(int32_t) * (serve_fb_off(S->cfg.max_tiles) + 1);
     if (hipStreamBeginCapture(sc.s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return lf_fail(LF_EDEVICE, "stream capture failed");
     hipMemcpyAsync(sc.d_work, sc.h_work, wbytes, hipMemcpyHostToDevice, sc.s);
     hipLaunchKernelGGL(k_serve_tiles, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs, S->d_slots,
-                       sc.d_work, S->pool);
+                       sc.d_work, S->cfg.max_tiles, S->pool);
+    hipLaunchKernelGGL(k_serve_fallback, dim3(S->grid), dim3(NT), 0, sc.s, S->d_geoms, S->d_ptrs, S->d_slots,
+                       sc.d_work, S->cfg.max_tiles, S->pool);
     if (hipStreamEndCapture(sc.s, &sc.graph) != hipSuccess) return lf_fail(LF_EDEVICE, "end capture failed");
     if (hipGraphInstantiate(&sc.exec, sc.graph, nullptr, nullptr, 0) != hipSuccess)
         return lf_fail(LF_EDEVICE, "graph instantiate failed");
@@ -213,9 +254,13 @@ bool lf_server::launch(StreamCtx& sc)
     if (cfg.use_graphs) {
         hipGraphLaunch(sc.exec, sc.s);
     } else {
+        const size_t fo = serve_fb_off(cfg.max_tiles);
         hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
+        hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
         hipLaunchKernelGGL(k_serve_tiles, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs, d_slots,
-                           sc.d_work, pool);
+                           sc.d_work, cfg.max_tiles, pool);
+        hipLaunchKernelGGL(k_serve_fallback, dim3(grid), dim3(NT), 0, sc.s, d_geoms, d_ptrs, d_slots, sc.d_work,
+                           cfg.max_tiles, pool);
     }
     hipEventRecord(sc.ev, sc.s);
     sc.busy = true;
@@ -326,7 +371,7 @@ extern "C" lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields
         hipMemcpy(S->d_geoms, S->geoms.data(), sizeof(LfGeom) * n_fields, hipMemcpyHostToDevice);
         hipMemcpy(S->d_ptrs, S->ptrs.data(), sizeof(LfPtrs) * n_fields, hipMemcpyHostToDevice);
     }
-    const size_t wbytes = sizeof(int32_t) * (1 + 3 * (size_t)cfg->max_tiles);
+    const size_t wbytes = sizeof(int32_t) * (serve_fb_off(cfg->max_tiles) + 1 + (size_t)cfg->max_tiles);
     S->streams.resize(cfg->n_streams);
     for (StreamCtx& sc : S->streams) {
         if (!ok) break;
@@ -441,8 +486,16 @@ extern "C" lf_status lf_server_destroy(lf_server* S)
 
 // ---------------------------------------------------------------------------
 // Open-loop replay of a request schedule, and the one-launch-per-request
-// baseline on the same schedule (both measure latency from arrival).
+// baseline on the same schedule (both measure latency from arrival).  With
+// HMLFC_SERVE_PROGRESS=1 both print a line on stderr after every tenth of
+// the requests.
 // ---------------------------------------------------------------------------
+
+static bool serve_progress()
+{
+    const char* e = getenv("HMLFC_SERVE_PROGRESS");
+    return e && atoi(e) != 0;
+}
 
 extern "C" lf_status lf_server_replay(lf_server* S, int64_t n, const int32_t* field, const float* cams,
                                       const int32_t* wh, const double* arrival_s, double* latency_ms,
@@ -466,7 +519,11 @@ extern "C" lf_status lf_server_replay(lf_server* S, int64_t n, const int32_t* fi
     });
     lf_status st = LF_OK;
     Clock::time_point last = t0;
+    const bool progress = serve_progress();
     for (int64_t k = 0; k < n; k++) {
+        if (progress && n >= 10 && k > 0 && k % (n / 10) == 0)
+            fprintf(stderr, "replay: %lld of %lld requests done, %.1f s\n", (long long)k, (long long)n,
+                    std::chrono::duration<double>(Clock::now() - t0).count());
         int64_t id;
         while ((id = ids[(size_t)k].load()) == 0) std::this_thread::sleep_for(std::chrono::microseconds(20));
         if (id < 0) {
@@ -504,7 +561,11 @@ extern "C" lf_status lf_serve_baseline(lf_handle* const* fields, int32_t n_field
     lf_status st = LF_OK;
     const auto t0 = Clock::now();
     Clock::time_point last = t0;
+    const bool progress = serve_progress();
     for (int64_t k = 0; k < n && st == LF_OK; k++) {
+        if (progress && n >= 10 && k > 0 && k % (n / 10) == 0)
+            fprintf(stderr, "baseline: %lld of %lld requests done, %.1f s\n", (long long)k, (long long)n,
+                    std::chrono::duration<double>(Clock::now() - t0).count());
         const auto arrive = t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[k]));
         std::this_thread::sleep_until(arrive);
         if (field[k] < 0 || field[k] >= n_fields || (int64_t)3 * wh[2 * k] * wh[2 * k + 1] * 4 > out_bytes) {
