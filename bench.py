@@ -159,8 +159,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i32+f32",
-        "views_per_group": lf.render_config()[0],
-        "views_per_chunk": lf.render_config()[1],
+        "views_per_group": lf.render_config(V, wo, ho)[0],
+        "views_per_chunk": lf.render_config(V, wo, ho)[1],
         "data": "synthetic",
         "config": {
             "workload": "%dx%d views of %dx%d RGB, %d-level tree, %dx%d blocks, step %d, quarter-pel MVs; "

@@ -127,12 +127,16 @@ lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t 
 lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                           int32_t height, float* d_out, void* stream);
 
-/* Launch configuration lf_render_views uses: views decoded together per
- * group, and views per workgroup chunk (decoded samples are kept in LDS
- * between the groups of a chunk).  Read once from the environment variables
- * HMLFC_VIEWS_PER_GROUP and HMLFC_VIEWS_PER_CHUNK (1..32) at first use.
- * Either pointer may be NULL. */
-lf_status lf_get_render_config(int32_t* views_per_group, int32_t* views_per_chunk);
+/* Launch configuration lf_render_views uses for n_views views of
+ * width x height: views decoded together per group, and views per workgroup
+ * chunk (decoded samples are kept in LDS between the groups of a chunk).
+ * The group size is HMLFC_VIEWS_PER_GROUP (1..64, default 10); the chunk is
+ * HMLFC_VIEWS_PER_CHUNK (1..64) if set, else as long as the launch keeps
+ * about 2048 workgroups of 32x8-pixel tiles (at most 64 views, balanced).
+ * Both variables are read once, at first use.  Either pointer may be NULL;
+ * LF_EINVAL for sizes below 1. */
+lf_status lf_get_render_config(int32_t n_views, int32_t width, int32_t height, int32_t* views_per_group,
+                               int32_t* views_per_chunk);
 
 /* The same rendering with one thread per ray and no staging (every ray walks
  * its 16 samples' tree paths itself).  Same arguments and results as

@@ -134,16 +134,25 @@ static int frames_per_group()
     static int v = env_int("HMLFC_VIEWS_PER_GROUP", 10, 1, FMAX);
     return v;
 }
-static int frames_per_chunk()
+// views per chunk: HMLFC_VIEWS_PER_CHUNK if set, else chunks as long as
+// possible while the launch still has about 2048 workgroups (balanced, at
+// most FMAX views each)
+static int frames_per_chunk(int nv, int tiles)
 {
-    static int v = env_int("HMLFC_VIEWS_PER_CHUNK", 30, 1, FMAX);
-    return v;
+    static int v = env_int("HMLFC_VIEWS_PER_CHUNK", 0, 0, FMAX);
+    if (v > 0) return v;
+    int64_t n_chunks = std::min<int64_t>(nv, std::max<int64_t>(1, (2048 + tiles - 1) / std::max(tiles, 1)));
+    n_chunks = std::max<int64_t>(n_chunks, (nv + FMAX - 1) / FMAX);
+    return (int)((nv + n_chunks - 1) / n_chunks);
 }
 
-extern "C" lf_status lf_get_render_config(int32_t* views_per_group, int32_t* views_per_chunk)
+extern "C" lf_status lf_get_render_config(int32_t n_views, int32_t width, int32_t height, int32_t* views_per_group,
+                                          int32_t* views_per_chunk)
 {
+    if (n_views < 1 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    const int tiles = ((width + TW - 1) / TW) * ((height + TH - 1) / TH);
     if (views_per_group) *views_per_group = frames_per_group();
-    if (views_per_chunk) *views_per_chunk = max(frames_per_chunk(), frames_per_group());
+    if (views_per_chunk) *views_per_chunk = frames_per_chunk(n_views, tiles);
     return LF_OK;
 }
 
@@ -151,7 +160,7 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
                                  hipStream_t s)
 {
     const int tx = (wo + TW - 1) / TW, ty = (ho + TH - 1) / TH;
-    const int fpg = frames_per_group(), chunk = max(frames_per_chunk(), fpg);
+    const int fpg = frames_per_group(), chunk = frames_per_chunk(nv, tx * ty);
     const int64_t n_work = (int64_t)tx * ty * ((nv + chunk - 1) / chunk);
     const int64_t grid = ((n_work + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");

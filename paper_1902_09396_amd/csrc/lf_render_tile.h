@@ -71,7 +71,7 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
 #define TW 32
 #define TH 8
 #define NT (TW * TH)
-#define FMAX 32          // views per workgroup (upper bound of the group size)
+#define FMAX 64          // views per workgroup chunk (4 FMAX <= NT: phase 0 gives each view 4 lanes)
 #define LMAX 64          // nodes of one level inside a group's bounding rectangle
 #define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
 #define SLOT_MAX 192  // staged channel planes decoded for one group (3 x CMAX)
@@ -201,19 +201,12 @@ __device__ __forceinline__ uint32_t lf_pack_lo(uint32_t a, uint32_t b)
     return __builtin_amdgcn_perm(b, a, 0x05040100u);
 }
 
-// n-bit field at bit o of a 96-bit window (o + n <= 96)
-__device__ __forceinline__ uint32_t lf_win_field(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t o, uint32_t n)
-{
-    const bool c1 = o >= 32u, c2 = o >= 64u;
-    const uint32_t lo = c2 ? w2 : (c1 ? w1 : w0);
-    const uint32_t hi = c1 ? w2 : w1;
-    return __builtin_amdgcn_alignbit(hi, lo, o & 31u) & ((1u << n) - 1u);
-}
-
 // Values i0 .. i0 + 3 of a block (i0 a multiple of 4).  They lie in at most
-// two groups (plain bits: four one-value groups); when those fit in one
-// 96-bit window of the payload (always for b <= 8 bits per value), it is read
-// once and every field is cut from it, else each value is read on its own.
+// two groups (plain bits: four one-value groups).  When those span at most 64
+// bits (always for b <= 4 bits per value, and for every plain-bits block
+// up to 16), three payload words are read once, shifted so that the first
+// group starts at bit 0 of one 64-bit word, and every field is cut from it
+// with one shift and mask; otherwise each value is read on its own.
 __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i0,
                                              const uint32_t* __restrict__ tab, uint32_t (&v)[4])
 {
@@ -225,19 +218,19 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
     const uint32_t g0 = fam == 0u ? i0 : __umulhi(i0, mg);
     const uint32_t pat = tab[LF_TAB_QUAD + 5u * fam + (i0 - __umul24(g0, gs))];
     const uint32_t first = __umul24(g0, gl);
-    const uint32_t wb = first & ~31u;
-    const uint32_t o0 = first - wb;
+    const uint32_t o0 = first & 31u;
     const uint32_t* q = w + (first >> 5);
     const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
-    if (o0 + __umul24(((pat >> 15) & 3u) + 1u, gl) <= 96u) {  // end of the last value's group
+    const uint64_t X = ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, o0) << 32) | __builtin_amdgcn_alignbit(w1, w0, o0);
+    if (__umul24(((pat >> 15) & 3u) + 1u, gl) <= 64u) {  // end of the last value's group
         const uint32_t tb = fam == 2u ? 256u : 0u;
-        const uint32_t d0 = tab[tb + lf_win_field(w0, w1, w2, o0, hb)];
-        const uint32_t d1 = tab[tb + lf_win_field(w0, w1, w2, o0 + gl, hb)];
-        const uint32_t base = o0 + hb;
+        const uint32_t hm = (1u << hb) - 1u, bm = (1u << b) - 1u;
+        const uint32_t d0 = tab[tb + ((uint32_t)X & hm)];
+        const uint32_t d1 = tab[tb + ((uint32_t)(X >> (gl & 63u)) & hm)];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const uint32_t dk = (pat >> (5 * k)) & 3u, kk = (pat >> (5 * k + 2)) & 7u;
-            const uint32_t lo = lf_win_field(w0, w1, w2, base + __umul24(dk, gl) + __umul24(kk, b), b);
+            const uint32_t lo = (uint32_t)(X >> ((hb + __umul24(dk, gl) + __umul24(kk, b)) & 63u)) & bm;
             const uint32_t dig = dk != 0u ? d1 : d0;
             v[k] = (((dig >> (4u * kk)) & 15u) << b) | lo;
         }

@@ -45,7 +45,7 @@ SIGNATURES = {
     "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
     "lf_render_views": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_render_views_per_ray": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
-    "lf_get_render_config": (C.c_int, [_P, _P]),
+    "lf_get_render_config": (C.c_int, [_I32, _I32, _I32, _P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_export_params": (C.c_int, [_P, _P, _P, _P]),
@@ -211,10 +211,10 @@ class LightField:
         return out
 
 
-def render_config() -> tuple[int, int]:
-    """(views decoded per group, views per workgroup chunk) of render_views."""
+def render_config(n_views: int, width: int, height: int) -> tuple[int, int]:
+    """(views decoded per group, views per workgroup chunk) render_views uses for n_views views."""
     g, c = C.c_int32(), C.c_int32()
-    check(lib().lf_get_render_config(C.byref(g), C.byref(c)))
+    check(lib().lf_get_render_config(n_views, width, height, C.byref(g), C.byref(c)))
     return g.value, c.value
 
 
