@@ -88,11 +88,16 @@ typedef struct {
 lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_bytes);
 
 /* Validate the stream completely on the host, copy it into the caller's
- * device arena (d_arena, arena_bytes >= lf_query_arena) and decode every
- * reference SRV into resident int16 planes.  The handle borrows d_arena
- * until lf_free; host_stream may be released when the call returns (the
- * copy is complete on return).  Errors: LF_EINVAL, LF_EFORMAT (any header
- * field, section size or block offset out of range), LF_ENOMEM (arena too
+ * device arena (d_arena, 256-byte aligned, arena_bytes >= lf_query_arena),
+ * decode every reference SRV into resident int16 planes and expand every
+ * block's table entry and motion vector into a 16-byte descriptor (Decoding
+ * Procedure; Decompression Memory Overhead).  Arena sections, 256-byte
+ * aligned: root, block table, payload, motion vectors, reference planes,
+ * descriptors, 256-byte status.  The handle borrows d_arena until lf_free;
+ * host_stream may be released when the call returns (the copy is complete
+ * on return).  Errors: LF_EINVAL, LF_EFORMAT (any header field, section
+ * size or block offset out of range, or a decoded reference SRV beyond
+ * +-2047, which no stream of 8-bit content produces), LF_ENOMEM (arena too
  * small), LF_EDEVICE. */
 lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
                              void* stream, lf_handle** out);
@@ -118,8 +123,9 @@ lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t 
 /* Novel-view rendering fused with decoding (Random Access for             */
 /* Interactive Rendering; two-plane interpolation of Light Field           */
 /* Rendering).  Each ray's (u, v, s, t) is clamped to the grid; the 16     */
-/* neighbouring samples are decoded and blended quadrilinearly in FP32     */
-/* (s, then t, then u, then v) after scaling to [0, 1].                    */
+/* neighbouring samples are decoded and blended quadrilinearly in FP32:    */
+/* per neighbouring view the (s, t) bilinear sum, then the (u, v) bilinear */
+/* sum of the four, scaled to [0, 1] at the end.                           */
 /* ---------------------------------------------------------------------- */
 
 /* d_cams: device float [n_views][18].  d_out: device float

@@ -2,6 +2,8 @@
 // per-ray reference renderer, behind the C ABI of include/hmlfc.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -163,15 +165,18 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
             rec += expect;
         }
     L->n_rec = rec;
-    // arena: [root][table][payload][mv][refs][status], 256-byte aligned; the
-    // 256-byte status tail also keeps the multi-word loads at the end of the
-    // reference planes inside the arena
+    // arena: [root][table][payload][mv][refs][desc][status], 256-byte
+    // aligned; desc holds one 16-byte block descriptor per (channel, node,
+    // block), expanded from the table and motion vectors at load; the status
+    // tail keeps the multi-word loads at the end of the last section inside
+    // the arena
     L->a_root = 0;
     L->a_table = align256(L->a_root + (int64_t)L->root_bytes);
     L->a_payload = align256(L->a_table + (int64_t)L->table_bytes);
     L->a_mv = align256(L->a_payload + (int64_t)L->payload_bytes);
     L->a_refs = align256(L->a_mv + (int64_t)L->mv_bytes);
-    L->a_status = align256(L->a_refs + 3 * refs * plane * 2);
+    L->a_desc = align256(L->a_refs + 3 * refs * plane * 2);
+    L->a_status = align256(L->a_desc + 3 * nodes * (int64_t)g.nblk * 16);
     L->arena = L->a_status + 256;
     L->stream_bytes = (int64_t)n;
     return LF_OK;
@@ -220,6 +225,21 @@ __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int*
     if (bad) atomicOr(status, 1);
 }
 
+// Block descriptors of every (channel, node, block), BFS node order.
+__global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc)
+{
+    const int64_t total = 3 * (int64_t)g.n_nodes * g.nblk;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int blk = (int)(t % g.nblk);
+        const int node = (int)((t / g.nblk) % g.n_nodes);
+        const int c = (int)(t / ((int64_t)g.nblk * g.n_nodes));
+        int l = 0;
+        while (l + 1 < g.H && node < g.node_base[l]) l++;  // levels are stored H-1 first
+        const int local = node - g.node_base[l];
+        desc[t] = lf_make_desc(g, p, c, l, local / g.na_l[l], local % g.na_l[l], blk);
+    }
+}
+
 extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
                                         void* stream, lf_handle** out)
 {
@@ -253,6 +273,7 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
     h->p.payload = (const uint32_t*)(A + L.a_payload);
     h->p.mv = (const uint32_t*)(A + L.a_mv);
     h->p.refs = (const int16_t*)(A + L.a_refs);
+    h->p.desc = (const uint4*)(A + L.a_desc);
     const int64_t total = 3 * (int64_t)L.g.n_refs * L.g.w * L.g.h;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -265,6 +286,16 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
         hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs,
                            status);
         st = lf_check_launch("load_refs");
+        if (st != LF_OK) {
+            delete h;
+            return st;
+        }
+    }
+    {
+        const int64_t nd = 3 * (int64_t)L.g.n_nodes * L.g.nblk;
+        const int64_t dblocks = std::min<int64_t>((nd + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_load_desc, dim3((unsigned)dblocks), dim3(256), 0, s, L.g, h->p, (uint4*)(A + L.a_desc));
+        st = lf_check_launch("load_desc");
         if (st != LF_OK) {
             delete h;
             return st;

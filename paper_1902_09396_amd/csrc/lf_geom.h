@@ -36,6 +36,7 @@ struct LfPtrs {
     const uint32_t* payload;  // block payload words (+ slack)
     const uint32_t* mv;       // motion-vector section words (+ slack)
     const int16_t* refs;      // [3][n_refs][h][w] decoded reference SRVs
+    const uint4* desc;        // [3][n_nodes][nblk] block descriptors (lf_make_desc), built at load
 };
 
 // Ordinal of predictive node (B, A) among the predictive nodes of its level,
@@ -165,8 +166,31 @@ __device__ __forceinline__ void lf_ycocg_to_rgb(int Y, int Co, int Cg, int& r, i
     b = lf_clampi(b, 0, 255);
 }
 
+#define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
+
+// Block descriptor: x = payload word, y = min (16) | step (13) << 16 | phase code << 29,
+// z = mx (12, signed) | my (12, signed) << 12 | mode << 24, w = plane offset (elements)
+// of the reference plane (predictive node) or of the node's own plane (reference node).
+__device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, int blk)
+{
+    const uint32_t plane = (uint32_t)(g.w * g.h);
+    const uint32_t ref = (uint32_t)(c * g.n_refs + g.ref_base[l] + (B >> 1) * g.na_l[l + 1] + (A >> 1)) * plane;
+    if (!((A | B) & 1)) return make_uint4(0u, 0u, (uint32_t)MODE_PLANE << 24, ref);
+    const int node = g.node_base[l] + B * g.na_l[l] + A;
+    const uint2 e = p.table[((size_t)c * g.n_nodes + node) * g.nblk + blk];
+    int mx, my, sg;
+    lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
+    uint32_t mode = (e.y >> 16) & 0xFFu, word = e.x, mn = e.y & 0xFFFFu;
+    if (mode == LF_MODE_ZERO) mode = word = mn = 0u;  // insignificant: zero-bit values, minimum 0
+    const uint32_t code = sg == 1 ? 0u : (sg == -1 ? 1u : 2u);
+    return make_uint4(word, mn | ((uint32_t)g.step[l] << 16) | (code << 29),
+                      ((uint32_t)mx & 0xFFFu) | (((uint32_t)my & 0xFFFu) << 12) | (mode << 24), ref);
+}
+
 // Ray coordinates: (h0 px + h1 py) + h2 per row, each product and sum
-// rounded separately (no fused multiply-add), then one IEEE division.
+// rounded separately (no fused multiply-add), then one IEEE division.  When a
+// homography's third row is exactly (0, 0, 1) its third component is exactly 1
+// at every pixel and x / 1 == x, so it is neither formed nor divided by.
 __device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float& u, float& v, float& s, float& t)
 {
 #pragma clang fp contract(off)
@@ -174,13 +198,25 @@ __device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float
     float q[6];
 #pragma unroll
     for (int r = 0; r < 6; r++) {
+        if (r == 2 || r == 5) continue;
         const float* h = cam + (r < 3 ? 0 : 9) + 3 * (r % 3);
         float a = h[0] * px;
         float bb = h[1] * py;
         float sum = a + bb;
         q[r] = sum + h[2];
     }
-    // x / 1 == x exactly, so affine maps (third row 0 0 1) skip the divisions
+#pragma unroll
+    for (int r = 2; r < 6; r += 3) {
+        const float* h = cam + (r < 3 ? 0 : 9) + 6;
+        if (h[0] == 0.0f && h[1] == 0.0f && h[2] == 1.0f) {
+            q[r] = 1.0f;
+        } else {
+            float a = h[0] * px;
+            float bb = h[1] * py;
+            float sum = a + bb;
+            q[r] = sum + h[2];
+        }
+    }
     if (q[2] == 1.0f) {
         u = q[0];
         v = q[1];

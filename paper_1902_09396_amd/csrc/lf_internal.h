@@ -13,7 +13,7 @@ struct LfLayout {
     int64_t n_rec;        // motion records over all channels and levels
     int64_t stream_bytes;
     // arena offsets
-    int64_t a_root, a_table, a_payload, a_mv, a_refs, a_status, arena;
+    int64_t a_root, a_table, a_payload, a_mv, a_refs, a_desc, a_status, arena;
 };
 
 struct lf_handle {

@@ -6,7 +6,6 @@
 
 #include "lf_internal.h"
 
-__device__ __forceinline__ float lf_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
 struct Ray {
     int a0, a1, b0, b1, x0, x1, y0, y1;
@@ -25,14 +24,42 @@ __device__ __forceinline__ Ray lf_ray_setup(const LfGeom& g, const float* __rest
     return r;
 }
 
-// quadrilinear blend of 16 samples given as unscaled 8-bit values; order s, t, u, v
-__device__ __forceinline__ float lf_blend16(const float (&sm)[16], const Ray& r)
+// Quadrilinear blend of 16 samples given as unscaled 8-bit values (sample
+// 4 q + k: view q = (v-bit << 1 | u-bit), pixel k = (t-bit << 1 | s-bit)):
+// per view the st-bilinear sum with weights (1-fs)(1-ft), fs(1-ft), (1-fs)ft,
+// fs ft, then the uv-bilinear sum of the four, in that fixed order; scaled
+// by 1/255 at the end.
+struct BlendW {
+    float st[4], uv[4];
+};
+
+__device__ __forceinline__ BlendW lf_blend_weights(const Ray& r)
 {
-    float vw[4];
+    BlendW w;
+    const float gs = 1.0f - r.fs, gt = 1.0f - r.ft, gu = 1.0f - r.fu, gv = 1.0f - r.fv;
+    w.st[0] = gs * gt;
+    w.st[1] = r.fs * gt;
+    w.st[2] = gs * r.ft;
+    w.st[3] = r.fs * r.ft;
+    w.uv[0] = gu * gv;
+    w.uv[1] = r.fu * gv;
+    w.uv[2] = gu * r.fv;
+    w.uv[3] = r.fu * r.fv;
+    return w;
+}
+
+__device__ __forceinline__ float lf_blend16(const float (&sm)[16], const BlendW& w)
+{
+    float acc = 0.0f;
 #pragma unroll
-    for (int q = 0; q < 4; q++)
-        vw[q] = lf_lerp(lf_lerp(sm[4 * q], sm[4 * q + 1], r.fs), lf_lerp(sm[4 * q + 2], sm[4 * q + 3], r.fs), r.ft);
-    return lf_lerp(lf_lerp(vw[0], vw[1], r.fu), lf_lerp(vw[2], vw[3], r.fu), r.fv) * (1.0f / 255.0f);
+    for (int q = 0; q < 4; q++) {
+        float t = sm[4 * q] * w.st[0];
+        t = fmaf(sm[4 * q + 1], w.st[1], t);
+        t = fmaf(sm[4 * q + 2], w.st[2], t);
+        t = fmaf(sm[4 * q + 3], w.st[3], t);
+        acc = q == 0 ? t * w.uv[0] : fmaf(t, w.uv[q], acc);
+    }
+    return acc * (1.0f / 255.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -55,12 +82,13 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
         lf_ycocg_to_rgb(Y, Co, Cg, R, G, B);
         px[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
     }
+    const BlendW w = lf_blend_weights(r);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         float sm[16];
 #pragma unroll
         for (int k = 0; k < 16; k++) sm[k] = (float)((px[k] >> (8 * c)) & 255u);
-        out[c] = lf_blend16(sm, r);
+        out[c] = lf_blend16(sm, w);
     }
 }
 
@@ -73,7 +101,6 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
 #define NT (TW * TH)
 #define FMAX 64          // views per workgroup chunk (4 FMAX <= NT: phase 0 gives each view 4 lanes)
 #define LMAX 64          // nodes of one level inside a group's bounding rectangle
-#define MODE_PLANE 0xFE  // descriptor of a reference node: read its resident plane
 #define SLOT_MAX 192  // staged channel planes decoded for one group (3 x CMAX)
 #define CMAX 64       // cache entries per kind (leaf views, ancestor nodes)
 #define CKEY_EMPTY 0xFFFFFFFFu
@@ -113,25 +140,6 @@ __device__ __forceinline__ uint32_t wave_pk_max(uint32_t v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = pk_max(v, (uint32_t)__shfl_xor((int)v, o, 64));
     return v;
-}
-
-// Block descriptor: x = payload word, y = min (16) | step (13) << 16 | phase code << 29,
-// z = mx (12, signed) | my (12, signed) << 12 | mode << 24, w = plane offset (elements)
-// of the reference plane (predictive node) or of the node's own plane (reference node).
-__device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, int blk)
-{
-    const uint32_t plane = (uint32_t)(g.w * g.h);
-    const uint32_t ref = (uint32_t)(c * g.n_refs + g.ref_base[l] + (B >> 1) * g.na_l[l + 1] + (A >> 1)) * plane;
-    if (!((A | B) & 1)) return make_uint4(0u, 0u, (uint32_t)MODE_PLANE << 24, ref);
-    const int node = g.node_base[l] + B * g.na_l[l] + A;
-    const uint2 e = p.table[((size_t)c * g.n_nodes + node) * g.nblk + blk];
-    int mx, my, sg;
-    lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
-    uint32_t mode = (e.y >> 16) & 0xFFu, word = e.x, mn = e.y & 0xFFFFu;
-    if (mode == LF_MODE_ZERO) mode = word = mn = 0u;  // insignificant: zero-bit values, minimum 0
-    const uint32_t code = sg == 1 ? 0u : (sg == -1 ? 1u : 2u);
-    return make_uint4(word, mn | ((uint32_t)g.step[l] << 16) | (code << 29),
-                      ((uint32_t)mx & 0xFFFu) | (((uint32_t)my & 0xFFFu) << 12) | (mode << 24), ref);
 }
 
 // Bounded-integer value i of a block, one code path for the three families
@@ -724,7 +732,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int e = nodelist[l][k] & 0xFF;
             const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
             const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
-            desc[d] = lf_make_desc(g, p, c, l, B, A, blk);
+            const int node = g.node_base[l] + B * g.na_l[l] + A;
+            desc[d] = p.desc[((size_t)c * g.n_nodes + node) * g.nblk + blk];
         }
         for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
             int l = 1;
@@ -853,12 +862,13 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 s16[4 * k + 3] = q1[1];
             }
             if (live) {
+                const BlendW w = lf_blend_weights(r);
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     float sm[16];
 #pragma unroll
                     for (int k = 0; k < 16; k++) sm[k] = (float)((s16[k] >> (8 * c)) & 255u);
-                    out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, r);
+                    out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, w);
                 }
             }
         }
