@@ -332,6 +332,14 @@ __device__ __forceinline__ uint32_t lf_magic(uint32_t d)
 }
 __device__ __forceinline__ int lf_qdiv(int n, uint32_t m) { return m ? (int)__umulhi((uint32_t)n, m) : n; }
 
+// floor(n / d) for 0 <= n, 1 <= d, n * d < 2^20 (small node and block
+// indices): (n + 1/2) / d is at least 1/(2d) away from an integer, and one
+// rounded reciprocal and product are off by less than n * 2^-22.
+__device__ __forceinline__ int lf_div_small(int n, int d)
+{
+    return (int)(((float)n + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 // Plan of one group of views: the footprint's pixel box, and per level l
 // (0 = leaf views .. H = root) the bounding rectangle of the nodes the group
 // reaches.  Decoded values stay in LDS across the groups of one call while
@@ -547,7 +555,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             // level 0: leaf views some ray of the group reaches
             bool use0 = false;
             if (ok && lane < nA0 * nB0) {
-                const int b = bmin + lane / nA0, a = amin + lane % nA0;
+                const int qb = lf_div_small(lane, nA0), b = bmin + qb, a = amin + lane - qb * nA0;
                 for (int q = f; q < f + n && !use0; q++) {
                     const uint32_t q0 = fbox[q][0], q1 = fbox[q][1];
                     use0 = (int)(q0 >> 16) <= b && (int)(q1 >> 16) >= b && (int)(q0 & 0xFFFFu) <= a &&
@@ -608,7 +616,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 if (nB * nA > LMAX) ok = 0;
                 bool need = false;
                 if (lane < nB * nA && nB * nA <= LMAX) {
-                    const int B = B0 + lane / nA, A = A0 + lane % nA;
+                    const int qb = lf_div_small(lane, nA), B = B0 + qb, A = A0 + lane - qb * nA;
                     const int rb0 = max(B << l, bmin) - bmin, rb1 = min(((B + 1) << l) - 1, bmax) - bmin;
                     const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
                     for (int r = rb0; r <= rb1 && !need; r++)
@@ -633,7 +641,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     nodemap[0][lane] = (int8_t)ent0;
                     const int k = __popcll(newm0 & ((1ull << lane) - 1ull));
                     nodelist[0][k] = (uint16_t)(lane | (ent0 << 8));
-                    ckey[0][ent0] = lf_node_key(0, bmin + lane / nA0, amin + lane % nA0);
+                    const int qb = lf_div_small(lane, nA0);
+                    ckey[0][ent0] = lf_node_key(0, bmin + qb, amin + lane - qb * nA0);
                 }
                 int q0 = 0, sb = 0, db = 3 * nbk * nnew0;
                 if (lane == 0) gp.dbase[0] = 0;
@@ -647,7 +656,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                         const int k = __popcll(nm & ((1ull << lane) - 1ull));
                         e = lf_nth_bit(free1, q0 + k);
                         nodelist[l][k] = (uint16_t)(lane | (e << 8));
-                        ckey[1][e] = lf_node_key(l, B0 + lane / nA, A0 + lane % nA);
+                        const int qb = lf_div_small(lane, nA);
+                        ckey[1][e] = lf_node_key(l, B0 + qb, A0 + lane - qb * nA);
                         nodemap[l][lane] = (int8_t)e;
                     }
                     if (lane == 0) {
@@ -730,8 +740,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int kb = d - gp.dbase[l] - row * nbk;
             const int k = row / 3, c = row - 3 * k;
             const int e = nodelist[l][k] & 0xFF;
-            const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
-            const int blk = (bky0 + kb / nbkx) * g.nbx + bkx0 + kb % nbkx;
+            const int qb = lf_div_small(e, gp.nA[l]), B = gp.B0[l] + qb, A = gp.A0[l] + e - qb * gp.nA[l];
+            const int qk = lf_div_small(kb, nbkx), blk = (bky0 + qk) * g.nbx + bkx0 + kb - qk * nbkx;
             const int node = g.node_base[l] + B * g.na_l[l] + A;
             desc[d] = p.desc[((size_t)c * g.n_nodes + node) * g.nblk + blk];
         }
@@ -744,7 +754,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             uint32_t info;
             if (l == g.H) {
                 const int e = nl & 0xFF;
-                const int B = gp.B0[l] + e / gp.nA[l], A = gp.A0[l] + e % gp.nA[l];
+                const int qb = lf_div_small(e, gp.nA[l]), B = gp.B0[l] + qb, A = gp.A0[l] + e - qb * gp.nA[l];
                 info = 0x80000000u | (uint32_t)((c * g.root_nb + B) * g.root_na + A);
             } else {
                 info = (uint32_t)(gp.dbase[l] + row * nbk);
@@ -754,7 +764,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         }
         for (int k = threadIdx.x; k < gp.nnew[0]; k += NT) {
             const int e = nodelist[0][k] & 0xFF;
-            const int b = gp.B0[0] + e / gp.nA[0], a = gp.A0[0] + e % gp.nA[0];
+            const int qb = lf_div_small(e, gp.nA[0]), b = gp.B0[0] + qb, a = gp.A0[0] + e - qb * gp.nA[0];
             for (int l = 1; l <= g.H; l++) {
                 const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
                 ancs[k][l - 1] = (uint8_t)(3 * nodemap[l][el]);
