@@ -209,26 +209,37 @@ __device__ __forceinline__ uint32_t lf_pack_lo(uint32_t a, uint32_t b)
     return __builtin_amdgcn_perm(b, a, 0x05040100u);
 }
 
-// Values i0 .. i0 + 3 of a block (i0 a multiple of 4).  They lie in at most
-// two groups (plain bits: four one-value groups).  When those span at most 64
-// bits (always for b <= 4 bits per value, and for every plain-bits block
-// up to 16), three payload words are read once, shifted so that the first
-// group starts at bit 0 of one 64-bit word, and every field is cut from it
-// with one shift and mask; otherwise each value is read on its own.
-__device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i0,
-                                             const uint32_t* __restrict__ tab, uint32_t (&v)[4])
+// Bit position of the first group of values i0 .. i0 + 3 (i0 a multiple of
+// 4) of a block with the given mode.
+__device__ __forceinline__ uint32_t lf_bise_first(uint32_t mode, uint32_t i0)
 {
     const uint32_t fam = mode >> 5, b = mode & 31u;
     const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
     const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
     const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;  // ceil(2^32 / 5), ceil(2^32 / 3)
-    const uint32_t gl = hb + gs * b;                             // bits per group
+    const uint32_t g0 = fam == 0u ? i0 : __umulhi(i0, mg);
+    return __umul24(g0, hb + gs * b);
+}
+
+// Values i0 .. i0 + 3 of a block (i0 a multiple of 4).  They lie in at most
+// two groups (plain bits: four one-value groups).  w0, w1, w2 are the three
+// payload words from word lf_bise_first(...) >> 5 on.  When the groups span
+// at most 64 bits (always for b <= 4 bits per value, and for plain bits up
+// to 16), the words are shifted so that the first group starts at bit 0 of
+// one 64-bit word and every field is cut from it with one shift and mask;
+// otherwise each value is read on its own from the block payload w.
+__device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uint32_t mode, uint32_t i0,
+                                             const uint32_t* __restrict__ tab, uint32_t w0, uint32_t w1,
+                                             uint32_t w2, uint32_t (&v)[4])
+{
+    const uint32_t fam = mode >> 5, b = mode & 31u;
+    const uint32_t hb = fam == 0u ? 0u : (fam == 1u ? 8u : 7u);
+    const uint32_t gs = fam == 0u ? 1u : (fam == 1u ? 5u : 3u);
+    const uint32_t mg = fam == 1u ? 858993460u : 1431655766u;
+    const uint32_t gl = hb + gs * b;  // bits per group
     const uint32_t g0 = fam == 0u ? i0 : __umulhi(i0, mg);
     const uint32_t pat = tab[LF_TAB_QUAD + 5u * fam + (i0 - __umul24(g0, gs))];
-    const uint32_t first = __umul24(g0, gl);
-    const uint32_t o0 = first & 31u;
-    const uint32_t* q = w + (first >> 5);
-    const uint32_t w0 = q[0], w1 = q[1], w2 = q[2];
+    const uint32_t o0 = __umul24(g0, gl) & 31u;
     const uint64_t X = ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, o0) << 32) | __builtin_amdgcn_alignbit(w1, w0, o0);
     if (__umul24(((pat >> 15) & 3u) + 1u, gl) <= 64u) {  // end of the last value's group
         const uint32_t tb = fam == 2u ? 256u : 0u;
@@ -251,25 +262,54 @@ __device__ __forceinline__ void lf_bise_quad(const uint32_t* __restrict__ w, uin
 // SRV values at (y, x0 .. x0 + 3) of the node a descriptor belongs to (x0 a
 // multiple of 4, so the quad lies in one block: one descriptor, one motion
 // vector, shared prediction taps and weights), as two int16 pairs
-// (x = pixels 0, 1; y = pixels 2, 3).
-//
-// Reference node: 4 int16 of its resident plane, 8-byte aligned.
-__device__ __forceinline__ uint2 lf_ref_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0)
+// (x = pixels 0, 1; y = pixels 2, 3).  The decode is split in two so that the
+// loads of several quads are in flight together: lf_quad_fetch issues every
+// load (payload window, two rows of prediction taps) unconditionally, and
+// lf_quad_finish computes.  A reference node's descriptor (MODE_PLANE) reads
+// its own plane, from `base` (resident reference planes, or the root planes
+// for a root slot): the first tap row is then the quad itself.
+struct QuadIn {
+    uint32_t w0, w1, w2;              // payload words from the quad's first group
+    uint32_t a0, a1, a2, b0, b1, b2;  // aligned words of tap rows y0, y0 + 1
+};
+
+__device__ __forceinline__ QuadIn lf_quad_fetch(const LfGeom& g, const LfPtrs& p, const int16_t* __restrict__ base,
+                                                const uint4& d, int y, int x0)
 {
-    return *reinterpret_cast<const uint2*>(p.refs + d.w + (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
+    QuadIn in;
+    const uint32_t mode = d.z >> 24;
+    const bool plane = mode == MODE_PLANE;
+    const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
+    const uint32_t* q = p.payload + d.x + (plane ? 0u : lf_bise_first(mode, i0) >> 5);
+    in.w0 = q[0];
+    in.w1 = q[1];
+    in.w2 = q[2];
+    const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
+    const int xb = x0 + (mx >> 2), y0 = (4 * y + my) >> 2;
+    // five taps from xb: the aligned words holding columns xs .. xs + 4, xs =
+    // xb clamped into the row (a reference node: its own quad at x0)
+    const int xs = plane ? x0 : max(min(xb, g.w - 5), 0);
+    const uint32_t ea = d.w + (uint32_t)__mul24(lf_clampi(y0, 0, g.h - 1), g.w) + (uint32_t)xs;
+    const uint32_t eb = d.w + (uint32_t)__mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w) + (uint32_t)xs;
+    const uint32_t* ra = reinterpret_cast<const uint32_t*>(base) + (ea >> 1);
+    const uint32_t* rb = reinterpret_cast<const uint32_t*>(base) + (eb >> 1);
+    in.a0 = ra[0];
+    in.a1 = ra[1];
+    in.a2 = ra[2];
+    in.b0 = rb[0];
+    in.b1 = rb[1];
+    in.b2 = rb[2];
+    return in;
 }
 
-// Predictive node: residual plus the signed quarter-pel prediction.  Every
-// load is unconditional (an insignificant block reads zero-bit values, a
-// block without prediction reads taps it then weighs by 0), so the loads of
-// several calls can be issued together.
-__device__ __forceinline__ uint2 lf_pred_quad(const LfGeom& g, const LfPtrs& p, uint4 d, int y, int x0,
-                                              const uint32_t* __restrict__ digits)
+__device__ __forceinline__ uint2 lf_quad_finish(const LfGeom& g, const LfPtrs& p, const QuadIn& in, const uint4& d,
+                                                int y, int x0, const uint32_t* __restrict__ digits)
 {
     const uint32_t mode = d.z >> 24;
+    if (mode == MODE_PLANE) return make_uint2(in.a0, in.a1);  // x0 is even: the words hold the quad
     const uint32_t i0 = ((uint32_t)(y & (g.bs - 1)) << g.bsl) | (uint32_t)(x0 & (g.bs - 1));
     uint32_t v[4];
-    lf_bise_quad(p.payload + d.x, mode, i0, digits, v);
+    lf_bise_quad(p.payload + d.x, mode, i0, digits, in.w0, in.w1, in.w2, v);
     const lf_i16x2 mn = lf_splat((int)(int16_t)(d.y & 0xFFFFu));
     const lf_i16x2 step = lf_splat((int)((d.y >> 16) & 0x1FFFu));
     const lf_i16x2 r01 = (lf_as_i16x2(lf_pack_lo(v[0], v[1])) + mn) * step;
@@ -277,26 +317,19 @@ __device__ __forceinline__ uint2 lf_pred_quad(const LfGeom& g, const LfPtrs& p, 
     const uint32_t code = d.y >> 29;
     const int mx = ((int)(d.z << 20)) >> 20, my = ((int)(d.z << 8)) >> 20;
     const int xb = x0 + (mx >> 2), fx = mx & 3;
-    const int Y = 4 * y + my, y0 = Y >> 2, fy = Y & 3;
-    // five taps from xb in rows y0, y0 + 1 (clamped): read the aligned words
-    // holding columns xs .. xs + 4, xs = xb clamped into the row
+    const int Y = 4 * y + my, fy = Y & 3;
     const int xs = max(min(xb, g.w - 5), 0);
-    const uint32_t ea = d.w + (uint32_t)__mul24(lf_clampi(y0, 0, g.h - 1), g.w) + (uint32_t)xs;
-    const uint32_t eb = d.w + (uint32_t)__mul24(lf_clampi(y0 + 1, 0, g.h - 1), g.w) + (uint32_t)xs;
-    const uint32_t* ra = reinterpret_cast<const uint32_t*>(p.refs) + (ea >> 1);
-    const uint32_t* rb = reinterpret_cast<const uint32_t*>(p.refs) + (eb >> 1);
-    const uint32_t a0 = ra[0], a1 = ra[1], a2 = ra[2], b0 = rb[0], b1 = rb[1], b2 = rb[2];
-    const uint32_t sh = (ea & 1u) << 4;  // the width is a multiple of 4: both rows share the parity
+    const uint32_t sh = (uint32_t)(xs & 1) << 4;  // plane offsets and rows are even: the parity is xs's
     // pairs (t0,t1) (t1,t2) (t2,t3) (t3,t4) of each row
     uint32_t A[4], B[4];
-    A[0] = __builtin_amdgcn_alignbit(a1, a0, sh);
-    A[2] = __builtin_amdgcn_alignbit(a2, a1, sh);
+    A[0] = __builtin_amdgcn_alignbit(in.a1, in.a0, sh);
+    A[2] = __builtin_amdgcn_alignbit(in.a2, in.a1, sh);
     A[1] = __builtin_amdgcn_alignbit(A[2], A[0], 16);
-    A[3] = __builtin_amdgcn_alignbit(a2 >> sh, A[2], 16);
-    B[0] = __builtin_amdgcn_alignbit(b1, b0, sh);
-    B[2] = __builtin_amdgcn_alignbit(b2, b1, sh);
+    A[3] = __builtin_amdgcn_alignbit(in.a2 >> sh, A[2], 16);
+    B[0] = __builtin_amdgcn_alignbit(in.b1, in.b0, sh);
+    B[2] = __builtin_amdgcn_alignbit(in.b2, in.b1, sh);
     B[1] = __builtin_amdgcn_alignbit(B[2], B[0], 16);
-    B[3] = __builtin_amdgcn_alignbit(b2 >> sh, B[2], 16);
+    B[3] = __builtin_amdgcn_alignbit(in.b2 >> sh, B[2], 16);
     if (xs != xb) {
         // image border: tap c is column clamp(xb + c) = xs + k of the window
         uint32_t ta[5], tb[5];
@@ -772,48 +805,79 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         }
         __syncthreads();
         // phase 1b: new values shared by several views, once per node and pixel
-        // quad: SRVs of levels 1..H-1 and the root RKV (level H)
-        for (int it = threadIdx.x; it < gp.nslots * rowq; it += NT) {
-            const int sl = lf_qdiv(it, m_rowq), rq = it - sl * rowq;
-            const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
-            const int y = ymin + yl, x0 = xq0 + 4 * qi;
-            const uint32_t info = slotinfo[sl];
-            uint2 packed;
-            if (info & 0x80000000u) {
-                packed = *reinterpret_cast<const uint2*>(p.root + (size_t)(info & 0x7FFFFFFFu) * (size_t)(g.w * g.h) +
-                                                         (uint32_t)__mul24(y, g.w) + (uint32_t)x0);
-            } else {
-                const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
-                const uint4 d = desc[info + kb];
-                packed = (d.z >> 24) == MODE_PLANE ? lf_ref_quad(g, p, d, y, x0) : lf_pred_quad(g, p, d, y, x0, digits);
+        // quad: SRVs of levels 1..H-1 and the root RKV (level H).  Four quads
+        // per thread at a time: all their loads are issued before any is used.
+        {
+            const int n1b = gp.nslots * rowq;
+            const uint32_t plane = (uint32_t)(g.w * g.h);
+            for (int it0 = threadIdx.x; it0 < n1b; it0 += 4 * NT) {
+                QuadIn in[4];
+                int yy[4], xx[4], sl4[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int it = min(it0 + u * NT, n1b - 1);  // past the end: repeat the last quad, not stored
+                    const int sl = lf_qdiv(it, m_rowq), rq = it - sl * rowq;
+                    const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
+                    const int y = ymin + yl, x0 = xq0 + 4 * qi;
+                    const uint32_t info = slotinfo[sl];
+                    const bool root = info & 0x80000000u;
+                    const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
+                    const uint4 d = root ? make_uint4(0u, 0u, (uint32_t)MODE_PLANE << 24, (info & 0x7FFFFFFFu) * plane)
+                                         : desc[info + kb];
+                    in[u] = lf_quad_fetch(g, p, root ? p.root : p.refs, d, y, x0);
+                    yy[u] = y;
+                    xx[u] = x0;
+                    sl4[u] = sl;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int it = it0 + u * NT;
+                    if (it < n1b) {
+                        const int sl = sl4[u], rq = it - sl * rowq;
+                        const uint32_t info = slotinfo[sl];
+                        const bool root = info & 0x80000000u;
+                        const int kb = __mul24((yy[u] >> g.bsl) - bky0, nbkx) + (xx[u] >> g.bsl) - bkx0;
+                        const uint4 d = root ? make_uint4(0u, 0u, (uint32_t)MODE_PLANE << 24, 0u) : desc[info + kb];
+                        reinterpret_cast<uint2*>(sval)[__mul24((int)slotdst[sl], rowq) + rq] =
+                            lf_quad_finish(g, p, in[u], d, yy[u], xx[u], digits);
+                    }
+                }
             }
-            reinterpret_cast<uint2*>(sval)[__mul24((int)slotdst[sl], rowq) + rq] = packed;
         }
         __syncthreads();
-        // phase 2: every new (view, pixel quad) sample: level-0 SRV + staged ancestors and root
-        for (int it = threadIdx.x; it < gp.nnew[0] * rowq; it += NT) {
-            const int k = lf_qdiv(it, m_rowq), rq = it - k * rowq;
-            const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
-            const int y = ymin + yl, x0 = xq0 + 4 * qi;
+        // phase 2: every new (view, pixel quad) sample: level-0 SRV + staged
+        // ancestors and root; two quads (six channel decodes) per thread at a time
+        const int n2 = gp.nnew[0] * rowq;
+        for (int it0 = threadIdx.x; it0 < n2; it0 += 2 * NT) {
+            QuadIn in[2][3];
+            int kk2[2], rq2[2], yy[2], xx[2];
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int it = min(it0 + u * NT, n2 - 1);
+                const int k = lf_qdiv(it, m_rowq), rq = it - k * rowq;
+                const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
+                const int y = ymin + yl, x0 = xq0 + 4 * qi;
+                const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
+                const uint4* dq = desc + __mul24(3 * k, nbk) + kb;
+#pragma unroll
+                for (int c = 0; c < 3; c++) in[u][c] = lf_quad_fetch(g, p, p.refs, dq[c * nbk], y, x0);
+                kk2[u] = k;
+                rq2[u] = rq;
+                yy[u] = y;
+                xx[u] = x0;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+            if (it0 + u * NT >= n2) continue;
+            const int k = kk2[u], rq = rq2[u], y = yy[u], x0 = xx[u];
             const int kb = __mul24((y >> g.bsl) - bky0, nbkx) + (x0 >> g.bsl) - bkx0;
             const uint4* dq = desc + __mul24(3 * k, nbk) + kb;
-            // the node is a reference (resident planes) or predictive in all three channels
-            uint4 dc[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) dc[c] = dq[c * nbk];
-            uint2 qc[3];
-            if ((dc[0].z >> 24) == MODE_PLANE) {
-#pragma unroll
-                for (int c = 0; c < 3; c++) qc[c] = lf_ref_quad(g, p, dc[c], y, x0);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; c++) qc[c] = lf_pred_quad(g, p, dc[c], y, x0, digits);
-            }
             lf_i16x2 ch[3][2];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                ch[c][0] = lf_as_i16x2(qc[c].x);
-                ch[c][1] = lf_as_i16x2(qc[c].y);
+                const uint2 q = lf_quad_finish(g, p, in[u][c], dq[c * nbk], y, x0, digits);
+                ch[c][0] = lf_as_i16x2(q.x);
+                ch[c][1] = lf_as_i16x2(q.y);
             }
             const uint2 an = *reinterpret_cast<const uint2*>(ancs[k]);
             for (int l = 1; l <= g.H; l++) {
@@ -852,6 +916,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 }
             }
             reinterpret_cast<uint4*>(rgba)[__mul24((int)(nodelist[0][k] >> 8), rowq) + rq] = px4;
+            }
         }
         __syncthreads();
         // phase 3: blend every ray of the group's views
