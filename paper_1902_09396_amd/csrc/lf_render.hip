@@ -174,9 +174,9 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     }
     hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
                        d_cams, nv, wo, ho, tx, ty, chunk, fpg, d_out);
-    // marked pairs: at most 8192 workgroups, each checking a contiguous range
+    // marked pairs: at most 1024 workgroups, each checking a contiguous range
     const int64_t pairs = (int64_t)tx * ty * nv;
-    const int64_t fb_grid = std::min<int64_t>(pairs, 8192);
+    const int64_t fb_grid = std::min<int64_t>(pairs, 1024);
     const int64_t per_wg = (pairs + fb_grid - 1) / fb_grid;
     if (per_wg > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
     hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)fb_grid), dim3(NT), 0, s, h->L.g, h->p, d_cams, nv, wo, ho, tx,
