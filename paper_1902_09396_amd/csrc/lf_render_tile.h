@@ -919,31 +919,45 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             }
         }
         __syncthreads();
-        // phase 3: blend every ray of the group's views
-        for (int q = f; q < f + n; q++) {
-            const Ray r = lf_ray_setup(g, cams + 18 * (v0 + q), ii, jj);
-            // x1 = x0 + 1 and y1 = y0 + 1: the captured views are at least one
-            // 4-pixel block wide and high on this path
-            const int pix = __mul24(r.y0 - ymin, sxp) + (r.x0 - xq0);
-            uint32_t s16[16];
+        // phase 3: blend every ray of the group's views, two views at a time
+        // (the second view's sample reads are in flight during the first's blend)
+        {
+            const int B00 = gp.B0[0], A00 = gp.A0[0], nA0 = gp.nA[0];
+            for (int q = f; q < f + n; q += 2) {
+                const bool two = q + 1 < f + n;  // uniform
+                Ray r[2];
+                uint32_t s16[2][16];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int b = (k & 2) ? r.b1 : r.b0, a = (k & 1) ? r.a1 : r.a0;
-                const uint32_t* q0 = rgba + __mul24(nodemap[0][__mul24(b - gp.B0[0], gp.nA[0]) + (a - gp.A0[0])], npix) + pix;
-                const uint32_t* q1 = q0 + sxp;
-                s16[4 * k + 0] = q0[0];
-                s16[4 * k + 1] = q0[1];
-                s16[4 * k + 2] = q1[0];
-                s16[4 * k + 3] = q1[1];
-            }
-            if (live) {
-                const BlendW w = lf_blend_weights(r);
+                for (int h = 0; h < 2; h++) {
+                    const int qq = (h == 1 && two) ? q + 1 : q;  // odd tail: repeat view q, not stored
+                    r[h] = lf_ray_setup(g, cams + 18 * (v0 + qq), ii, jj);
+                    // x1 = x0 + 1 and y1 = y0 + 1: the captured views are at least one
+                    // 4-pixel block wide and high on this path
+                    const int pix = __mul24(r[h].y0 - ymin, sxp) + (r[h].x0 - xq0);
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    float sm[16];
+                    for (int k = 0; k < 4; k++) {
+                        const int b = (k & 2) ? r[h].b1 : r[h].b0, a = (k & 1) ? r[h].a1 : r[h].a0;
+                        const uint32_t* q0 = rgba + __mul24(nodemap[0][__mul24(b - B00, nA0) + (a - A00)], npix) + pix;
+                        const uint32_t* q1 = q0 + sxp;
+                        s16[h][4 * k + 0] = q0[0];
+                        s16[h][4 * k + 1] = q0[1];
+                        s16[h][4 * k + 2] = q1[0];
+                        s16[h][4 * k + 3] = q1[1];
+                    }
+                }
+                if (live) {
 #pragma unroll
-                    for (int k = 0; k < 16; k++) sm[k] = (float)((s16[k] >> (8 * c)) & 255u);
-                    out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, w);
+                    for (int h = 0; h < 2; h++) {
+                        if (h == 1 && !two) break;
+                        const BlendW w = lf_blend_weights(r[h]);
+#pragma unroll
+                        for (int c = 0; c < 3; c++) {
+                            float sm[16];
+#pragma unroll
+                            for (int k = 0; k < 16; k++) sm[k] = (float)((s16[h][k] >> (8 * c)) & 255u);
+                            out[((int64_t)(v0 + q + h) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, w);
+                        }
+                    }
                 }
             }
         }
