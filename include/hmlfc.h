@@ -136,7 +136,7 @@ lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_vie
 /* Launch configuration lf_render_views uses for n_views views of
  * width x height: views decoded together per group, and views per workgroup
  * chunk (decoded samples are kept in LDS between the groups of a chunk).
- * The group size is HMLFC_VIEWS_PER_GROUP (1..64, default 10); the chunk is
+ * The group size is HMLFC_VIEWS_PER_GROUP (1..64, default 12); the chunk is
  * HMLFC_VIEWS_PER_CHUNK (1..64) if set, else as long as the launch keeps
  * about 2048 workgroups of 32x8-pixel tiles (at most 64 views, balanced).
  * Both variables are read once, at first use.  Either pointer may be NULL;

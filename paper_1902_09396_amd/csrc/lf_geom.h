@@ -191,46 +191,40 @@ __device__ __forceinline__ uint4 lf_make_desc(const LfGeom& g, const LfPtrs& p, 
 // rounded separately (no fused multiply-add), then one IEEE division.  When a
 // homography's third row is exactly (0, 0, 1) its third component is exactly 1
 // at every pixel and x / 1 == x, so it is neither formed nor divided by.
-__device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float& u, float& v, float& s, float& t)
+// lf_ray_h maps the pixel centre through one homography h (row-major 3x3).
+__device__ __forceinline__ void lf_ray_h(const float* __restrict__ h, float px, float py, float& x, float& y)
 {
 #pragma clang fp contract(off)
-    const float px = (float)i + 0.5f, py = (float)j + 0.5f;
-    float q[6];
+    float q[3];
 #pragma unroll
-    for (int r = 0; r < 6; r++) {
-        if (r == 2 || r == 5) continue;
-        const float* h = cam + (r < 3 ? 0 : 9) + 3 * (r % 3);
-        float a = h[0] * px;
-        float bb = h[1] * py;
+    for (int r = 0; r < 2; r++) {
+        float a = h[3 * r] * px;
+        float bb = h[3 * r + 1] * py;
         float sum = a + bb;
-        q[r] = sum + h[2];
+        q[r] = sum + h[3 * r + 2];
     }
-#pragma unroll
-    for (int r = 2; r < 6; r += 3) {
-        const float* h = cam + (r < 3 ? 0 : 9) + 6;
-        if (h[0] == 0.0f && h[1] == 0.0f && h[2] == 1.0f) {
-            q[r] = 1.0f;
-        } else {
-            float a = h[0] * px;
-            float bb = h[1] * py;
-            float sum = a + bb;
-            q[r] = sum + h[2];
-        }
+    if (h[6] == 0.0f && h[7] == 0.0f && h[8] == 1.0f) {
+        q[2] = 1.0f;
+    } else {
+        float a = h[6] * px;
+        float bb = h[7] * py;
+        float sum = a + bb;
+        q[2] = sum + h[8];
     }
     if (q[2] == 1.0f) {
-        u = q[0];
-        v = q[1];
+        x = q[0];
+        y = q[1];
     } else {
-        u = q[0] / q[2];
-        v = q[1] / q[2];
+        x = q[0] / q[2];
+        y = q[1] / q[2];
     }
-    if (q[5] == 1.0f) {
-        s = q[3];
-        t = q[4];
-    } else {
-        s = q[3] / q[5];
-        t = q[4] / q[5];
-    }
+}
+
+__device__ inline void lf_ray(const float* __restrict__ cam, int i, int j, float& u, float& v, float& s, float& t)
+{
+    const float px = (float)i + 0.5f, py = (float)j + 0.5f;
+    lf_ray_h(cam, px, py, u, v);
+    lf_ray_h(cam + 9, px, py, s, t);
 }
 
 // Clamp a coordinate to [0, n-1]; lower neighbour k (<= n-2), upper

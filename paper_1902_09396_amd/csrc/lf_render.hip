@@ -131,7 +131,7 @@ static int env_int(const char* name, int dflt, int lo, int hi)
 // cached between its groups)
 static int frames_per_group()
 {
-    static int v = env_int("HMLFC_VIEWS_PER_GROUP", 10, 1, FMAX);
+    static int v = env_int("HMLFC_VIEWS_PER_GROUP", 12, 1, FMAX);
     return v;
 }
 // views per chunk: HMLFC_VIEWS_PER_CHUNK if set, else chunks as long as

@@ -392,6 +392,7 @@ struct GroupPlan {
     int nslots, ndesc;
     uint32_t m_rowq, m_nq, m_nbk;  // reciprocals of sy * nq, nq and nbk
     uint32_t cbox0, cbox1;         // box the cache entries hold values of (all ones: none)
+    int st_shared;                 // every view of the call has the same st homography
 };
 
 // Key of node (B, A) of level l (B, A < 2^14)
@@ -526,6 +527,14 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             fbox[f][2] = m2;
             fbox[f][3] = m3;
         }
+    }
+    if (wid == 0) {
+        bool eq = true;
+        if (lane < nf)
+#pragma unroll
+            for (int e = 0; e < 9; e++) eq = eq && cams[18 * (v0 + lane) + 9 + e] == cams[18 * v0 + 9 + e];
+        const bool shared = __ballot(lane < nf && !eq) == 0ull;
+        if (lane == 0) gp.st_shared = shared;
     }
     __syncthreads();
     for (int f = 0; f < nf; f++) {
@@ -923,6 +932,17 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         // (the second view's sample reads are in flight during the first's blend)
         {
             const int B00 = gp.B0[0], A00 = gp.A0[0], nA0 = gp.nA[0];
+            // all views of the call share one st homography (a camera path with
+            // one st window): each ray's (s, t) axis is computed once
+            const bool st_shared = gp.st_shared;
+            const float* hst = cams + 18 * v0 + 9;
+            Ray rst;
+            {
+                float s, t;
+                lf_ray_h(hst, (float)ii + 0.5f, (float)jj + 0.5f, s, t);
+                lf_axis(s, g.w, rst.x0, rst.x1, rst.fs);
+                lf_axis(t, g.h, rst.y0, rst.y1, rst.ft);
+            }
             for (int q = f; q < f + n; q += 2) {
                 const bool two = q + 1 < f + n;  // uniform
                 Ray r[2];
@@ -930,7 +950,20 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
                     const int qq = (h == 1 && two) ? q + 1 : q;  // odd tail: repeat view q, not stored
-                    r[h] = lf_ray_setup(g, cams + 18 * (v0 + qq), ii, jj);
+                    if (st_shared) {
+                        float u, v;
+                        lf_ray_h(cams + 18 * (v0 + qq), (float)ii + 0.5f, (float)jj + 0.5f, u, v);
+                        lf_axis(u, g.na, r[h].a0, r[h].a1, r[h].fu);
+                        lf_axis(v, g.nb, r[h].b0, r[h].b1, r[h].fv);
+                        r[h].x0 = rst.x0;
+                        r[h].x1 = rst.x1;
+                        r[h].y0 = rst.y0;
+                        r[h].y1 = rst.y1;
+                        r[h].fs = rst.fs;
+                        r[h].ft = rst.ft;
+                    } else {
+                        r[h] = lf_ray_setup(g, cams + 18 * (v0 + qq), ii, jj);
+                    }
                     // x1 = x0 + 1 and y1 = y0 + 1: the captured views are at least one
                     // 4-pixel block wide and high on this path
                     const int pix = __mul24(r[h].y0 - ymin, sxp) + (r[h].x0 - xq0);
