@@ -207,6 +207,28 @@ def test_cached_groups_equal_per_ray(torch_mod, lfmod, mid_stream):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("shape", [(1, 5, 64, 32, 3, 8), (7, 3, 48, 40, 2, 4), (2, 2, 32, 32, 1, 16),
+                                   (9, 1, 16, 64, 4, 16)])
+def test_thin_and_ragged_grids(torch_mod, lfmod, shape):
+    """Single-row and single-column grids, odd grid sizes, one-level trees and
+    4-pixel blocks: decode bit-exact, render <= 1e-5, staged = per-ray."""
+    torch = torch_mod
+    na, nb, w, h, levels, block = shape
+    lf = np.ascontiguousarray(lfscene.make_lf(na, nb, h, w, lfscene.get_config("tiny")["lf"]["spec"], 7))
+    cfg = lfscene.get_config("tiny", levels=levels, block=block, step=4, win=4, t_ref=0, t_pred=0)
+    s = oracle.encode(lf, cfg["enc"])
+    o = oracle.OracleLF(s)
+    L = lfmod.LightField(s)
+    coords = _all_coords(o)
+    got = L.decode_pixels(torch.from_numpy(coords).cuda()).cpu().numpy()
+    assert np.array_equal(got, o.decode_full().reshape(-1, 3))
+    cams = lfscene.random_pinhole_cameras(5, na, nb, w, h, 45, 27, seed=3, rho=1.0 / 8.0)
+    c = _cams_dev(torch, cams)
+    img = L.render_views(c, 45, 27).cpu().numpy()
+    assert np.abs(img.astype(np.float64) - o.render(cams, 45, 27)).max() <= RENDER_TOL
+    assert np.array_equal(img, L.render_views(c, 45, 27, per_ray=True).cpu().numpy())
+
+
 def test_render_deterministic(torch_mod, lfmod, mid_stream):
     torch = torch_mod
     cams = _cams_dev(torch, lfscene.camera_path_orbit(8, 17, 17, 128, 128, 96, 80))
