@@ -61,6 +61,8 @@ def lib():
             "orc_info": (None, [P, P]),
             "orc_decode_at": (C.c_int, [P, P, i64, P]),
             "orc_decode_at_ycocg": (C.c_int, [P, P, i64, P]),
+            "orc_decode_node": (C.c_int, [P, C.c_int, P, i64, P]),
+            "orc_render_lod": (C.c_int, [P, C.c_int, P, C.c_int, C.c_int, C.c_int, P]),
             "orc_decode_full": (C.c_int, [P, P]),
             "orc_decode_full_ycocg": (C.c_int, [P, P]),
             "orc_decode_srv": (C.c_int, [P, P]),
@@ -244,6 +246,22 @@ class OracleLF:
         out = np.empty((coords.shape[0], 3), dtype=np.int32)
         if lib().orc_decode_at_ycocg(self._h, _p(coords), coords.shape[0], _p(out)) != 0:
             raise ValueError("coordinate out of range")
+        return out
+
+    def decode_node(self, level: int, coords: np.ndarray) -> np.ndarray:
+        """Node images of `level` (0 .. H) at (B, A, y, x): progressive decode."""
+        coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 4)
+        out = np.empty((coords.shape[0], 3), dtype=np.uint8)
+        if lib().orc_decode_node(self._h, int(level), _p(coords), coords.shape[0], _p(out)) != 0:
+            raise ValueError("level or coordinate out of range")
+        return out
+
+    def render_lod(self, level: int, cams: np.ndarray, wo: int, ho: int) -> np.ndarray:
+        """render() with every sample's walk stopped at `level`."""
+        cams = np.ascontiguousarray(cams, dtype=np.float32).reshape(-1, 18)
+        out = np.empty((cams.shape[0], 3, ho, wo), dtype=np.float64)
+        if lib().orc_render_lod(self._h, int(level), _p(cams), cams.shape[0], wo, ho, _p(out)) != 0:
+            raise ValueError("level out of range")
         return out
 
     def decode_full(self) -> np.ndarray:

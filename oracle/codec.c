@@ -836,12 +836,15 @@ static int32_t qpel_stream(const orc_lf* lf, int c, int l, int Br, int Ar, int y
     return orc_asr(acc + 8, 4);
 }
 
-/* One channel of one sample: root RKV plus the decoded SRVs of every level
- * on the path from the leaf view to the root. */
-static int32_t decode_channel(const orc_lf* lf, int c, int b, int a, int y, int x)
+/* One channel of one sample: root RKV plus the decoded SRVs of the levels
+ * lod .. H-1 on the path from the leaf view (b, a) to the root (Decoding
+ * Procedure).  lod = 0 gives the leaf view itself; lod = l > 0 stops the
+ * walk at the level-l ancestor (B, A) = (b >> l, a >> l) and gives that
+ * node's reconstructed RKV, the progressive decode of the hierarchy. */
+static int32_t decode_channel_lod(const orc_lf* lf, int c, int b, int a, int y, int x, int lod)
 {
     int32_t v = orc_root_value(lf, c, b, a, y, x);
-    for (int l = 0; l < lf->H; l++) {
+    for (int l = lod; l < lf->H; l++) {
         int B = b >> l, A = a >> l;
         int32_t r = orc_srv_value(lf, c, l, B, A, y, x);
         if ((A | B) & 1) {
@@ -853,6 +856,36 @@ static int32_t decode_channel(const orc_lf* lf, int c, int b, int a, int y, int 
         v += r;
     }
     return v;
+}
+
+static int32_t decode_channel(const orc_lf* lf, int c, int b, int a, int y, int x)
+{
+    return decode_channel_lod(lf, c, b, a, y, x, 0);
+}
+
+/* Node images at level `level` (0 .. H): coords[k] = (B, A, y, x) with B, A
+ * node indices of that level; RGB of the node's reconstructed RKV. */
+int orc_decode_node(const orc_lf* lf, int level, const int32_t* coords, int64_t n, uint8_t* rgb)
+{
+    if (level < 0 || level > lf->H) return -1;
+    int status = 0;
+    for (int64_t k = 0; k < n; k++) {
+        const int32_t* q = coords + 4 * k;
+        const int b = q[0] << level, a = q[1] << level;
+        if (q[0] < 0 || q[1] < 0 || b >= lf->nb || a >= lf->na || q[2] < 0 || q[2] >= lf->h || q[3] < 0 ||
+            q[3] >= lf->w) {
+            status = -1;
+            continue;
+        }
+        int ch[3];
+        for (int c = 0; c < 3; c++) ch[c] = decode_channel_lod(lf, c, b, a, q[2], q[3], level);
+        int r, g, bl;
+        orc_ycocg_inv(ch[0], ch[1], ch[2], &r, &g, &bl);
+        rgb[3 * k] = (uint8_t)(r < 0 ? 0 : (r > 255 ? 255 : r));
+        rgb[3 * k + 1] = (uint8_t)(g < 0 ? 0 : (g > 255 ? 255 : g));
+        rgb[3 * k + 2] = (uint8_t)(bl < 0 ? 0 : (bl > 255 ? 255 : bl));
+    }
+    return status;
 }
 
 static int valid_coord(const orc_lf* lf, const int32_t* q)

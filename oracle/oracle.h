@@ -90,6 +90,7 @@ void orc_info(const orc_lf* lf, int64_t* out10);
 
 /* ---- decoders ---- */
 int orc_decode_at(const orc_lf* lf, const int32_t* coords, int64_t n, uint8_t* rgb);
+int orc_decode_node(const orc_lf* lf, int level, const int32_t* coords, int64_t n, uint8_t* rgb); /* (B,A,y,x) */
 int orc_decode_at_ycocg(const orc_lf* lf, const int32_t* coords, int64_t n, int32_t* ycc);
 int orc_decode_full(const orc_lf* lf, uint8_t* out);           /* [nb][na][h][w][3]        */
 int orc_decode_full_ycocg(const orc_lf* lf, int32_t* out);     /* [3][nb][na][h][w]        */
@@ -99,6 +100,8 @@ int orc_decode_srv(const orc_lf* lf, int32_t* out);
 /* ---- renderer ---- */
 int orc_ray_coords(const float* cam, int wo, int ho, int i, int j, float* uvst4);
 int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int nthreads, double* out);
+/* rendering with every sample's walk stopped at level lod (progressive decode) */
+int orc_render_lod(const orc_lf* lf, int lod, const float* cams, int nv, int wo, int ho, double* out);
 int orc_render_rays(const orc_lf* lf, const float* cams, int wo, int ho, const int32_t* rays, int64_t n,
                     double* out);
 int orc_render_dense(const uint8_t* lf, int nb, int na, int h, int w, const float* cams, int nv,

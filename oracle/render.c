@@ -125,6 +125,42 @@ int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int 
     return status;
 }
 
+/* The same rendering with every sample replaced by its level-lod ancestor's
+ * reconstructed RKV: the view (b, a) of a sample reads node (b >> lod,
+ * a >> lod) of level lod (progressive decode, lod = 0: orc_render). */
+int orc_render_lod(const orc_lf* lf, int lod, const float* cams, int nv, int wo, int ho, double* out)
+{
+    if (lod < 0 || lod > lf->H) return -1;
+    int status = 0;
+    const int64_t npix = (int64_t)wo * ho;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < (int64_t)nv * npix; r++) {
+        int v = (int)(r / npix);
+        int j = (int)((r % npix) / wo), i = (int)(r % wo);
+        footprint fp;
+        ray_footprint(cams + 18 * v, wo, ho, i, j, lf->na, lf->nb, lf->w, lf->h, &fp);
+        int32_t coords[16 * 4];
+        uint8_t rgb[16 * 3];
+        int k = 0;
+        for (int jb = 0; jb < 2; jb++)
+            for (int ia = 0; ia < 2; ia++)
+                for (int jy = 0; jy < 2; jy++)
+                    for (int ix = 0; ix < 2; ix++, k++) {
+                        coords[4 * k] = fp.b[jb] >> lod;
+                        coords[4 * k + 1] = fp.a[ia] >> lod;
+                        coords[4 * k + 2] = fp.y[jy];
+                        coords[4 * k + 3] = fp.x[ix];
+                    }
+        if (orc_decode_node(lf, lod, coords, 16, rgb)) status = -1;
+        for (int c = 0; c < 3; c++) {
+            double s[2][2][2][2];
+            for (k = 0; k < 16; k++) s[k >> 3][(k >> 2) & 1][(k >> 1) & 1][k & 1] = rgb[3 * k + c] / 255.0;
+            out[((int64_t)v * 3 + c) * npix + (int64_t)j * wo + i] = blend16(s, &fp);
+        }
+    }
+    return status;
+}
+
 /* Selected rays only: rays[k] = (view, i, j); out[k][3]. */
 int orc_render_rays(const orc_lf* lf, const float* cams, int wo, int ho, const int32_t* rays, int64_t n,
                     double* out)

@@ -114,3 +114,43 @@ def test_malformed_streams_rejected(tiny_stream):
     bad[136:144] = np.frombuffer(np.uint64(12345).tobytes(), np.uint8)  # table size
     with pytest.raises(ValueError):
         oracle.OracleLF(bad)
+
+
+def _all_nodes(o, level):
+    nb, na = -(-o.nb // (1 << level)), -(-o.na // (1 << level))
+    B, A, y, x = np.meshgrid(np.arange(nb), np.arange(na), np.arange(o.h), np.arange(o.w), indexing="ij")
+    return np.stack([B.ravel(), A.ravel(), y.ravel(), x.ravel()], 1).astype(np.int32), (nb, na)
+
+
+@pytest.mark.parametrize("no_mc", [False, True])
+def test_progressive_decode_is_the_rkv_pyramid(tiny_lf, no_mc):
+    """Stopping the walk at level l gives the level-l node images; coded
+    losslessly (step 1), those are the rounded-mean pyramid of the original
+    views (Hierarchical Compression Scheme), whatever the motion vectors."""
+    s = stream_for("tiny", tiny_lf, step=1, no_mc=no_mc)
+    o = oracle.OracleLF(s)
+    I0 = np.moveaxis(_ycocg_lf(tiny_lf), -1, 0)  # [3][8][8][h][w]
+    I1 = np.floor_divide(I0.reshape(3, 4, 2, 4, 2, 64, 64).sum(axis=(2, 4)) + 2, 4)
+    I2 = np.floor_divide(I1.reshape(3, 2, 2, 2, 2, 64, 64).sum(axis=(2, 4)) + 2, 4)
+    for level, I in ((0, I0), (1, I1), (2, I2)):
+        coords, (nb, na) = _all_nodes(o, level)
+        got = o.decode_node(level, coords).reshape(nb, na, 64, 64, 3)
+        expect = np.clip(oracle.ycocg_inv(np.moveaxis(I, 0, -1).reshape(-1, 3)), 0, 255)
+        assert np.array_equal(got, expect.reshape(nb, na, 64, 64, 3).astype(np.uint8)), level
+    with pytest.raises(ValueError):
+        o.decode_node(3, coords[:1])
+
+
+def test_progressive_decode_levels_lossy(tiny_lf):
+    """Level 0 is the random-access decode; a level-l render reads each
+    sample's level-l ancestor, so views of one cluster render alike."""
+    o = oracle.OracleLF(stream_for("tiny", tiny_lf))
+    coords = np.array([[5, 3, 10, 20], [7, 7, 63, 63], [0, 0, 0, 0]], dtype=np.int32)
+    assert np.array_equal(o.decode_node(0, coords), o.decode_at(coords))
+    node = o.decode_node(1, np.array([[2, 1, 10, 20]], dtype=np.int32))
+    cams = np.stack([lfscene.cameras.fixed_uv_camera(4.0, 2.0, lfscene.full_frame_st(64, 64, 16, 16)),
+                     lfscene.cameras.fixed_uv_camera(4.5, 2.5, lfscene.full_frame_st(64, 64, 16, 16))])
+    r = o.render_lod(1, cams, 16, 16)
+    assert np.array_equal(r[0], r[1])  # every sample of both reads views b 2..3, a 4..5: level-1 node (1, 2)
+    assert np.array_equal(o.render_lod(0, cams, 16, 16), o.render(cams, 16, 16))
+    assert node.shape == (1, 3)
