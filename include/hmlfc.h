@@ -119,6 +119,18 @@ lf_status lf_get_info(const lf_handle* h, lf_info* out);
  * grid are clamped to it.  d_rgb: device uint8 [n][3].  n = 0 is a no-op. */
 lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t n, uint8_t* d_rgb, void* stream);
 
+/* Progressive decoding (claimed in the Introduction's contributions and the
+ * HMLFC Overview; the hierarchy of the RLFC scheme): the walk stops at tree
+ * level `level`, giving samples of the reconstructed level-`level` node
+ * images (the root RKV plus the SRVs of levels level .. H-1).  level = 0 is
+ * lf_decode_pixels; level = H is the root RKV alone.  d_coords: device int32
+ * [n][4] = (B, A, y, x) with (B, A) a node of that level (0 <= B <
+ * ceil(nb / 2^level), likewise A); coordinates outside are clamped.  Must be
+ * 16-byte aligned.  d_rgb: device uint8 [n][3].  LF_EINVAL for level outside
+ * 0 .. H. */
+lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, const int32_t* d_coords, int64_t n,
+                               uint8_t* d_rgb, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Novel-view rendering fused with decoding (Random Access for             */
 /* Interactive Rendering; two-plane interpolation of Light Field           */
@@ -149,6 +161,15 @@ lf_status lf_get_render_config(int32_t n_views, int32_t width, int32_t height, i
  * lf_render_views, bit for bit; kept as the simple reference path. */
 lf_status lf_render_views_per_ray(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                                   int32_t height, float* d_out, void* stream);
+
+/* Level-of-detail rendering from the progressive decode: the same rays and
+ * blend as lf_render_views over the full-resolution view grid, but sample
+ * (b, a, y, x) is read from the level-`level` node image of (b >> level,
+ * a >> level), i.e. every view of a 2^level x 2^level cluster shows its
+ * reconstructed RKV.  One thread per ray (the walk is short).  level = 0
+ * equals lf_render_views_per_ray.  LF_EINVAL for level outside 0 .. H. */
+lf_status lf_render_views_lod(const lf_handle* h, int32_t level, const float* d_cams, int32_t n_views,
+                              int32_t width, int32_t height, float* d_out, void* stream);
 
 /* Ray coordinates as the renderer computes them (binary32, no contraction):
  * d_uvst: device float [n_views][height][width][4] = (u, v, s, t) before

@@ -379,6 +379,39 @@ extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coord
     return lf_check_launch("decode_pixels");
 }
 
+// Progressive decode: samples of the level-`lod` node images.
+__global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __restrict__ coords, int64_t n,
+                               uint8_t* __restrict__ rgb)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int4 q = reinterpret_cast<const int4*>(coords)[k];
+    int B = lf_clampi(q.x, 0, g.nb_l[lod] - 1), A = lf_clampi(q.y, 0, g.na_l[lod] - 1);
+    int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
+    int Y = lf_decode_channel(g, p, 0, B << lod, A << lod, y, x, lod);
+    int Co = lf_decode_channel(g, p, 1, B << lod, A << lod, y, x, lod);
+    int Cg = lf_decode_channel(g, p, 2, B << lod, A << lod, y, x, lod);
+    int r, gg, bl;
+    lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
+    rgb[3 * k] = (uint8_t)r;
+    rgb[3 * k + 1] = (uint8_t)gg;
+    rgb[3 * k + 2] = (uint8_t)bl;
+}
+
+extern "C" lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, const int32_t* d_coords, int64_t n,
+                                          uint8_t* d_rgb, void* stream)
+{
+    if (!h || n < 0 || level < 0 || level > h->L.g.H) return lf_fail(LF_EINVAL, "bad argument");
+    if (n == 0) return LF_OK;
+    if (!d_coords || !d_rgb) return lf_fail(LF_EINVAL, "null buffer");
+    if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
+    hipLaunchKernelGGL(k_decode_nodes, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->L.g, h->p,
+                       (int)level, d_coords, n, d_rgb);
+    return lf_check_launch("decode_pixels_lod");
+}
+
 // ---------------------------------------------------------------------------
 // ray coordinates (exposed for checking the renderer's arithmetic)
 // ---------------------------------------------------------------------------

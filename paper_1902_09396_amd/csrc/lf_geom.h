@@ -131,13 +131,17 @@ __device__ __forceinline__ const int16_t* lf_ref_plane(const LfGeom& g, const Lf
 // One YCoCg channel of sample (b, a, y, x): root RKV plus the SRV of every
 // level on the path (Decoding Procedure).  Reference SRVs come from the
 // resident planes; predictive SRVs are residual + phase * prediction.
-__device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c, int b, int a, int y, int x)
+// One channel of one sample: the root RKV plus the SRVs of levels lod .. H-1
+// on the path from leaf view (b, a) up (lod = 0: the leaf view itself; lod =
+// l: the reconstructed RKV of the level-l ancestor, the progressive decode).
+__device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c, int b, int a, int y, int x,
+                                        int lod = 0)
 {
     const int plane = g.w * g.h;
     int v = p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * plane + y * g.w + x];
     const int blk = (y >> g.bsl) * g.nbx + (x >> g.bsl);
     const int i = ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1));
-    for (int l = 0; l < g.H; l++) {
+    for (int l = lod; l < g.H; l++) {
         int B = b >> l, A = a >> l;
         const int16_t* ref = lf_ref_plane(g, p, c, l, B >> 1, A >> 1);
         if (!((A | B) & 1)) {

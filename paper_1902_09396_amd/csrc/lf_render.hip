@@ -20,7 +20,7 @@
 #include "lf_render_tile.h"
 
 __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
-                                                     int wo, int ho, float* __restrict__ out)
+                                                     int wo, int ho, float* __restrict__ out, int lod)
 {
     const int64_t npix = (int64_t)wo * ho;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,19 +29,19 @@ __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const f
     const int64_t px = r - (int64_t)v * npix;
     const int j = (int)(px / wo), i = (int)(px % wo);
     float o[3];
-    lf_render_one(g, p, cams + 18 * v, i, j, o);
+    lf_render_one(g, p, cams + 18 * v, i, j, o, lod);
 #pragma unroll
     for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
 }
 
 lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,
-                                hipStream_t s)
+                                hipStream_t s, int lod = 0)
 {
     int64_t total = (int64_t)nv * wo * ho;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many rays");
     hipLaunchKernelGGL(k_render_rays, dim3((unsigned)blocks), dim3(256), 0, s, h->L.g, h->p, d_cams, nv, wo, ho,
-                       d_out);
+                       d_out, lod);
     return lf_check_launch("render_rays");
 }
 
@@ -202,4 +202,14 @@ extern "C" lf_status lf_render_views_per_ray(const lf_handle* h, const float* d_
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
     return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
+}
+
+extern "C" lf_status lf_render_views_lod(const lf_handle* h, int32_t level, const float* d_cams, int32_t n_views,
+                                         int32_t width, int32_t height, float* d_out, void* stream)
+{
+    if (!h || n_views < 0 || width < 1 || height < 1 || level < 0 || level > h->L.g.H)
+        return lf_fail(LF_EINVAL, "bad argument");
+    if (n_views == 0) return LF_OK;
+    if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
+    return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream, level);
 }

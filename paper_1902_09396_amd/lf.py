@@ -45,6 +45,8 @@ SIGNATURES = {
     "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
     "lf_render_views": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_render_views_per_ray": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_decode_pixels_lod": (C.c_int, [_P, _I32, _P, _I64, _P, _P]),
+    "lf_render_views_lod": (C.c_int, [_P, _I32, _P, _I32, _I32, _I32, _P, _P]),
     "lf_get_render_config": (C.c_int, [_I32, _I32, _I32, _P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
@@ -145,6 +147,22 @@ class LightField:
         coords = _dev(coords, torch.int32, "coords").reshape(-1, 4)
         out = torch.empty((coords.shape[0], 3), dtype=torch.uint8, device=coords.device)
         check(lib().lf_decode_pixels(self._h, _ptr(coords), coords.shape[0], _ptr(out), _stream()))
+        return out
+
+    def decode_nodes(self, level: int, coords: torch.Tensor) -> torch.Tensor:
+        """Progressive decode: coords int32 [n, 4] (B, A, y, x) of level-`level`
+        nodes on the device -> uint8 [n, 3] RGB of their reconstructed images."""
+        coords = _dev(coords, torch.int32, "coords").reshape(-1, 4)
+        out = torch.empty((coords.shape[0], 3), dtype=torch.uint8, device=coords.device)
+        check(lib().lf_decode_pixels_lod(self._h, level, _ptr(coords), coords.shape[0], _ptr(out), _stream()))
+        return out
+
+    def render_views_lod(self, level: int, cams: torch.Tensor, width: int, height: int) -> torch.Tensor:
+        """Level-of-detail render: every view reads its level-`level` ancestor's image."""
+        cams = _dev(cams, torch.float32, "cams").reshape(-1, 18)
+        out = torch.empty((cams.shape[0], 3, height, width), dtype=torch.float32, device=cams.device)
+        check(lib().lf_render_views_lod(self._h, level, _ptr(cams), cams.shape[0], width, height, _ptr(out),
+                                        _stream()))
         return out
 
     def render_views(self, cams: torch.Tensor, width: int, height: int, out: torch.Tensor | None = None,
