@@ -309,6 +309,43 @@ lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t heig
                     const lf_encode_params* params, int32_t threads, uint8_t** out_stream, size_t* out_bytes);
 void lf_encode_free(uint8_t* stream);
 
+/* The same encoder with the phase-shifted motion search (its costly step)
+ * on the GPU: per level, the SRV planes and the reconstructed reference
+ * planes are uploaded to d_work and every predictive block is searched by
+ * lf_mc_search; quantisation, thresholds and packing stay on the host.
+ * The stream is byte-identical to lf_encode's.  d_work: caller-owned device
+ * workspace of at least lf_encode_workspace_bytes bytes.  Synchronous: the
+ * call waits for its work on `stream` before returning.  Extra errors:
+ * LF_EINVAL for block sizes other than 2..64 in powers of two and windows
+ * with block + 2W + 1 > 96; LF_ENOMEM for a short workspace; LF_EDEVICE. */
+lf_status lf_encode_workspace_bytes(int32_t nb, int32_t na, int32_t height, int32_t width,
+                                    const lf_encode_params* params, int64_t* bytes);
+lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
+                           const lf_encode_params* params, int32_t threads, void* d_work, int64_t work_bytes,
+                           void* stream, uint8_t** out_stream, size_t* out_bytes);
+
+/* Phase-shifted motion search (Phase-shifted Motion Compensation, Eq. 1 and
+ * 2) of n blocks on the GPU.  d_pred: device int16 [n_pred][height][width]
+ * SRV planes to predict; d_ref: device int16 [n_ref][height][width]
+ * reconstructed reference SRV planes.  d_items: device int32 [n][3] =
+ * (pred plane, ref plane, block index k; block k covers rows
+ * (k / (width / block)) * block and columns (k % (width / block)) * block).
+ * For each item: the integer displacement (dx, dy) in [-win, win]^2 and phase
+ * sigma in {+1, -1} minimising sum |p - sigma * R(x + dx, y + dy)| (clamped
+ * reference coordinates), then, if subpel, the +-3 quarter-pel
+ * neighbourhood of each phase's best (bilinear prediction
+ * (sum w * tap + 8) >> 4, within +-4 win); candidates rank by (cost,
+ * |mx| + |my|, my, mx), phase -1 wins only on a strictly lower cost; with
+ * zero_phase, "no prediction" (sigma = 0) wins when strictly cheaper.
+ * d_out: device int32 [n][4] = (mx, my, sigma, cost), mx/my in quarter
+ * pixels, 16-byte aligned.  Per-item errors: cost -1 when the reference
+ * window holds the value -32768 (values must lie in -32767..32767), cost -2
+ * for an item whose indices are out of range.  block: 2, 4, 8, 16, 32 or 64,
+ * dividing width and height; block + 2 win + 1 <= 96; else LF_EINVAL. */
+lf_status lf_mc_search(const int16_t* d_pred, int64_t n_pred, const int16_t* d_ref, int64_t n_ref, int32_t width,
+                       int32_t height, int32_t block, int32_t win, int32_t subpel, int32_t zero_phase,
+                       const int32_t* d_items, int64_t n, int32_t* d_out, void* stream);
+
 /* Message for the calling thread's last non-OK status. */
 const char* lf_last_error(void);
 

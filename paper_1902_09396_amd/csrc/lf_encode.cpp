@@ -21,6 +21,7 @@
 // the result.
 #include <omp.h>
 
+#include <algorithm>
 #include <atomic>
 #include <climits>
 #include <cstdio>
@@ -226,10 +227,16 @@ struct Coded {
 void put32(uint8_t* p, uint32_t v) { memcpy(p, &v, 4); }
 void put64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
 
-}  // namespace
+// device workspace and stream for the motion search (null: search on the host)
+struct DeviceSearch {
+    void* work;
+    int64_t bytes;
+    void* stream;
+};
 
-extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
-                               const lf_encode_params* prm, int32_t threads, uint8_t** out_stream, size_t* out_bytes)
+lf_status encode_impl(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
+                      const lf_encode_params* prm, int32_t threads, const DeviceSearch* dev, uint8_t** out_stream,
+                      size_t* out_bytes)
 {
     if (!host_lf || !prm || !out_stream || !out_bytes) return lf_fail(LF_EINVAL, "null argument");
     const int H = prm->levels, bs = prm->block, w = width, h = height;
@@ -368,6 +375,29 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
             for (int A = 0; A < nal; A++)
                 if ((A | B) & 1) pnodes.push_back(B * nal + A);
         const int64_t items = 3 * npred[l];
+        if (dev && !prm->no_mc && items > 0) {
+            // every predictive block of the level in one device search
+            std::vector<int32_t> work((size_t)(3 * items)), res((size_t)(4 * items));
+            for (int64_t it = 0; it < items; it++) {
+                const int c = (int)(it / npred[l]);
+                const int64_t j = it % npred[l];
+                const int v = pnodes[(size_t)(j / nblk)];
+                const int B = v / nal, A = v % nal;
+                work[(size_t)(3 * it)] = (int32_t)(c * nv + v);
+                work[(size_t)(3 * it + 1)] = (int32_t)(c * nv + (int64_t)(B & ~1) * nal + (A & ~1));
+                work[(size_t)(3 * it + 2)] = (int32_t)(j % nblk);
+            }
+            lf_status st = lf_search_level_device(S.data(), Shat.data(), 3 * nv, w, h, bs, prm->win[l],
+                                                  prm->subpel != 0, prm->zero_phase != 0, work.data(), items,
+                                                  res.data(), dev->work, dev->bytes, dev->stream);
+            if (st != LF_OK) return st;
+            for (int64_t it = 0; it < items; it++) {
+                if (res[(size_t)(4 * it + 3)] < 0) return lf_fail(LF_EINVAL, "search input out of range");
+                mvs[(size_t)((it / npred[l]) * H + l)][(size_t)(it % npred[l])] =
+                    MV{res[(size_t)(4 * it)], res[(size_t)(4 * it + 1)], res[(size_t)(4 * it + 2)]};
+            }
+        }
+        const bool searched = dev && !prm->no_mc;
         std::atomic<int64_t> done{0};
 #pragma omp parallel for schedule(dynamic, 8)
         for (int64_t it = 0; it < items; it++) {
@@ -386,7 +416,10 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
             const int16_t* R = &Shat[(c * nv + rv) * plane];
             const int by0 = (k / nbx) * bs, bx0 = (k % nbx) * bs;
             MV m{0, 0, 0};
-            if (!prm->no_mc) m = search_block(P, R, w, h, by0, bx0, bs, prm->win[l], prm->subpel != 0, prm->zero_phase != 0);
+            if (searched)
+                m = mvs[c * H + l][(size_t)j];
+            else if (!prm->no_mc)
+                m = search_block(P, R, w, h, by0, bx0, bs, prm->win[l], prm->subpel != 0, prm->zero_phase != 0);
             mvs[c * H + l][(size_t)j] = m;
             int e[64 * 64], q[64 * 64], pr[64 * 64];
             for (int i = 0; i < n; i++) {
@@ -497,6 +530,57 @@ extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, i
     *out_stream = s;
     *out_bytes = (size_t)total;
     return LF_OK;
+}
+
+}  // namespace
+
+extern "C" lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
+                               const lf_encode_params* prm, int32_t threads, uint8_t** out_stream, size_t* out_bytes)
+{
+    return encode_impl(host_lf, nb, na, height, width, prm, threads, nullptr, out_stream, out_bytes);
+}
+
+extern "C" lf_status lf_encode_workspace_bytes(int32_t nb, int32_t na, int32_t height, int32_t width,
+                                               const lf_encode_params* prm, int64_t* bytes)
+{
+    if (!prm || !bytes) return lf_fail(LF_EINVAL, "null argument");
+    const int H = prm->levels, bs = prm->block;
+    if (H < 1 || H > LF_MAX_LEVELS || bs < 1 || width < 1 || height < 1 || width % bs || height % bs || na < 1 ||
+        nb < 1)
+        return lf_fail(LF_EINVAL, "bad geometry");
+    int64_t need = 0;
+    if (!prm->no_mc) {
+        int nal = na, nbl = nb;
+        for (int l = 0; l < H; l++) {
+            const int64_t nblk = (int64_t)(width / bs) * (height / bs);
+            const int64_t npred = ((int64_t)(nbl / 2) * nal + (int64_t)((nbl + 1) / 2) * (nal / 2)) * nblk;
+            need = std::max(need, lf_search_work_bytes(3 * (int64_t)nal * nbl, width, height, 3 * npred));
+            nal = (nal + 1) / 2;
+            nbl = (nbl + 1) / 2;
+        }
+    }
+    *bytes = need;
+    return LF_OK;
+}
+
+extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
+                                      const lf_encode_params* prm, int32_t threads, void* d_work, int64_t work_bytes,
+                                      void* stream, uint8_t** out_stream, size_t* out_bytes)
+{
+    int64_t need = 0;
+    lf_status st = lf_encode_workspace_bytes(nb, na, height, width, prm, &need);
+    if (st != LF_OK) return st;
+    if (need > work_bytes || (need > 0 && !d_work)) return lf_fail(LF_ENOMEM, "workspace too small");
+    const int bs = prm->block;
+    if (!prm->no_mc) {
+        if (bs != 2 && bs != 4 && bs != 8 && bs != 16 && bs != 32 && bs != 64)
+            return lf_fail(LF_EINVAL, "device search needs a block size of 2, 4, 8, 16, 32 or 64");
+        for (int l = 0; l < prm->levels; l++)
+            if (prm->win[l] < 0 || bs + 2 * prm->win[l] + 1 > 96)
+                return lf_fail(LF_EINVAL, "device search window too large at level %d", l);
+    }
+    const DeviceSearch dev{d_work, work_bytes, stream};
+    return encode_impl(host_lf, nb, na, height, width, prm, threads, &dev, out_stream, out_bytes);
 }
 
 extern "C" void lf_encode_free(uint8_t* p) { free(p); }

@@ -56,6 +56,9 @@ SIGNATURES = {
     "lf_render_backward": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _P, _I64, _P]),
     "lf_encode": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "lf_encode_free": (None, [_P]),
+    "lf_encode_workspace_bytes": (C.c_int, [_I32, _I32, _I32, _I32, _P, _P]),
+    "lf_encode_device": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _I64, _P, _P, _P]),
+    "lf_mc_search": (C.c_int, [_P, _I64, _P, _I64, _I32, _I32, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "lf_last_error": (C.c_char_p, []),
 }
 
@@ -250,22 +253,55 @@ class EncodeParams(C.Structure):
                 ("no_mc", C.c_int32)]
 
 
-def encode(light_field: np.ndarray, enc: dict, threads: int = 0) -> np.ndarray:
-    """Encode a uint8 [nb][na][h][w][3] light field on the host; returns the stream bytes."""
+def encode(light_field: np.ndarray, enc: dict, threads: int = 0, device: bool = False) -> np.ndarray:
+    """Encode a uint8 [nb][na][h][w][3] light field; returns the stream bytes.
+
+    device=True runs the motion search on the current GPU (same stream bytes)."""
     lf = np.ascontiguousarray(light_field, dtype=np.uint8)
     nb, na, h, w, _ = lf.shape
+    p = _encode_params(enc)
+    out = C.c_void_p()
+    n = C.c_size_t()
+    if device:
+        need = C.c_int64()
+        check(lib().lf_encode_workspace_bytes(nb, na, h, w, C.byref(p), C.byref(need)))
+        work = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device="cuda")
+        check(lib().lf_encode_device(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads,
+                                     _ptr(work), work.numel(), _stream(), C.byref(out), C.byref(n)))
+        del work
+    else:
+        check(lib().lf_encode(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads, C.byref(out),
+                              C.byref(n)))
+    buf = np.ctypeslib.as_array(C.cast(out, C.POINTER(C.c_uint8)), shape=(n.value,)).copy()
+    lib().lf_encode_free(out)
+    return buf
+
+
+def mc_search(pred: torch.Tensor, ref: torch.Tensor, items: torch.Tensor, block: int, win: int,
+              subpel: bool = True, zero_phase: bool = False) -> torch.Tensor:
+    """Phase-shifted motion search on the device.
+
+    pred, ref: int16 [planes, h, w]; items: int32 [n, 3] (pred plane, ref plane,
+    block index) -> int32 [n, 4] (mx, my, sigma, cost)."""
+    pred = _dev(pred, torch.int16, "pred")
+    ref = _dev(ref, torch.int16, "ref")
+    items = _dev(items, torch.int32, "items").reshape(-1, 3)
+    if pred.dim() != 3 or ref.dim() != 3 or pred.shape[1:] != ref.shape[1:]:
+        raise ValueError("pred and ref must be [planes, h, w] with the same plane size")
+    out = torch.empty((items.shape[0], 4), dtype=torch.int32, device=items.device)
+    check(lib().lf_mc_search(_ptr(pred), pred.shape[0], _ptr(ref), ref.shape[0], pred.shape[2], pred.shape[1], block,
+                             win, int(subpel), int(zero_phase), _ptr(items), items.shape[0], _ptr(out), _stream()))
+    return out
+
+
+def _encode_params(enc: dict):
     p = EncodeParams()
     p.levels, p.block = enc["levels"], enc["block"]
     for l in range(enc["levels"]):
         p.step[l], p.t_ref[l], p.t_pred[l], p.win[l] = enc["step"][l], enc["t_ref"][l], enc["t_pred"][l], enc["win"][l]
     p.subpel, p.zero_phase, p.no_mc = int(enc.get("subpel", True)), int(enc.get("zero_phase", False)), \
         int(enc.get("no_mc", False))
-    out = C.c_void_p()
-    n = C.c_size_t()
-    check(lib().lf_encode(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads, C.byref(out), C.byref(n)))
-    buf = np.ctypeslib.as_array(C.cast(out, C.POINTER(C.c_uint8)), shape=(n.value,)).copy()
-    lib().lf_encode_free(out)
-    return buf
+    return p
 
 
 def query_arena(stream) -> int:
