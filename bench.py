@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="serving workload instead: resident light fields, Poisson view requests")
     ap.add_argument("--serve-fields", default="serve256,path512,serve1024,batch1080")
+    ap.add_argument("--encode", action="store_true",
+                    help="encoder: GPU phase-shifted motion search throughput and whole-field encode time")
     ap.add_argument("--grad", action="store_true",
                     help="differentiation workload instead: relaxed render + adjoint of 16 views")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
@@ -95,6 +97,9 @@ def main():
         return
     if args.grad:
         grad_bench(args)
+        return
+    if args.encode:
+        encode_bench(args)
         return
     cfg = lfscene.get_config(args.workload)
     L = cfg["lf"]
@@ -322,6 +327,97 @@ def grad_bench(args):
         "gradient_bytes": int((res.numel() + sh.numel()) * 4),
         "nonzero_residual_grads": int((g_res != 0).sum().item()),
     }), flush=True)
+
+
+def encode_bench(args):
+    """Encoder side of the 17x17x512x512 field: the phase-shifted motion
+    search of every level-0 predictive block (3 channels x 208 views x 1024
+    blocks of 16x16, W = 8, quarter-pel refinement) as one lf_mc_search
+    launch, and the whole encode with the search on the host and on the GPU
+    (identical streams).  Search planes: channel c of each predictive view
+    and of its cluster's reference view; the kernel's work does not depend on
+    the values."""
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+
+    cfg = lfscene.get_config(args.workload)
+    L, enc = cfg["lf"], cfg["enc"]
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    host_stream = lf.encode(light, enc, threads=threads)
+    t_host = time.time() - t0
+    log("host encode %.2fs" % t_host)
+    lf.encode(light, enc, device=True)  # first call pays for module load and allocator growth
+    torch.cuda.synchronize()
+    t0 = time.time()
+    dev_stream = lf.encode(light, enc, threads=threads, device=True)
+    t_dev = time.time() - t0
+    log("device-search encode %.2fs" % t_dev)
+    assert np.array_equal(host_stream, dev_stream), "device search changed the stream"
+
+    nb, na, h, w = light.shape[:4]
+    bs, win = enc["block"], enc["win"][0]
+    pred_views = [(b, a) for b in range(nb) for a in range(na) if (a | b) & 1]
+    ref_views = [(b, a) for b in range(0, nb, 2) for a in range(0, na, 2)]
+    ref_index = {v: i for i, v in enumerate(ref_views)}
+    pred = np.stack([light[b, a, :, :, c] for c in range(3) for (b, a) in pred_views]).astype(np.int16)
+    ref = np.stack([light[b, a, :, :, c] for c in range(3) for (b, a) in ref_views]).astype(np.int16)
+    nblk = (h // bs) * (w // bs)
+    items = np.array([(c * len(pred_views) + j, c * len(ref_views) + ref_index[(b & ~1, a & ~1)], k)
+                      for c in range(3) for j, (b, a) in enumerate(pred_views) for k in range(nblk)], dtype=np.int32)
+    P, R, I = (torch.from_numpy(x).cuda() for x in (pred, ref, items))
+    s = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        out = lf.mc_search(P, R, I, bs, win)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(args.steps):
+        out = lf.mc_search(P, R, I, bs, win)
+    b.record(s)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    n = items.shape[0]
+    # algorithmic work: one |p - prediction| term per pixel, candidate and phase
+    ops_per_block = bs * bs * (2 * (2 * win + 1) ** 2 + 2 * 48)
+    achieved = n * ops_per_block / (ms * 1e-3) / 1e12
+    peak = 256 * 64 * 2 * 2.4e9 / 1e12  # v_sad_u16: two pixel terms per lane and clock
+    result = {
+        "metric": "phase-shifted motion search: predictive blocks searched per second",
+        "value": round(n / (ms * 1e-3) / 1e6, 3), "unit": "Mblocks/s", "higher_is_better": True,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "dtype": "i16/u32",
+        "data": "synthetic",
+        "config": {"workload": "level-0 search of the 17x17x512x512 field: %d blocks of %dx%d, W = %d, both "
+                               "phases, quarter-pel refinement" % (n, bs, bs, win)},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "Tops/s",
+                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": "k_mc_search",
+                     "ops_per_block": ops_per_block},
+        "encode_seconds": {"host_search": round(t_host, 2), "gpu_search": round(t_dev, 2),
+                           "host_threads": threads, "stream_bytes": int(host_stream.size)},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        rng = np.random.default_rng(3)
+        order = rng.permutation(n)[:200000]
+        p32 = [pred[i].astype(np.int32) for i in sorted(set(items[order, 0]))]  # planes converted once, untimed
+        p32 = dict(zip(sorted(set(items[order, 0])), p32))
+        r32 = {i: ref[i].astype(np.int32) for i in sorted(set(items[order, 1]))}
+        t0 = time.perf_counter()
+        done = 0
+        for idx in order:
+            pi, ri, k = items[idx]
+            oracle.mc_search(p32[pi], r32[ri], (k // (w // bs)) * bs, (k % (w // bs)) * bs, bs, win, True, False)
+            done += 1
+            if time.perf_counter() - t0 > 12.0:
+                break
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(done / dt / 1e6, 6), "unit": "Mblocks/s", "cores": 1,
+                                  "kind": "oracle", "sample": "%d random blocks of the same search, %.1f s" % (done, dt)}
+    print(json.dumps(result), flush=True)
 
 
 def cpu_baseline(cfg, light, cams_np, wo, ho, n_rays):

@@ -338,9 +338,9 @@ lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_t na, int32
  * |mx| + |my|, my, mx), phase -1 wins only on a strictly lower cost; with
  * zero_phase, "no prediction" (sigma = 0) wins when strictly cheaper.
  * d_out: device int32 [n][4] = (mx, my, sigma, cost), mx/my in quarter
- * pixels, 16-byte aligned.  Per-item errors: cost -1 when the reference
- * window holds the value -32768 (values must lie in -32767..32767), cost -2
- * for an item whose indices are out of range.  block: 2, 4, 8, 16, 32 or 64,
+ * pixels, 16-byte aligned.  Per-item errors: cost -1 when the block to
+ * predict holds the value -32768 (reference values may span the whole int16
+ * range), cost -2 for an item whose indices are out of range.  block: 2, 4, 8, 16, 32 or 64,
  * dividing width and height; block + 2 win + 1 <= 96; else LF_EINVAL. */
 lf_status lf_mc_search(const int16_t* d_pred, int64_t n_pred, const int16_t* d_ref, int64_t n_ref, int32_t width,
                        int32_t height, int32_t block, int32_t win, int32_t subpel, int32_t zero_phase,

@@ -15,11 +15,13 @@
 // 32768, twice: as pixel pairs starting at even and at odd columns, so every
 // pair a candidate needs is one aligned dword.
 //  - integer candidates: v_sad_u16 adds |p - r| for two pixels per
-//    instruction; the -1 phase compares with the packed negation of the
-//    biased pair, since p + r = p - (-r) and 32768 - r = -(r + 32768) mod 2^16;
+//    instruction; the -1 phase compares the packed negation of the biased
+//    block, 32768 - p = -(p + 32768) mod 2^16, with the same reference pair,
+//    since |p + r| = |(32768 - p) - (r + 32768)|;
 //  - quarter-pel candidates: v_dot2_u32_u16 applies two bilinear weights per
 //    instruction to biased taps; the weights sum to 16, so the bias passes
-//    through the rounding shift exactly.
+//    through the rounding shift exactly.  Two lanes share a candidate (eight
+//    rows each), and each lane carries the lower tap row to the next row.
 // A ranking key packs (cost, |mx| + |my|, my, mx) into 64 bits; each phase's
 // best is a wave-wide minimum.
 #include <hip/hip_runtime.h>
@@ -85,11 +87,11 @@ __host__ __device__ inline int window_dwords(int D) { return (D / 2) | 1; }
 __host__ __device__ inline int search_lds_dwords(int bs, int win)
 {
     const int D = bs + 2 * win + 1;
-    return 2 * D * window_dwords(D) + bs * bs / 2;
+    return 2 * D * window_dwords(D) + bs * bs;
 }
 
 template <int BS>
-__global__ void __launch_bounds__(64) k_mc_search(const int16_t* __restrict__ pred, const int16_t* __restrict__ ref,
+__global__ void __launch_bounds__(64, BS >= 32 ? 3 : 8) k_mc_search(const int16_t* __restrict__ pred, const int16_t* __restrict__ ref,
                                                   int64_t n_pred, int64_t n_ref, int w, int h, int win, int subpel,
                                                   int zero_phase, const int32_t* __restrict__ items, int64_t n,
                                                   int32_t* __restrict__ out)
@@ -103,8 +105,9 @@ __global__ void __launch_bounds__(64) k_mc_search(const int16_t* __restrict__ pr
     const int D = BS + 2 * win + 1, Dj = window_dwords(D);
     uint32_t* E = lds;
     uint32_t* O = lds + D * Dj;
-    uint32_t* Pb = lds + 2 * D * Dj;
     constexpr int HB = BS / 2;  // pixel pairs per block row
+    uint32_t* Pb = lds + 2 * D * Dj;
+    uint32_t* Pn = Pb + BS * HB;  // negated block: 32768 - p
 
     const int64_t pi = items[3 * it], ri = items[3 * it + 1];
     const int k = items[3 * it + 2];
@@ -125,60 +128,62 @@ __global__ void __launch_bounds__(64) k_mc_search(const int16_t* __restrict__ pr
         const int c0 = bx0 - win + 2 * j;
         const int v0 = row[min(max(c0, 0), w - 1)], v1 = row[min(max(c0 + 1, 0), w - 1)],
                   v2 = row[min(max(c0 + 2, 0), w - 1)];
-        bad |= v0 == -32768 || v1 == -32768 || v2 == -32768;
         E[e] = (uint32_t)(v0 + 32768) | ((uint32_t)(v1 + 32768) << 16);
         O[e] = (uint32_t)(v1 + 32768) | ((uint32_t)(v2 + 32768) << 16);
     }
     for (int e = lane; e < BS * HB; e += 64) {
         const int y = e / HB, i = e - y * HB;
         const int16_t* px = P + (int64_t)(by0 + y) * w + bx0 + 2 * i;
-        Pb[e] = (uint32_t)(px[0] + 32768) | ((uint32_t)(px[1] + 32768) << 16);
+        const int p0 = px[0], p1 = px[1];
+        bad |= p0 == -32768 || p1 == -32768;
+        Pb[e] = (uint32_t)(p0 + 32768) | ((uint32_t)(p1 + 32768) << 16);
+        Pn[e] = (uint32_t)(32768 - p0) | ((uint32_t)(32768 - p1) << 16);
     }
     bad = __ballot(bad) != 0;
     __syncthreads();
 
     // ---- integer displacements, both phases in one pass ----
-    const int WD = 2 * win + 1, NP = WD * WD;
+    // A task is one window row offset dy and three offsets dx0, dx0 + 2,
+    // dx0 + 4 of one parity: the three share the reference dwords of a row
+    // (offset dx0 + 2u starts u dwords later), so each loaded dword serves
+    // six absolute-difference instructions.
+    const int ne = win + 1, no = win;  // even / odd offsets in [0, 2W]
+    const int ge = (ne + 2) / 3, go = (no + 2) / 3, gpr = ge + go;
+    const int n_tasks = (2 * win + 1) * gpr;
     uint64_t bestp = ~0ull, bestm = ~0ull;
-    constexpr int NBM = BS >= 32 ? 4 : 8;  // candidates per lane per pass
-    for (int base = 0; base < NP; base += 64 * NBM) {
-        const int nb = min(NBM, (NP - base + 63) / 64);
-        uint32_t accp[NBM], accm[NBM];
-        int roff[NBM];
-#pragma unroll
-        for (int j = 0; j < NBM; j++) {
-            accp[j] = 0;
-            accm[j] = 0;
-            const int q = min(base + j * 64 + lane, NP - 1);
-            const int dy = q / WD, dx = q - dy * WD;  // window offsets in [0, 2W]
-            roff[j] = ((dx & 1) ? D * Dj : 0) + dy * Dj + (dx >> 1);
-        }
+    for (int t = lane; t - lane < n_tasks; t += 64) {
+        const bool active = t < n_tasks;
+        const int tt = active ? t : 0;
+        const int dy = tt / gpr, g = tt - dy * gpr;
+        const int par = g >= ge;
+        const int dx0 = par + 6 * (par ? g - ge : g);
+        const uint32_t* r = lds + (par ? D * Dj : 0) + dy * Dj + (dx0 >> 1);
+        uint32_t acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll 2
         for (int y = 0; y < BS; y++) {
-            uint32_t pr[HB];
+            uint32_t rv[HB + 2];
 #pragma unroll
-            for (int i = 0; i < HB; i++) pr[i] = Pb[y * HB + i];
+            for (int i = 0; i < HB + 2; i++) rv[i] = r[y * Dj + i];
 #pragma unroll
-            for (int j = 0; j < NBM; j++) {
-                if (j < nb) {
-                    const uint32_t* r = lds + roff[j] + y * Dj;
+            for (int i = 0; i < HB; i++) {
+                const uint32_t pp = Pb[y * HB + i], pm = Pn[y * HB + i];
 #pragma unroll
-                    for (int i = 0; i < HB; i++) {
-                        const uint32_t rv = r[i];
-                        accp[j] = sad2(pr[i], rv, accp[j]);
-                        accm[j] = sad2(pr[i], pk_neg(rv), accm[j]);
-                    }
+                for (int u = 0; u < 3; u++) {
+                    acc[u][0] = sad2(pp, rv[i + u], acc[u][0]);
+                    acc[u][1] = sad2(pm, rv[i + u], acc[u][1]);
                 }
             }
         }
+        if (active) {
 #pragma unroll
-        for (int j = 0; j < NBM; j++) {
-            const int q = base + j * 64 + lane;
-            if (j < nb && q < NP) {
-                const int dy = q / WD, dx = q - dy * WD;
-                const int mx = 4 * (dx - win), my = 4 * (dy - win);
-                const uint64_t kp = mv_key(accp[j], mx, my), km = mv_key(accm[j], mx, my);
-                bestp = kp < bestp ? kp : bestp;
-                bestm = km < bestm ? km : bestm;
+            for (int u = 0; u < 3; u++) {
+                const int dx = dx0 + 2 * u;
+                if (dx <= 2 * win) {
+                    const int mx = 4 * (dx - win), my = 4 * (dy - win);
+                    const uint64_t kp = mv_key(acc[u][0], mx, my), km = mv_key(acc[u][1], mx, my);
+                    bestp = kp < bestp ? kp : bestp;
+                    bestm = km < bestm ? km : bestm;
+                }
             }
         }
     }
@@ -186,40 +191,58 @@ __global__ void __launch_bounds__(64) k_mc_search(const int16_t* __restrict__ pr
     bestm = wave_min64(bestm);
 
     // ---- quarter-pel refinement: 48 offsets around each phase's best ----
+    // 96 candidates x 2 row halves = 3 rounds of the wave; lanes 2m and 2m + 1
+    // take the two halves of one candidate
     if (subpel && win > 0) {
         const int lim = 4 * win;
         const int cxp = key_mx(bestp), cyp = key_my(bestp), cxm = key_mx(bestm), cym = key_my(bestm);
         uint64_t kq0 = ~0ull, kq1 = ~0ull;
-        for (int c = lane; c < 96; c += 64) {
+        constexpr int HR = BS / 2;  // rows per half
+        for (int u = lane; u < 192; u += 64) {
+            const int c = u >> 1, half = u & 1;
             const int s = c >= 48;
             const int o = c - 48 * s;
             const int oo = o + (o >= 24);  // skip the centre of the 7x7 neighbourhood
             const int qx = (s ? cxm : cxp) + oo % 7 - 3, qy = (s ? cym : cyp) + oo / 7 - 3;
-            if (qx < -lim || qx > lim || qy < -lim || qy > lim) continue;
-            const int fx = qx & 3, fy = qy & 3;
-            const int ox = win + (qx >> 2), oy = win + (qy >> 2);  // window position of the top-left tap
-            const u16x2 wa = {(unsigned short)((4 - fx) * (4 - fy)), (unsigned short)(fx * (4 - fy))};
-            const u16x2 wb = {(unsigned short)((4 - fx) * fy), (unsigned short)(fx * fy)};
-            // pixel x of a row starts its tap pair at column ox + x: even x in the
-            // copy of ox's parity, odd x in the other one
-            const uint32_t* A = ((ox & 1) ? O : E) + (ox >> 1);
-            const uint32_t* B = ((ox & 1) ? E : O) + ((ox + 1) >> 1);
+            const bool ok = qx >= -lim && qx <= lim && qy >= -lim && qy <= lim;
             uint32_t acc = 0;
-            for (int y = 0; y < BS; y++) {
-                const int r0 = (oy + y) * Dj, r1 = r0 + Dj;
+            if (ok) {
+                const int fx = qx & 3, fy = qy & 3;
+                const int ox = win + (qx >> 2), oy = win + (qy >> 2) + half * HR;  // window position of the first tap
+                const u16x2 wa = {(unsigned short)((4 - fx) * (4 - fy)), (unsigned short)(fx * (4 - fy))};
+                const u16x2 wb = {(unsigned short)((4 - fx) * fy), (unsigned short)(fx * fy)};
+                // pixel x of a row starts its tap pair at column ox + x: even x in
+                // the copy of ox's parity, odd x in the other one
+                const uint32_t* A = ((ox & 1) ? O : E) + (ox >> 1) + oy * Dj;
+                const uint32_t* B = ((ox & 1) ? E : O) + ((ox + 1) >> 1) + oy * Dj;
+                const uint32_t* Pp = (s ? Pn : Pb) + half * HR * HB;
+                uint32_t a0[HB], b0[HB];
 #pragma unroll
                 for (int i = 0; i < HB; i++) {
-                    const uint32_t t0 = dot2(A[r0 + i], wa, dot2(A[r1 + i], wb, 8u)) >> 4;
-                    const uint32_t t1 = dot2(B[r0 + i], wa, dot2(B[r1 + i], wb, 8u)) >> 4;
-                    const uint32_t q = t0 | (t1 << 16);
-                    acc = sad2(Pb[y * HB + i], s ? pk_neg(q) : q, acc);
+                    a0[i] = A[i];
+                    b0[i] = B[i];
+                }
+                for (int y = 0; y < HR; y++) {
+                    const int r1 = (y + 1) * Dj;
+#pragma unroll
+                    for (int i = 0; i < HB; i++) {
+                        const uint32_t a1 = A[r1 + i], b1 = B[r1 + i];
+                        const uint32_t t0 = dot2(a0[i], wa, dot2(a1, wb, 8u)) >> 4;
+                        const uint32_t t1 = dot2(b0[i], wa, dot2(b1, wb, 8u)) >> 4;
+                        acc = sad2(Pp[y * HB + i], t0 | (t1 << 16), acc);
+                        a0[i] = a1;
+                        b0[i] = b1;
+                    }
                 }
             }
-            const uint64_t key = mv_key(acc, qx, qy);
-            if (s)
-                kq1 = key < kq1 ? key : kq1;
-            else
-                kq0 = key < kq0 ? key : kq0;
+            acc += __shfl_xor(acc, 1, 64);
+            if (ok && half == 0) {
+                const uint64_t key = mv_key(acc, qx, qy);
+                if (s)
+                    kq1 = key < kq1 ? key : kq1;
+                else
+                    kq0 = key < kq0 ? key : kq0;
+            }
         }
         const uint64_t k0 = wave_min64(kq0), k1 = wave_min64(kq1);
         bestp = k0 < bestp ? k0 : bestp;

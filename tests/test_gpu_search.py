@@ -115,13 +115,15 @@ def test_search_errors(torch_mod):
     rng = np.random.default_rng(8)
     pred = rng.integers(-300, 300, (2, 32, 32)).astype(np.int16)
     ref = rng.integers(-300, 300, (2, 32, 32)).astype(np.int16)
-    ref[1, 0, 0] = -32768
-    items = np.array([[0, 0, 0], [0, 1, 0], [0, 1, 3], [2, 0, 0], [0, 0, 4], [-1, 0, 0]], dtype=np.int32)
-    got = _run(torch, pred, ref, items, 16, 4)
-    assert np.array_equal(got[0], _expect(pred, ref, items[:1], 16, 4)[0])
-    assert got[1, 3] == -1  # window holds -32768
-    assert got[2, 3] != -1  # block 3 (bottom right) is 16 pixels from (0, 0), beyond its window
-    assert np.all(got[3:, 3] == -2) and np.all(got[3:, :3] == 0)  # bad plane / block indices
+    ref[1, 0:3, 0:3] = -32768  # the reference may hold the int16 minimum
+    pred[1, 5, 5] = -32768  # the predicted block may not
+    items = np.array([[0, 0, 0], [0, 1, 0], [1, 1, 0], [1, 1, 3], [2, 0, 0], [0, 0, 4], [-1, 0, 0]], dtype=np.int32)
+    for zp in (False, True):
+        got = _run(torch, pred, ref, items, 16, 4, True, zp)
+        assert np.array_equal(got[:2], _expect(pred, ref, items[:2], 16, 4, True, zp))
+        assert tuple(got[2]) == (0, 0, 0, -1)  # block 0 of plane 1 holds -32768
+        assert np.array_equal(got[3], _expect(pred, ref, items[3:4], 16, 4, True, zp)[0])
+        assert np.all(got[4:, 3] == -2) and np.all(got[4:, :3] == 0)  # bad plane / block indices
     P, R, I = (torch.from_numpy(a).cuda() for a in (pred, ref, items))
     for bs, win in ((12, 2), (16, 40), (64, 16)):
         with pytest.raises(lf.LFError) as e:
