@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--serve-fields", default="serve256,path512,serve1024,batch1080")
     ap.add_argument("--encode", action="store_true",
                     help="encoder: GPU phase-shifted motion search throughput and whole-field encode time")
+    ap.add_argument("--rd", action="store_true",
+                    help="rate-distortion sweeps (block size, search window, block threshold) on the synthetic field")
     ap.add_argument("--grad", action="store_true",
                     help="differentiation workload instead: relaxed render + adjoint of 16 views")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="requests per second")
@@ -100,6 +102,9 @@ def main():
         return
     if args.encode:
         encode_bench(args)
+        return
+    if args.rd:
+        rd_bench(args)
         return
     cfg = lfscene.get_config(args.workload)
     L = cfg["lf"]
@@ -418,6 +423,89 @@ def encode_bench(args):
         result["cpu_baseline"] = {"value": round(done / dt / 1e6, 6), "unit": "Mblocks/s", "cores": 1,
                                   "kind": "oracle", "sample": "%d random blocks of the same search, %.1f s" % (done, dt)}
     print(json.dumps(result), flush=True)
+
+
+def decode_field(field, nb, na, h, w):
+    """Every sample of every view, decoded on the GPU: uint8 [nb][na][h][w][3]."""
+    import torch
+
+    y, x = torch.meshgrid(torch.arange(h, dtype=torch.int32, device="cuda"),
+                          torch.arange(w, dtype=torch.int32, device="cuda"), indexing="ij")
+    yx = torch.stack([y.reshape(-1), x.reshape(-1)], 1)
+    out = torch.empty((nb, na, h * w, 3), dtype=torch.uint8, device="cuda")
+    coords = torch.empty((h * w, 4), dtype=torch.int32, device="cuda")
+    coords[:, 2:] = yx
+    for b in range(nb):
+        for a in range(na):
+            coords[:, 0] = b
+            coords[:, 1] = a
+            out[b, a] = field.decode_pixels(coords)
+    return out.reshape(nb, na, h, w, 3)
+
+
+def rd_point(light, enc, light_dev=None):
+    """(bits per light-field pixel, PSNR in dB over all RGB samples, stream
+    bytes, bytes of the per-block random-access table inside the stream)."""
+    import torch
+
+    from paper_1902_09396_amd import lf
+
+    stream = lf.encode(light, enc, threads=min(16, os.cpu_count() or 1), device=True)
+    nb, na, h, w = light.shape[:4]
+    field = lf.LightField(stream, device="cuda:0")
+    dec = decode_field(field, nb, na, h, w)
+    field.close()
+    src = light_dev if light_dev is not None else torch.from_numpy(light).cuda()
+    mse = ((dec.to(torch.float64) - src.to(torch.float64)) ** 2).mean().item()
+    psnr = float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)
+    table_bytes = int(np.frombuffer(stream[136:144].tobytes(), np.uint64)[0])
+    return 8.0 * stream.size / (nb * na * h * w), psnr, int(stream.size), table_bytes
+
+
+def rd_bench(args):
+    """Synthetic analogues of the paper's rate-distortion studies (Table 2:
+    block size at threshold 75, window 16, tree height 3; Fig. 5: search
+    window at block size 4, tree height 3; the threshold sweep of HMLFC
+    against the plain hierarchy without motion compensation) on the
+    17x17x512x512 synthetic field.  Streams come from the encoder with the
+    GPU search; PSNR is over every decoded RGB sample of every view."""
+    import torch
+
+    import lfscene
+
+    cfg = lfscene.get_config(args.workload)
+    L = cfg["lf"]
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    light_dev = torch.from_numpy(light).cuda()
+    H = 3
+
+    def enc(block, win, thr, no_mc=False, step=4):
+        e = dict(cfg["enc"])
+        e.update(levels=H, block=block, step=[step] * H, win=[win] * H, t_ref=[thr] * H, t_pred=[thr] * H,
+                 no_mc=no_mc)
+        return e
+
+    def point(name, e):
+        t0 = time.time()
+        bpp, psnr, nbytes, tbytes = rd_point(light, e, light_dev)
+        log("%s: %.4f bpp, %.2f dB (%.1fs)" % (name, bpp, psnr, time.time() - t0))
+        return {"bpp": round(bpp, 5), "bpp_without_table": round(bpp * (nbytes - tbytes) / nbytes, 5),
+                "psnr_db": round(psnr, 3), "bytes": nbytes}
+
+    table2 = {str(bs): point("block %d" % bs, enc(bs, 16, 75)) for bs in (2, 4, 8)}
+    fig5 = {str(wn): point("window %d" % wn, enc(4, wn, 75)) for wn in (1, 2, 4, 8, 16)}
+    thr = {}
+    for t in (0, 25, 75, 150, 300, 600):
+        thr[str(t)] = {"hmlfc": point("threshold %d" % t, enc(4, 16, t)),
+                       "no_mc": point("threshold %d, no MC" % t, enc(4, 16, t, no_mc=True))}
+    print(json.dumps({
+        "metric": "rate-distortion sweeps: bits per light-field pixel and PSNR",
+        "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": "17x17x512x512 synthetic field, tree height %d, quantisation step 4" % H},
+        "block_size_at_threshold75_window16": table2,
+        "window_at_block4_threshold75": fig5,
+        "threshold_at_block4_window16": thr,
+    }), flush=True)
 
 
 def cpu_baseline(cfg, light, cams_np, wo, ho, n_rays):

@@ -158,3 +158,19 @@ def test_device_encoder_odd_grid(torch_mod):
     with pytest.raises(lf.LFError) as e:
         lf.encode(x, enc, device=True)
     assert e.value.status == lf.LF_EINVAL
+
+
+def test_rd_point_lossless_and_lossy(torch_mod, tiny_lf):
+    """The rate-distortion measurement: a lossless stream decodes to the
+    source (infinite PSNR); a lossy one has the PSNR of the oracle's decode."""
+    import bench
+
+    enc = lfscene.get_config("tiny", step=1)["enc"]
+    bpp, psnr, nbytes, tbytes = bench.rd_point(tiny_lf, enc)
+    assert psnr == float("inf") and nbytes == stream_for("tiny", tiny_lf, step=1).size
+    assert bpp == 8.0 * nbytes / tiny_lf[..., 0].size and 0 < tbytes < nbytes
+    enc = lfscene.get_config("tiny", step=8, t_ref=200, t_pred=400)["enc"]
+    bpp, psnr, nbytes, _ = bench.rd_point(tiny_lf, enc)
+    dec = oracle.OracleLF(stream_for("tiny", tiny_lf, step=8, t_ref=200, t_pred=400)).decode_full()
+    mse = ((dec.astype(np.float64) - tiny_lf.astype(np.float64)) ** 2).mean()
+    assert abs(psnr - 10 * np.log10(255.0 ** 2 / mse)) < 1e-9
