@@ -164,9 +164,15 @@ __global__ void __launch_bounds__(64, BS >= 32 ? 3 : 8) k_mc_search(const int16_
             uint32_t rv[HB + 2];
 #pragma unroll
             for (int i = 0; i < HB + 2; i++) rv[i] = r[y * Dj + i];
+            // the block row is the same for every lane: scalar loads from the
+            // plane (4-byte aligned: w and bx0 are even), biased and negated
+            // per 16-bit half in scalar registers
+            const uint32_t* prow = reinterpret_cast<const uint32_t*>(P + (int64_t)(by0 + y) * w + bx0);
 #pragma unroll
             for (int i = 0; i < HB; i++) {
-                const uint32_t pp = Pb[y * HB + i], pm = Pn[y * HB + i];
+                const uint32_t raw = prow[i];
+                const uint32_t pp = raw ^ BIAS2;
+                const uint32_t pm = ((0x8000u - (raw & 0xFFFFu)) & 0xFFFFu) | ((0x8000u - (raw >> 16)) << 16);
 #pragma unroll
                 for (int u = 0; u < 3; u++) {
                     acc[u][0] = sad2(pp, rv[i + u], acc[u][0]);
