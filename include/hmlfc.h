@@ -75,7 +75,17 @@ typedef struct {
     int64_t arena_bytes;     /* device bytes the handle occupies              */
     int64_t stream_bytes;    /* compressed stream size                        */
     int64_t payload_bytes;   /* block payload section size                    */
+    int64_t ref_bytes;       /* device bytes of the resident reference SRVs   */
+    int32_t sparse_refs;     /* 1: loaded with LF_LOAD_SPARSE_REFS            */
 } lf_info;
+
+/* Load flag: keep the reference SRVs block-sparse (only significant blocks,
+ * as int16 tiles, plus a tile index per block) instead of dense planes — the
+ * reduced-memory reference storage of the Decompression Analysis.  Every
+ * result is unchanged.  A sparse handle serves lf_decode_pixels(_lod),
+ * lf_render_views(_per_ray, _lod) (one thread per ray) and the relaxed
+ * render and adjoint; the serving loop rejects it. */
+#define LF_LOAD_SPARSE_REFS 1
 
 /* ---------------------------------------------------------------------- */
 /* Loading (Decompression Memory Overhead: the top-level RKVs and every    */
@@ -101,6 +111,16 @@ lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_
  * small), LF_EDEVICE. */
 lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
                              void* stream, lf_handle** out);
+
+/* lf_query_arena / lf_load_compressed with load flags (0 or
+ * LF_LOAD_SPARSE_REFS; other bits: LF_EINVAL).  Sparse arena sections:
+ * root, block table, payload, motion vectors, reference tiles (int16
+ * [n_tiles][Bs][Bs], significant reference blocks in (channel, reference
+ * node, block) order), tile index (int32 [3][n_refs][n_blocks], -1 for a
+ * zero block), status; no descriptors. */
+lf_status lf_query_arena_ex(const void* host_stream, size_t nbytes, int32_t flags, int64_t* arena_bytes);
+lf_status lf_load_compressed_ex(const void* host_stream, size_t nbytes, int32_t flags, void* d_arena,
+                                int64_t arena_bytes, void* stream, lf_handle** out);
 
 /* Release the host-side handle (the arena stays the caller's). */
 lf_status lf_free(lf_handle* h);

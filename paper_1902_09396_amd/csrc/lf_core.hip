@@ -3,11 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/hmlfc.h"
 #include "lf_geom.h"
@@ -182,14 +182,66 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     return LF_OK;
 }
 
-extern "C" lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_bytes)
+// Sparse reference residency: significant blocks of the reference SRVs take
+// consecutive tiles in (channel, reference node, block) order; a block coded
+// as insignificant decodes to zero and takes none.  Writes the tile of every
+// reference block to slots (when given) and returns the tile count.
+static int64_t lf_ref_slots(const uint8_t* s, const LfLayout& L, int32_t* slots)
+{
+    const LfGeom& g = L.g;
+    const uint8_t* tab = s + L.table_off;
+    int64_t n = 0;
+    for (int c = 0; c < 3; c++)
+        for (int l = 0; l < g.H; l++)
+            for (int Bp = 0; Bp < g.nb_l[l + 1]; Bp++)
+                for (int Ap = 0; Ap < g.na_l[l + 1]; Ap++) {
+                    const int64_t node = g.node_base[l] + 2 * Bp * g.na_l[l] + 2 * Ap;
+                    const int64_t rp = (int64_t)c * g.n_refs + g.ref_base[l] + (int64_t)Bp * g.na_l[l + 1] + Ap;
+                    const uint8_t* e = tab + 8 * (((int64_t)c * g.n_nodes + node) * g.nblk);
+                    for (int blk = 0; blk < g.nblk; blk++) {
+                        const bool sig = e[8 * blk + 6] != LF_MODE_ZERO;
+                        if (slots) slots[rp * g.nblk + blk] = sig ? (int32_t)n : -1;
+                        n += sig;
+                    }
+                }
+    return n;
+}
+
+// Re-lay a parsed layout for sparse residency: [root][table][payload][mv]
+// [tiles][slots][status].
+static lf_status lf_layout_sparse(const uint8_t* s, LfLayout* L)
+{
+    const LfGeom& g = L->g;
+    L->n_tiles = lf_ref_slots(s, *L, nullptr);
+    if (L->n_tiles > 0x7FFFFFFF) return lf_fail(LF_EFORMAT, "too many reference blocks");
+    L->sparse = 1;
+    L->a_slots = align256(L->a_refs + L->n_tiles * (int64_t)g.bs * g.bs * 2);
+    L->a_desc = L->a_status = align256(L->a_slots + 3 * (int64_t)g.n_refs * g.nblk * 4);
+    L->arena = L->a_status + 256;
+    return LF_OK;
+}
+
+static lf_status lf_parse_ex(const uint8_t* s, size_t n, int32_t flags, LfLayout* L)
+{
+    if (flags & ~LF_LOAD_SPARSE_REFS) return lf_fail(LF_EINVAL, "unknown load flags 0x%x", flags);
+    lf_status st = lf_parse(s, n, L);
+    if (st != LF_OK || !(flags & LF_LOAD_SPARSE_REFS)) return st;
+    return lf_layout_sparse(s, L);
+}
+
+extern "C" lf_status lf_query_arena_ex(const void* host_stream, size_t nbytes, int32_t flags, int64_t* arena_bytes)
 {
     if (!arena_bytes) return lf_fail(LF_EINVAL, "null output");
     LfLayout L;
-    lf_status st = lf_parse((const uint8_t*)host_stream, nbytes, &L);
+    lf_status st = lf_parse_ex((const uint8_t*)host_stream, nbytes, flags, &L);
     if (st != LF_OK) return st;
     *arena_bytes = L.arena;
     return LF_OK;
+}
+
+extern "C" lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_bytes)
+{
+    return lf_query_arena_ex(host_stream, nbytes, 0, arena_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,6 +277,32 @@ __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int*
     if (bad) atomicOr(status, 1);
 }
 
+// Sparse residency: the tile of every significant reference block.
+__global__ void k_load_tiles(LfGeom g, LfPtrs p, int16_t* __restrict__ tiles, int* __restrict__ status)
+{
+    bool bad = false;
+    const int n = g.bs * g.bs;
+    const int64_t total = 3 * (int64_t)g.n_refs * g.nblk * n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rb = t / n;  // (reference plane, block)
+        const int tile = p.slots[rb];
+        if (tile < 0) continue;
+        const int i = (int)(t - rb * n);
+        const int blk = (int)(rb % g.nblk);
+        const int64_t rp = rb / g.nblk;
+        const int c = (int)(rp / g.n_refs), r = (int)(rp % g.n_refs);
+        int l = 0;
+        while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
+        const int local = r - g.ref_base[l];
+        const int Bp = local / g.na_l[l + 1], Ap = local % g.na_l[l + 1];
+        const int node = g.node_base[l] + (2 * Bp) * g.na_l[l] + 2 * Ap;
+        const int v = lf_residual(g, p, c, l, node, blk, i);
+        bad |= v < -LF_REF_LIMIT || v > LF_REF_LIMIT;
+        tiles[(int64_t)tile * n + i] = (int16_t)v;
+    }
+    if (bad) atomicOr(status, 1);
+}
+
 // Block descriptors of every (channel, node, block), BFS node order.
 __global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc)
 {
@@ -240,13 +318,13 @@ __global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc)
     }
 }
 
-extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
-                                        void* stream, lf_handle** out)
+extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbytes, int32_t flags, void* d_arena,
+                                           int64_t arena_bytes, void* stream, lf_handle** out)
 {
     if (!out || !d_arena) return lf_fail(LF_EINVAL, "null argument");
     *out = nullptr;
     LfLayout L;
-    lf_status st = lf_parse((const uint8_t*)host_stream, nbytes, &L);
+    lf_status st = lf_parse_ex((const uint8_t*)host_stream, nbytes, flags, &L);
     if (st != LF_OK) return st;
     if (arena_bytes < L.arena)
         return lf_fail(LF_ENOMEM, "arena of %lld bytes, %lld needed", (long long)arena_bytes, (long long)L.arena);
@@ -273,7 +351,8 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
     h->p.payload = (const uint32_t*)(A + L.a_payload);
     h->p.mv = (const uint32_t*)(A + L.a_mv);
     h->p.refs = (const int16_t*)(A + L.a_refs);
-    h->p.desc = (const uint4*)(A + L.a_desc);
+    h->p.desc = L.sparse ? nullptr : (const uint4*)(A + L.a_desc);
+    h->p.slots = L.sparse ? (const int32_t*)(A + L.a_slots) : nullptr;
     const int64_t total = 3 * (int64_t)L.g.n_refs * L.g.w * L.g.h;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -282,7 +361,22 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
         delete h;
         return lf_fail(LF_EDEVICE, "status clear failed");
     }
-    if (total > 0) {
+    std::vector<int32_t> slots;
+    if (L.sparse && total > 0) {
+        slots.resize((size_t)(3 * (int64_t)L.g.n_refs * L.g.nblk));
+        lf_ref_slots(S, L, slots.data());
+        if (hipMemcpyAsync(A + L.a_slots, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
+            delete h;
+            return lf_fail(LF_EDEVICE, "upload failed");
+        }
+        hipLaunchKernelGGL(k_load_tiles, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs,
+                           status);
+        st = lf_check_launch("load_tiles");
+        if (st != LF_OK) {
+            delete h;
+            return st;
+        }
+    } else if (total > 0) {
         hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs,
                            status);
         st = lf_check_launch("load_refs");
@@ -291,7 +385,7 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
             return st;
         }
     }
-    {
+    if (!L.sparse) {
         const int64_t nd = 3 * (int64_t)L.g.n_nodes * L.g.nblk;
         const int64_t dblocks = std::min<int64_t>((nd + 255) / 256, 65536);
         hipLaunchKernelGGL(k_load_desc, dim3((unsigned)dblocks), dim3(256), 0, s, L.g, h->p, (uint4*)(A + L.a_desc));
@@ -314,6 +408,12 @@ extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, 
     }
     *out = h;
     return LF_OK;
+}
+
+extern "C" lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
+                                        void* stream, lf_handle** out)
+{
+    return lf_load_compressed_ex(host_stream, nbytes, 0, d_arena, arena_bytes, stream, out);
 }
 
 extern "C" lf_status lf_free(lf_handle* h)
@@ -340,6 +440,8 @@ extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
     o->arena_bytes = h->L.arena;
     o->stream_bytes = h->L.stream_bytes;
     o->payload_bytes = (int64_t)h->L.payload_bytes;
+    o->sparse_refs = h->L.sparse;
+    o->ref_bytes = h->L.sparse ? h->L.a_status - h->L.a_refs : h->L.a_desc - h->L.a_refs;
     return LF_OK;
 }
 
@@ -347,6 +449,7 @@ extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
 // random-access sample decoding
 // ---------------------------------------------------------------------------
 
+template <bool SPARSE>
 __global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ coords, int64_t n,
                                 uint8_t* __restrict__ rgb)
 {
@@ -355,9 +458,9 @@ __global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ 
     int4 q = reinterpret_cast<const int4*>(coords)[k];
     int b = lf_clampi(q.x, 0, g.nb - 1), a = lf_clampi(q.y, 0, g.na - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
-    int Y = lf_decode_channel(g, p, 0, b, a, y, x);
-    int Co = lf_decode_channel(g, p, 1, b, a, y, x);
-    int Cg = lf_decode_channel(g, p, 2, b, a, y, x);
+    int Y = lf_decode_channel<SPARSE>(g, p, 0, b, a, y, x);
+    int Co = lf_decode_channel<SPARSE>(g, p, 1, b, a, y, x);
+    int Cg = lf_decode_channel<SPARSE>(g, p, 2, b, a, y, x);
     int r, gg, bl;
     lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
     rgb[3 * k] = (uint8_t)r;
@@ -374,12 +477,13 @@ extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coord
     if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
     int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
-    hipLaunchKernelGGL(k_decode_pixels, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->L.g, h->p,
-                       d_coords, n, d_rgb);
+    hipLaunchKernelGGL(h->p.slots ? k_decode_pixels<true> : k_decode_pixels<false>, dim3((unsigned)blocks), dim3(256),
+                       0, (hipStream_t)stream, h->L.g, h->p, d_coords, n, d_rgb);
     return lf_check_launch("decode_pixels");
 }
 
 // Progressive decode: samples of the level-`lod` node images.
+template <bool SPARSE>
 __global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __restrict__ coords, int64_t n,
                                uint8_t* __restrict__ rgb)
 {
@@ -388,9 +492,9 @@ __global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __res
     int4 q = reinterpret_cast<const int4*>(coords)[k];
     int B = lf_clampi(q.x, 0, g.nb_l[lod] - 1), A = lf_clampi(q.y, 0, g.na_l[lod] - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
-    int Y = lf_decode_channel(g, p, 0, B << lod, A << lod, y, x, lod);
-    int Co = lf_decode_channel(g, p, 1, B << lod, A << lod, y, x, lod);
-    int Cg = lf_decode_channel(g, p, 2, B << lod, A << lod, y, x, lod);
+    int Y = lf_decode_channel<SPARSE>(g, p, 0, B << lod, A << lod, y, x, lod);
+    int Co = lf_decode_channel<SPARSE>(g, p, 1, B << lod, A << lod, y, x, lod);
+    int Cg = lf_decode_channel<SPARSE>(g, p, 2, B << lod, A << lod, y, x, lod);
     int r, gg, bl;
     lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
     rgb[3 * k] = (uint8_t)r;
@@ -407,8 +511,8 @@ extern "C" lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, con
     if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
-    hipLaunchKernelGGL(k_decode_nodes, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->L.g, h->p,
-                       (int)level, d_coords, n, d_rgb);
+    hipLaunchKernelGGL(h->p.slots ? k_decode_nodes<true> : k_decode_nodes<false>, dim3((unsigned)blocks), dim3(256), 0,
+                       (hipStream_t)stream, h->L.g, h->p, (int)level, d_coords, n, d_rgb);
     return lf_check_launch("decode_pixels_lod");
 }
 

@@ -35,8 +35,11 @@ struct LfPtrs {
     const uint2* table;       // [3][n_nodes][nblk]: x = payload word, y = min | mode << 16
     const uint32_t* payload;  // block payload words (+ slack)
     const uint32_t* mv;       // motion-vector section words (+ slack)
-    const int16_t* refs;      // [3][n_refs][h][w] decoded reference SRVs
-    const uint4* desc;        // [3][n_nodes][nblk] block descriptors (lf_make_desc), built at load
+    const int16_t* refs;      // dense: [3][n_refs][h][w] decoded reference SRVs;
+                              // sparse: [n_tiles][bs][bs] tiles of the significant reference blocks
+    const uint4* desc;        // [3][n_nodes][nblk] block descriptors (lf_make_desc), built at load (dense only)
+    const int32_t* slots;     // sparse: [3][n_refs][nblk] tile of each reference block, -1 = zero block;
+                              // null for dense planes
 };
 
 // Ordinal of predictive node (B, A) among the predictive nodes of its level,
@@ -107,33 +110,46 @@ __device__ __forceinline__ void lf_motion(const LfGeom& g, const LfPtrs& p, int 
 
 __device__ __forceinline__ int lf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// Quarter-pel bilinear prediction from an int16 reference plane, taps
-// clamped to the plane, rounded as (sum w * tap + 8) >> 4 with weights
-// (4 - fx)(4 - fy), fx(4 - fy), (4 - fx)fy, fx fy.
-__device__ __forceinline__ int lf_qpel(const int16_t* __restrict__ plane, int w, int h, int y, int x, int mx,
-                                       int my)
+// Pixel (y, x) of reference plane rp (index into [3][n_refs]).  Dense
+// residency reads the plane; sparse residency (the paper's reduced-memory
+// reference storage, Decompression Analysis) reads the tile of the pixel's
+// block, a zero block having no tile.
+template <bool SPARSE>
+__device__ __forceinline__ int lf_ref_tap(const LfGeom& g, const LfPtrs& p, uint32_t rp, int y, int x)
+{
+    if (!SPARSE) return p.refs[(size_t)rp * (size_t)(g.w * g.h) + y * g.w + x];
+    const int t = p.slots[(size_t)rp * g.nblk + (y >> g.bsl) * g.nbx + (x >> g.bsl)];
+    return t < 0 ? 0 : p.refs[((size_t)t << (2 * g.bsl)) + (((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1)))];
+}
+
+// Quarter-pel bilinear prediction from reference plane rp, taps clamped to
+// the plane, rounded as (sum w * tap + 8) >> 4 with weights (4 - fx)(4 - fy),
+// fx(4 - fy), (4 - fx)fy, fx fy.
+template <bool SPARSE>
+__device__ __forceinline__ int lf_qpel(const LfGeom& g, const LfPtrs& p, uint32_t rp, int y, int x, int mx, int my)
 {
     int X = 4 * x + mx, Y = 4 * y + my;
     int x0 = X >> 2, y0 = Y >> 2, fx = X & 3, fy = Y & 3;
-    int xa = lf_clampi(x0, 0, w - 1), xb = lf_clampi(x0 + 1, 0, w - 1);
-    int ya = lf_clampi(y0, 0, h - 1), yb = lf_clampi(y0 + 1, 0, h - 1);
-    int acc = (4 - fx) * (4 - fy) * plane[ya * w + xa] + fx * (4 - fy) * plane[ya * w + xb] +
-              (4 - fx) * fy * plane[yb * w + xa] + fx * fy * plane[yb * w + xb];
+    int xa = lf_clampi(x0, 0, g.w - 1), xb = lf_clampi(x0 + 1, 0, g.w - 1);
+    int ya = lf_clampi(y0, 0, g.h - 1), yb = lf_clampi(y0 + 1, 0, g.h - 1);
+    int acc = (4 - fx) * (4 - fy) * lf_ref_tap<SPARSE>(g, p, rp, ya, xa) +
+              fx * (4 - fy) * lf_ref_tap<SPARSE>(g, p, rp, ya, xb) +
+              (4 - fx) * fy * lf_ref_tap<SPARSE>(g, p, rp, yb, xa) + fx * fy * lf_ref_tap<SPARSE>(g, p, rp, yb, xb);
     return (acc + 8) >> 4;
 }
 
-__device__ __forceinline__ const int16_t* lf_ref_plane(const LfGeom& g, const LfPtrs& p, int c, int l, int Bp,
-                                                       int Ap)
+__device__ __forceinline__ uint32_t lf_ref_index(const LfGeom& g, int c, int l, int Bp, int Ap)
 {
-    return p.refs + ((size_t)c * g.n_refs + g.ref_base[l] + Bp * g.na_l[l + 1] + Ap) * (size_t)(g.w * g.h);
+    return (uint32_t)(c * g.n_refs + g.ref_base[l] + Bp * g.na_l[l + 1] + Ap);
 }
 
-// One YCoCg channel of sample (b, a, y, x): root RKV plus the SRV of every
-// level on the path (Decoding Procedure).  Reference SRVs come from the
-// resident planes; predictive SRVs are residual + phase * prediction.
-// One channel of one sample: the root RKV plus the SRVs of levels lod .. H-1
-// on the path from leaf view (b, a) up (lod = 0: the leaf view itself; lod =
-// l: the reconstructed RKV of the level-l ancestor, the progressive decode).
+// One YCoCg channel of sample (b, a, y, x) (Decoding Procedure): the root
+// RKV plus the SRVs of levels lod .. H-1 on the path from leaf view (b, a) up
+// (lod = 0: the leaf view itself; lod = l: the reconstructed RKV of the
+// level-l ancestor, the progressive decode).  Reference SRVs come from the
+// resident reference storage; predictive SRVs are residual + phase *
+// prediction.
+template <bool SPARSE = false>
 __device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c, int b, int a, int y, int x,
                                         int lod = 0)
 {
@@ -143,16 +159,16 @@ __device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c,
     const int i = ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1));
     for (int l = lod; l < g.H; l++) {
         int B = b >> l, A = a >> l;
-        const int16_t* ref = lf_ref_plane(g, p, c, l, B >> 1, A >> 1);
+        const uint32_t rp = lf_ref_index(g, c, l, B >> 1, A >> 1);
         if (!((A | B) & 1)) {
-            v += ref[y * g.w + x];
+            v += lf_ref_tap<SPARSE>(g, p, rp, y, x);
             continue;
         }
         int node = g.node_base[l] + B * g.na_l[l] + A;
         int r = lf_residual(g, p, c, l, node, blk, i);
         int mx, my, sg;
         lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
-        if (sg) r += sg * lf_qpel(ref, g.w, g.h, y, x, mx, my);
+        if (sg) r += sg * lf_qpel<SPARSE>(g, p, rp, y, x, mx, my);
         v += r;
     }
     return v;

@@ -14,6 +14,10 @@ struct LfLayout {
     int64_t stream_bytes;
     // arena offsets
     int64_t a_root, a_table, a_payload, a_mv, a_refs, a_desc, a_status, arena;
+    // sparse reference residency (LF_LOAD_SPARSE_REFS): a_refs holds n_tiles
+    // block tiles, a_slots the tile of every reference block; no descriptors
+    int32_t sparse;
+    int64_t n_tiles, a_slots;
 };
 
 struct lf_handle {

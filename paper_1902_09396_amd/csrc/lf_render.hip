@@ -19,6 +19,7 @@
 
 #include "lf_render_tile.h"
 
+template <bool SPARSE>
 __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, float* __restrict__ out, int lod)
 {
@@ -29,7 +30,7 @@ __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const f
     const int64_t px = r - (int64_t)v * npix;
     const int j = (int)(px / wo), i = (int)(px % wo);
     float o[3];
-    lf_render_one(g, p, cams + 18 * v, i, j, o, lod);
+    lf_render_one<SPARSE>(g, p, cams + 18 * v, i, j, o, lod);
 #pragma unroll
     for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
 }
@@ -40,8 +41,8 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
     int64_t total = (int64_t)nv * wo * ho;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many rays");
-    hipLaunchKernelGGL(k_render_rays, dim3((unsigned)blocks), dim3(256), 0, s, h->L.g, h->p, d_cams, nv, wo, ho,
-                       d_out, lod);
+    hipLaunchKernelGGL(h->p.slots ? k_render_rays<true> : k_render_rays<false>, dim3((unsigned)blocks), dim3(256), 0,
+                       s, h->L.g, h->p, d_cams, nv, wo, ho, d_out, lod);
     return lf_check_launch("render_rays");
 }
 
@@ -190,8 +191,10 @@ extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, in
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
-    // the tile kernel decodes quads of 4 pixels inside one block
-    if (h->L.g.bs < 4) return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
+    // the tile kernel decodes quads of 4 pixels inside one block and reads
+    // dense reference planes
+    if (h->L.g.bs < 4 || h->p.slots)
+        return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
     return lf_launch_render_batch(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
 }
 

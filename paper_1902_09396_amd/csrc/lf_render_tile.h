@@ -66,6 +66,7 @@ __device__ __forceinline__ float lf_blend16(const float (&sm)[16], const BlendW&
 // per-ray reference path
 // ---------------------------------------------------------------------------
 
+template <bool SPARSE = false>
 __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cam, int i, int j,
                                      float out[3], int lod = 0)
 {
@@ -75,9 +76,9 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
     for (int k = 0; k < 16; k++) {
         const int b = (k & 8) ? r.b1 : r.b0, a = (k & 4) ? r.a1 : r.a0;
         const int y = (k & 2) ? r.y1 : r.y0, x = (k & 1) ? r.x1 : r.x0;
-        int Y = lf_decode_channel(g, p, 0, b, a, y, x, lod);
-        int Co = lf_decode_channel(g, p, 1, b, a, y, x, lod);
-        int Cg = lf_decode_channel(g, p, 2, b, a, y, x, lod);
+        int Y = lf_decode_channel<SPARSE>(g, p, 0, b, a, y, x, lod);
+        int Co = lf_decode_channel<SPARSE>(g, p, 1, b, a, y, x, lod);
+        int Cg = lf_decode_channel<SPARSE>(g, p, 2, b, a, y, x, lod);
         int R, G, B;
         lf_ycocg_to_rgb(Y, Co, Cg, R, G, B);
         px[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);

@@ -17,6 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libhmlfc.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EFORMAT, LF_EDEVICE = 0, -1, -2, -3, -4
+LF_LOAD_SPARSE_REFS = 1
 _NAMES = {LF_EINVAL: "LF_EINVAL", LF_ENOMEM: "LF_ENOMEM", LF_EFORMAT: "LF_EFORMAT", LF_EDEVICE: "LF_EDEVICE"}
 
 
@@ -30,7 +31,8 @@ class LfInfo(C.Structure):
     _fields_ = [("na", C.c_int32), ("nb", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("levels", C.c_int32), ("block", C.c_int32), ("root_na", C.c_int32), ("root_nb", C.c_int32),
                 ("n_nodes", C.c_int64), ("n_pred_records", C.c_int64), ("n_refs", C.c_int64),
-                ("arena_bytes", C.c_int64), ("stream_bytes", C.c_int64), ("payload_bytes", C.c_int64)]
+                ("arena_bytes", C.c_int64), ("stream_bytes", C.c_int64), ("payload_bytes", C.c_int64),
+                ("ref_bytes", C.c_int64), ("sparse_refs", C.c_int32)]
 
 
 _lib = None
@@ -40,6 +42,8 @@ _P, _I32, _I64, _SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
 SIGNATURES = {
     "lf_query_arena": (C.c_int, [_P, _SZ, _P]),
     "lf_load_compressed": (C.c_int, [_P, _SZ, _P, _I64, _P, _P]),
+    "lf_query_arena_ex": (C.c_int, [_P, _SZ, _I32, _P]),
+    "lf_load_compressed_ex": (C.c_int, [_P, _SZ, _I32, _P, _I64, _P, _P]),
     "lf_free": (C.c_int, [_P]),
     "lf_get_info": (C.c_int, [_P, _P]),
     "lf_decode_pixels": (C.c_int, [_P, _P, _I64, _P, _P]),
@@ -108,20 +112,23 @@ def require_gpu():
 class LightField:
     """A compressed light field resident in device memory."""
 
-    def __init__(self, stream, device=None):
+    def __init__(self, stream, device=None, sparse_refs: bool = False):
+        """sparse_refs=True keeps only the significant reference blocks resident
+        (same results; rendered one thread per ray)."""
         require_gpu()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         host = np.ascontiguousarray(np.frombuffer(bytes(stream), np.uint8) if isinstance(stream, (bytes, bytearray))
                                     else np.asarray(stream, dtype=np.uint8))
         self.stream_bytes = host.size
+        flags = LF_LOAD_SPARSE_REFS if sparse_refs else 0
         need = C.c_int64()
-        check(lib().lf_query_arena(host.ctypes.data_as(C.c_void_p), host.size, C.byref(need)))
+        check(lib().lf_query_arena_ex(host.ctypes.data_as(C.c_void_p), host.size, flags, C.byref(need)))
         with torch.cuda.device(self.device):
             # torch's caching allocator returns 512-byte aligned blocks
             self.arena = torch.empty(int(need.value), dtype=torch.uint8, device=self.device)
             h = C.c_void_p()
-            check(lib().lf_load_compressed(host.ctypes.data_as(C.c_void_p), host.size, _ptr(self.arena),
-                                           int(need.value), _stream(), C.byref(h)))
+            check(lib().lf_load_compressed_ex(host.ctypes.data_as(C.c_void_p), host.size, flags, _ptr(self.arena),
+                                              int(need.value), _stream(), C.byref(h)))
         self._h = h
         info = LfInfo()
         check(lib().lf_get_info(self._h, C.byref(info)))
@@ -304,8 +311,9 @@ def _encode_params(enc: dict):
     return p
 
 
-def query_arena(stream) -> int:
+def query_arena(stream, sparse_refs: bool = False) -> int:
     host = np.ascontiguousarray(np.asarray(stream, dtype=np.uint8))
     need = C.c_int64()
-    check(lib().lf_query_arena(host.ctypes.data_as(C.c_void_p), host.size, C.byref(need)))
+    check(lib().lf_query_arena_ex(host.ctypes.data_as(C.c_void_p), host.size,
+                                  LF_LOAD_SPARSE_REFS if sparse_refs else 0, C.byref(need)))
     return int(need.value)

@@ -56,3 +56,48 @@ def test_query_arena_and_format_errors(tiny_stream):
             break
     with pytest.raises(lf.LFError):
         lf.query_arena(bad)
+
+
+def _sparse_arena_expected(stream):
+    """Arena of a sparse-residency load, derived from the stream header and
+    table: [root][table][payload][mv][tiles][slots][status], 256-aligned."""
+    s = np.asarray(stream, dtype=np.uint8)
+    rd = lambda o, t: int(np.frombuffer(s[o:o + np.dtype(t).itemsize].tobytes(), t)[0])  # noqa: E731
+    na, nb, w, h, H, bs = (rd(16 + 4 * k, np.int32) for k in range(6))
+    al = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    root, table, payload, mv = (rd(120 + 16 * k, np.uint64) for k in range(4))
+    na_l, nb_l = [na], [nb]
+    for _ in range(H):
+        na_l.append((na_l[-1] + 1) // 2)
+        nb_l.append((nb_l[-1] + 1) // 2)
+    node_base, n = {}, 0
+    for lev in range(H - 1, -1, -1):
+        node_base[lev] = n
+        n += na_l[lev] * nb_l[lev]
+    nblk = (w // bs) * (h // bs)
+    toff = rd(128, np.uint64)
+    modes = s[toff:toff + table].reshape(3, n, nblk, 8)[..., 6]
+    tiles = 0
+    n_refs = 0
+    for lev in range(H):
+        refs = [node_base[lev] + 2 * B * na_l[lev] + 2 * A for B in range(nb_l[lev + 1]) for A in range(na_l[lev + 1])]
+        n_refs += len(refs)
+        tiles += int((modes[:, refs, :] != 0xFF).sum())
+    a = al(al(al(al(root) + table) + payload) + mv)
+    a = al(al(a + tiles * bs * bs * 2) + 3 * n_refs * nblk * 4)
+    return a + 256, tiles
+
+
+def test_sparse_residency_arena(tiny_lf, tiny_stream):
+    from conftest import stream_for
+    from paper_1902_09396_amd import lf
+
+    for s in (tiny_stream, stream_for("tiny", tiny_lf, step=8, t_ref=200, t_pred=400)):
+        expect, tiles = _sparse_arena_expected(s)
+        assert lf.query_arena(s, sparse_refs=True) == expect
+        assert tiles > 0
+    dense, sparse = lf.query_arena(s), lf.query_arena(s, sparse_refs=True)
+    assert sparse < dense  # thresholds zero many reference blocks; no descriptors either
+    with pytest.raises(lf.LFError) as e:  # unknown load flags
+        lf.check(lf.lib().lf_query_arena_ex(s.ctypes.data_as(C.c_void_p), s.size, 6, C.byref(C.c_int64())))
+    assert e.value.status == lf.LF_EINVAL

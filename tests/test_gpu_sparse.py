@@ -1,0 +1,91 @@
+"""Sparse reference residency (only significant reference blocks resident,
+as tiles): every decode and render equals the dense handle's bit for bit,
+and the oracle's; the relaxed render is unaffected; serving rejects it."""
+
+import numpy as np
+import pytest
+
+import lfscene
+import oracle
+from conftest import stream_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _coords(nb, na, h, w, n, seed):
+    rng = np.random.default_rng(seed)
+    c = np.stack([rng.integers(0, nb, n), rng.integers(0, na, n), rng.integers(0, h, n), rng.integers(0, w, n)], 1)
+    return c.astype(np.int32)
+
+
+@pytest.mark.parametrize("over", [{}, {"step": 8, "t_ref": 200, "t_pred": 400}, {"subpel": False, "t_ref": 300},
+                                  {"no_mc": True, "t_ref": 300}])
+def test_sparse_equals_dense_tiny(torch_mod, tiny_lf, tiny_cams, tiny_cams_ez, over):
+    from paper_1902_09396_amd import lf
+
+    torch = torch_mod
+    s = stream_for("tiny", tiny_lf, **over)
+    dense, sparse = lf.LightField(s), lf.LightField(s, sparse_refs=True)
+    assert sparse.info["sparse_refs"] == 1 and dense.info["sparse_refs"] == 0
+    # no descriptors in a sparse arena; with thresholds, zero reference blocks take no tiles
+    assert sparse.info["arena_bytes"] < dense.info["arena_bytes"]
+    if over.get("t_ref", 0) > 0:
+        assert sparse.info["ref_bytes"] < dense.info["ref_bytes"]
+    o = oracle.OracleLF(s)
+    b, a, y, x = np.meshgrid(np.arange(8), np.arange(8), np.arange(64), np.arange(64), indexing="ij")
+    coords = torch.from_numpy(np.stack([b.ravel(), a.ravel(), y.ravel(), x.ravel()], 1).astype(np.int32)).cuda()
+    got = sparse.decode_pixels(coords)
+    assert torch.equal(got, dense.decode_pixels(coords))
+    assert np.array_equal(got.cpu().numpy().reshape(8, 8, 64, 64, 3), o.decode_full())
+    cams = torch.from_numpy(np.concatenate([tiny_cams, tiny_cams_ez]).astype(np.float32)).cuda()
+    r_s = sparse.render_views(cams, 48, 40)
+    assert torch.equal(r_s, dense.render_views(cams, 48, 40))
+    assert torch.equal(sparse.render_views(cams, 48, 40, per_ray=True), r_s)
+    for level in (1, 2):
+        c = coords[: 4096].clone()
+        c[:, 0] //= 1 << level
+        c[:, 1] //= 1 << level
+        assert torch.equal(sparse.decode_nodes(level, c), dense.decode_nodes(level, c))
+        assert torch.equal(sparse.render_views_lod(level, cams, 32, 24), dense.render_views_lod(level, cams, 32, 24))
+    res, sh = sparse.export_params()
+    res_d, sh_d = dense.export_params()
+    assert torch.equal(res, res_d) and torch.equal(sh, sh_d)
+    assert torch.equal(sparse.render_relaxed(res, sh, cams, 32, 24), dense.render_relaxed(res_d, sh_d, cams, 32, 24))
+
+
+def test_sparse_mid_thresholded(torch_mod, mid_lf):
+    """17x17x128x128 with block thresholds: most reference blocks are zero."""
+    from paper_1902_09396_amd import lf
+
+    torch = torch_mod
+    enc = lfscene.get_config("path512")["enc"]
+    H = enc["levels"]
+    enc.update(t_ref=[1200] * H, t_pred=[2400] * H)  # about half the reference blocks become zero
+    s = lf.encode(mid_lf, enc)
+    dense, sparse = lf.LightField(s), lf.LightField(s, sparse_refs=True)
+    assert sparse.info["ref_bytes"] < 0.8 * dense.info["ref_bytes"]
+    coords = torch.from_numpy(_coords(17, 17, 128, 128, 500000, 3)).cuda()
+    assert torch.equal(sparse.decode_pixels(coords), dense.decode_pixels(coords))
+    cams = torch.from_numpy(lfscene.random_pinhole_cameras(3, 17, 17, 128, 128, 96, 64, seed=9,
+                                                           rho=1.0 / 16.0).astype(np.float32)).cuda()
+    assert torch.equal(sparse.render_views(cams, 96, 64), dense.render_views(cams, 96, 64))
+    o = oracle.OracleLF(s)
+    assert np.abs(sparse.render_views(cams, 96, 64).cpu().numpy() - o.render(cams.cpu().numpy(), 96, 64)).max() <= 1e-5
+
+
+def test_serving_rejects_sparse(torch_mod, tiny_stream):
+    from paper_1902_09396_amd import lf
+    from paper_1902_09396_amd.serve import Server
+
+    sparse = lf.LightField(tiny_stream, sparse_refs=True)
+    with pytest.raises(lf.LFError) as e:
+        Server([sparse], pool_bytes=1 << 20)
+    assert e.value.status == lf.LF_EINVAL
