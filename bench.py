@@ -498,6 +498,7 @@ def rd_bench(args):
     for t in (0, 25, 75, 150, 300, 600):
         thr[str(t)] = {"hmlfc": point("threshold %d" % t, enc(4, 16, t)),
                        "no_mc": point("threshold %d, no MC" % t, enc(4, 16, t, no_mc=True))}
+    paper = residency_point(cfg, light, enc(4, 16, 75) | {"subpel": False}, args)
     print(json.dumps({
         "metric": "rate-distortion sweeps: bits per light-field pixel and PSNR",
         "n_gpus": 1, "data": "synthetic",
@@ -505,7 +506,45 @@ def rd_bench(args):
         "block_size_at_threshold75_window16": table2,
         "window_at_block4_threshold75": fig5,
         "threshold_at_block4_window16": thr,
+        "residency_block4_window16_threshold75_integer_pel": paper,
     }), flush=True)
+
+
+def residency_point(cfg, light, enc, args):
+    """Dense against sparse reference residency for one stream: resident
+    reference bytes, arena bytes, and the 120-frame 512x512 orbit rendered
+    with each (tile kernel on the dense handle, one thread per ray on the
+    sparse one)."""
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+
+    stream = lf.encode(light, enc, threads=min(16, os.cpu_count() or 1), device=True)
+    cams_np = lfscene.make_views(cfg)
+    cams = torch.from_numpy(cams_np).cuda()
+    wo, ho = cfg["views"]["wo"], cfg["views"]["ho"]
+    out = {}
+    for name, sparse in (("dense", False), ("sparse", True)):
+        field = lf.LightField(stream, device="cuda:0", sparse_refs=sparse)
+        img = torch.empty((cams.shape[0], 3, ho, wo), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            field.render_views(cams, wo, ho, out=img)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            field.render_views(cams, wo, ho, out=img)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        out[name] = {"ref_bytes": int(field.info["ref_bytes"]), "arena_bytes": int(field.info["arena_bytes"]),
+                     "ms_per_frame": round(ms / cams.shape[0], 5)}
+        log("%s residency: refs %.2f MB, arena %.2f MB, %.4f ms per 512x512 frame" %
+            (name, field.info["ref_bytes"] / 1e6, field.info["arena_bytes"] / 1e6, ms / cams.shape[0]))
+        field.close()
+    out["stream_bytes"] = int(stream.size)
+    return out
 
 
 def cpu_baseline(cfg, light, cams_np, wo, ho, n_rays):
