@@ -175,9 +175,11 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     }
     hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
                        d_cams, nv, wo, ho, tx, ty, chunk, fpg, d_out);
-    // marked pairs: at most 1024 workgroups, each checking a contiguous range
+    // marked pairs: workgroups each check a contiguous range.  With 16x16
+    // blocks few tiles exceed the staging budget and 1024 workgroups keep the
+    // pass short; smaller blocks mark many more tiles, which need the wider grid.
     const int64_t pairs = (int64_t)tx * ty * nv;
-    const int64_t fb_grid = std::min<int64_t>(pairs, 1024);
+    const int64_t fb_grid = std::min<int64_t>(pairs, h->L.g.bs >= 16 ? 1024 : 8192);
     const int64_t per_wg = (pairs + fb_grid - 1) / fb_grid;
     if (per_wg > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
     hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)fb_grid), dim3(NT), 0, s, h->L.g, h->p, d_cams, nv, wo, ho, tx,
@@ -191,9 +193,10 @@ extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, in
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
-    // the tile kernel decodes quads of 4 pixels inside one block and reads
-    // dense reference planes
-    if (h->L.g.bs < 4 || h->p.slots)
+    // the tile kernel reads dense reference planes; with blocks below 8x8 a
+    // tile's footprint holds more block descriptors than its LDS budget, so
+    // nearly every tile would fall back to the per-ray pass anyway
+    if (h->L.g.bs < 8 || h->p.slots)
         return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
     return lf_launch_render_batch(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
 }
