@@ -66,21 +66,114 @@ __device__ __forceinline__ float lf_blend16(const float (&sm)[16], const BlendW&
 // per-ray reference path
 // ---------------------------------------------------------------------------
 
+// SRV values of node (B, A) of level l, channel c, at the pixels (ys[k >> 1],
+// xs[k & 1]), k < 4: a reference node reads its resident SRV; a predictive
+// node adds its dequantised residual and its phase-signed prediction.  The
+// block descriptor (table entry and motion record) is read once when the four
+// pixels share a block.
+template <bool SPARSE>
+__device__ inline void lf_srv_quad(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, const int ys[2],
+                                   const int xs[2], int v[4])
+{
+    const uint32_t rp = lf_ref_index(g, c, l, B >> 1, A >> 1);
+    if (!((A | B) & 1)) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) v[k] = lf_ref_tap<SPARSE>(g, p, rp, ys[k >> 1], xs[k & 1]);
+        return;
+    }
+    const int node = g.node_base[l] + B * g.na_l[l] + A;
+    const uint32_t rec = (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk);
+    const size_t tab = ((size_t)c * g.n_nodes + node) * g.nblk;
+    int blk0 = -1, mode = 0, mn = 0, mx = 0, my = 0, sg = 0;
+    uint32_t word = 0;
+#pragma unroll 1  // unrolled, the four inlined walks of a ray exhaust the registers
+    for (int k = 0; k < 4; k++) {
+        const int y = ys[k >> 1], x = xs[k & 1];
+        const int blk = (y >> g.bsl) * g.nbx + (x >> g.bsl);
+        if (blk != blk0) {
+            const uint2 e = p.table[tab + blk];
+            mode = (int)((e.y >> 16) & 0xFFu);
+            mn = (int)(int16_t)(e.y & 0xFFFFu);
+            word = e.x;
+            lf_motion(g, p, c, l, rec + (uint32_t)blk, mx, my, sg);
+            blk0 = blk;
+        }
+        const int i = ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1));
+        int r = mode == LF_MODE_ZERO ? 0 : (mn + (int)lf_bise_get(p.payload + word, mode, (uint32_t)i)) * g.step[l];
+        if (sg) r += sg * lf_qpel<SPARSE>(g, p, rp, y, x, mx, my);
+        v[k] = r;
+    }
+}
+
+// One channel of the 16 samples of a ray (4 views x 4 pixels; sample k is
+// view k >> 2 = b0a0, b0a1, b1a0, b1a1 and pixel k & 3): root plus the SRVs
+// of levels lod .. H-1.  Per level, views whose tree nodes coincide share one
+// SRV evaluation (views (b, a) and (b', a') share the level-l node when
+// b >> l == b' >> l and a >> l == a' >> l): the same sums as 16 independent
+// tree walks.
+template <bool SPARSE>
+__device__ __forceinline__ void lf_ray_channel(const LfGeom& g, const LfPtrs& p, const Ray& r, int c, int lod,
+                                               int acc[16])
+{
+    const int ys[2] = {r.y0, r.y1}, xs[2] = {r.x0, r.x1};
+    const int H = g.H;
+    {
+        const bool eqA = (r.a0 >> H) == (r.a1 >> H), eqB = (r.b0 >> H) == (r.b1 >> H);
+        const size_t plane = (size_t)g.w * g.h;
+        int v[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int b = (q & 2) ? r.b1 : r.b0, a = (q & 1) ? r.a1 : r.a0;
+            const bool dup = (q == 1 && eqA) || (q == 2 && eqB) || (q == 3 && (eqA || eqB));
+            if (!dup) {
+                const int16_t* rt = p.root + ((size_t)(c * g.root_nb + (b >> H)) * g.root_na + (a >> H)) * plane;
+#pragma unroll
+                for (int k = 0; k < 4; k++) v[q][k] = rt[ys[k >> 1] * g.w + xs[k & 1]];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (eqA) v[1][k] = v[0][k];
+            if (eqB) v[2][k] = v[0][k];
+            if (eqB) v[3][k] = v[1][k];
+            else if (eqA) v[3][k] = v[2][k];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[4 * q + k] = v[q][k];
+        }
+    }
+    for (int l = lod; l < H; l++) {
+        const bool eqA = (r.a0 >> l) == (r.a1 >> l), eqB = (r.b0 >> l) == (r.b1 >> l);
+        int v[4][4];
+        lf_srv_quad<SPARSE>(g, p, c, l, r.b0 >> l, r.a0 >> l, ys, xs, v[0]);
+        if (!eqA) lf_srv_quad<SPARSE>(g, p, c, l, r.b0 >> l, r.a1 >> l, ys, xs, v[1]);
+        if (!eqB) lf_srv_quad<SPARSE>(g, p, c, l, r.b1 >> l, r.a0 >> l, ys, xs, v[2]);
+        if (!eqA && !eqB) lf_srv_quad<SPARSE>(g, p, c, l, r.b1 >> l, r.a1 >> l, ys, xs, v[3]);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (eqA) v[1][k] = v[0][k];
+            if (eqB) v[2][k] = v[0][k];
+            if (eqB) v[3][k] = v[1][k];
+            else if (eqA) v[3][k] = v[2][k];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[4 * q + k] += v[q][k];
+        }
+    }
+}
+
 template <bool SPARSE = false>
 __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cam, int i, int j,
                                      float out[3], int lod = 0)
 {
     const Ray r = lf_ray_setup(g, cam, i, j);
+    int Y[16], Co[16], Cg[16];
+    lf_ray_channel<SPARSE>(g, p, r, 0, lod, Y);
+    lf_ray_channel<SPARSE>(g, p, r, 1, lod, Co);
+    lf_ray_channel<SPARSE>(g, p, r, 2, lod, Cg);
     uint32_t px[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-        const int b = (k & 8) ? r.b1 : r.b0, a = (k & 4) ? r.a1 : r.a0;
-        const int y = (k & 2) ? r.y1 : r.y0, x = (k & 1) ? r.x1 : r.x0;
-        int Y = lf_decode_channel<SPARSE>(g, p, 0, b, a, y, x, lod);
-        int Co = lf_decode_channel<SPARSE>(g, p, 1, b, a, y, x, lod);
-        int Cg = lf_decode_channel<SPARSE>(g, p, 2, b, a, y, x, lod);
         int R, G, B;
-        lf_ycocg_to_rgb(Y, Co, Cg, R, G, B);
+        lf_ycocg_to_rgb(Y[k], Co[k], Cg[k], R, G, B);
         px[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
     }
     const BlendW w = lf_blend_weights(r);
