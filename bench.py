@@ -112,7 +112,7 @@ def main():
     light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
     log("scene %.1fs" % (time.time() - t0))
     t0 = time.time()
-    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1), device=True)
     log("encode %.1fs, %d bytes" % (time.time() - t0, stream.size))
     field = lf.LightField(stream, device="cuda:0")
     cams_np = lfscene.make_views(cfg)
@@ -224,7 +224,7 @@ def serve_bench(args):
         t0 = time.time()
         light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"],
                                 progress=lambda d, t, nm=name: log("field %s: %d of %d views generated" % (nm, d, t)))
-        stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+        stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1), device=True)
         del light
         fields.append(lf.LightField(stream, device="cuda:0"))
         shapes.append((L["na"], L["nb"], L["w"], L["h"]))
@@ -294,7 +294,7 @@ def grad_bench(args):
     L = cfg["lf"]
     t0 = time.time()
     light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
-    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1))
+    stream = lf.encode(light, cfg["enc"], threads=min(16, os.cpu_count() or 1), device=True)
     del light
     log("grad field: %d bytes, %.1fs" % (stream.size, time.time() - t0))
     field = lf.LightField(stream, device="cuda:0")
