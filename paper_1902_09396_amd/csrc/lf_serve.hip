@@ -49,21 +49,31 @@ struct ServeWork {  // one tile of one request
 // Work buffer of one launch (int32): [0] = item count n, [1 .. 1 + 3 max)
 // = items, [1 + 3 max] = count of tiles left for the per-ray pass, then
 // their item indices.
+// Work buffer of one launch (int32): [0] tile count n, [1 .. 3 max_tiles]
+// the tiles, then the fallback count, the tile-queue and fallback-queue
+// counters (all three uploaded as zero with the list), then the fallback list.
 __host__ __device__ inline size_t serve_fb_off(int max_tiles) { return 1 + 3 * (size_t)max_tiles; }
+__host__ __device__ inline size_t serve_fbl_off(int max_tiles) { return serve_fb_off(max_tiles) + 3; }
 
-__global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ geoms, const LfPtrs* __restrict__ ptrs,
+__global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict__ geoms, const LfPtrs* __restrict__ ptrs,
                                                     const ServeSlot* __restrict__ slots, int32_t* __restrict__ work,
                                                     int max_tiles, uint8_t* __restrict__ pool)
 {
     TILE_LDS_DECL
     __shared__ LfGeom sg;
     __shared__ LfPtrs sp;
-    __shared__ int cur_field;
+    __shared__ int cur_field, next;
     const int n = work[0];
     const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
+    int32_t* fb = work + serve_fb_off(max_tiles);
     if (threadIdx.x == 0) cur_field = -1;
-    __syncthreads();
-    for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    // tiles come from a queue (their costs differ widely): every workgroup
+    // takes the next one until the queue is past n
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(fb + 1, 1);
+        __syncthreads();
+        const int w = next;  // read before the barrier below; rewritten only after it
+        if (w >= n) break;
         const ServeWork it = items[w];
         const ServeSlot* sl = slots + it.slot;
         const int field = sl->field;
@@ -82,10 +92,7 @@ __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ g
         }
         const bool left = lf_tile_views<false>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
                                                reinterpret_cast<float*>(pool + sl->out_off), S);
-        if (left && threadIdx.x == 0) {
-            int32_t* fb = work + serve_fb_off(max_tiles);
-            fb[1 + atomicAdd(fb, 1)] = w;
-        }
+        if (left && threadIdx.x == 0) work[serve_fbl_off(max_tiles) + atomicAdd(fb, 1)] = w;
     }
 }
 
@@ -94,14 +101,20 @@ __global__ void __launch_bounds__(NT) k_serve_tiles(const LfGeom* __restrict__ g
 __global__ void __launch_bounds__(NT) k_serve_fallback(const LfGeom* __restrict__ geoms,
                                                        const LfPtrs* __restrict__ ptrs,
                                                        const ServeSlot* __restrict__ slots,
-                                                       const int32_t* __restrict__ work, int max_tiles,
+                                                       int32_t* __restrict__ work, int max_tiles,
                                                        uint8_t* __restrict__ pool)
 {
-    const int32_t* fb = work + serve_fb_off(max_tiles);
+    __shared__ int next;
+    int32_t* fb = work + serve_fb_off(max_tiles);
     const int nfb = fb[0];
     const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
-    for (int k = blockIdx.x; k < nfb; k += gridDim.x) {
-        const ServeWork it = items[fb[1 + k]];
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(fb + 2, 1);
+        __syncthreads();
+        const int k = next;
+        __syncthreads();  // every thread has read `next` before thread 0 rewrites it
+        if (k >= nfb) break;
+        const ServeWork it = items[work[serve_fbl_off(max_tiles) + k]];
         const ServeSlot* sl = slots + it.slot;
         const int i = it.tx * TW + (int)threadIdx.x % TW, j = it.ty * TH + (int)threadIdx.x / TW;
         if (i < sl->wo && j < sl->ho) {
@@ -169,8 +182,12 @@ struct PoolAlloc {
 struct StreamCtx {
     hipStream_t s = nullptr;
     hipEvent_t ev = nullptr;
-    int32_t* h_work = nullptr;  // pinned: count + items + zero fallback count (serve_fb_off)
+    int32_t* h_work = nullptr;  // pinned: count + items + zero fallback count and queue counters
     int32_t* d_work = nullptr;
+    // this stream's copy of the slot table, uploaded with every launch: a
+    // slot is reassigned only after every launch holding its tiles completed,
+    // so a launch never reads a slot that changes under it
+    ServeSlot* d_slots = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool busy = false;
@@ -184,8 +201,7 @@ struct lf_server {
     std::vector<LfPtrs> ptrs;
     LfGeom* d_geoms = nullptr;
     LfPtrs* d_ptrs = nullptr;
-    ServeSlot* d_slots = nullptr;
-    ServeSlot* h_slots = nullptr;  // pinned staging
+    ServeSlot* h_slots = nullptr;  // pinned slot table, copied by every launch
     uint8_t* pool = nullptr;
     int64_t pool_bytes = 0;
     lf_server_config cfg{};
@@ -211,13 +227,14 @@ struct lf_server {
 static lf_status capture_graph(lf_server* S, StreamCtx& sc)
 {
     // upload the whole list and the zero fallback count (no memset node in the graph)
-    const size_t wbytes = sizeof(int32_t) * (serve_fb_off(S->cfg.max_tiles) + 1);
+    const size_t wbytes = sizeof(int32_t) * serve_fbl_off(S->cfg.max_tiles);
     if (hipStreamBeginCapture(sc.s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return lf_fail(LF_EDEVICE, "stream capture failed");
     hipMemcpyAsync(sc.d_work, sc.h_work, wbytes, hipMemcpyHostToDevice, sc.s);
-    hipLaunchKernelGGL(k_serve_tiles, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs, S->d_slots,
+    hipMemcpyAsync(sc.d_slots, S->h_slots, sizeof(ServeSlot) * S->cfg.max_slots, hipMemcpyHostToDevice, sc.s);
+    hipLaunchKernelGGL(k_serve_tiles, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs, sc.d_slots,
                        sc.d_work, S->cfg.max_tiles, S->pool);
-    hipLaunchKernelGGL(k_serve_fallback, dim3(S->grid), dim3(NT), 0, sc.s, S->d_geoms, S->d_ptrs, S->d_slots,
+    hipLaunchKernelGGL(k_serve_fallback, dim3(S->grid), dim3(NT), 0, sc.s, S->d_geoms, S->d_ptrs, sc.d_slots,
                        sc.d_work, S->cfg.max_tiles, S->pool);
     if (hipStreamEndCapture(sc.s, &sc.graph) != hipSuccess) return lf_fail(LF_EDEVICE, "end capture failed");
     if (hipGraphInstantiate(&sc.exec, sc.graph, nullptr, nullptr, 0) != hipSuccess)
@@ -256,10 +273,11 @@ bool lf_server::launch(StreamCtx& sc)
     } else {
         const size_t fo = serve_fb_off(cfg.max_tiles);
         hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
-        hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
-        hipLaunchKernelGGL(k_serve_tiles, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs, d_slots,
+        hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, 3 * sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
+        hipMemcpyAsync(sc.d_slots, h_slots, sizeof(ServeSlot) * cfg.max_slots, hipMemcpyHostToDevice, sc.s);
+        hipLaunchKernelGGL(k_serve_tiles, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs, sc.d_slots,
                            sc.d_work, cfg.max_tiles, pool);
-        hipLaunchKernelGGL(k_serve_fallback, dim3(grid), dim3(NT), 0, sc.s, d_geoms, d_ptrs, d_slots, sc.d_work,
+        hipLaunchKernelGGL(k_serve_fallback, dim3(grid), dim3(NT), 0, sc.s, d_geoms, d_ptrs, sc.d_slots, sc.d_work,
                            cfg.max_tiles, pool);
     }
     hipEventRecord(sc.ev, sc.s);
@@ -316,9 +334,7 @@ void lf_server::run()
             hs.wo = r.wo;
             hs.ho = r.ho;
             hs.tiles_x = r.tiles_x;
-            hs.out_off = (uint64_t)off;
-            // ordered before every launch that uses the slot: all streams wait on it
-            hipMemcpy(d_slots + slot, &hs, sizeof(ServeSlot), hipMemcpyHostToDevice);
+            hs.out_off = (uint64_t)off;  // reaches the device with the next launch's slot table
             active.push_back(r.id);
             pending.pop_front();
             stats.admitted++;
@@ -332,7 +348,7 @@ void lf_server::run()
         if (!launched) {
             if (inflight) {
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
                 lk.lock();
             } else {
                 cv_work.wait_for(lk, std::chrono::milliseconds(2));
@@ -366,20 +382,21 @@ extern "C" lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields
     S->slot_owner.assign(cfg->max_slots, -1);
     bool ok = hipMalloc(&S->d_geoms, sizeof(LfGeom) * n_fields) == hipSuccess &&
               hipMalloc(&S->d_ptrs, sizeof(LfPtrs) * n_fields) == hipSuccess &&
-              hipMalloc(&S->d_slots, sizeof(ServeSlot) * cfg->max_slots) == hipSuccess &&
               hipHostMalloc(&S->h_slots, sizeof(ServeSlot) * cfg->max_slots, hipHostMallocDefault) == hipSuccess;
     if (ok) {
+        memset(S->h_slots, 0, sizeof(ServeSlot) * cfg->max_slots);
         hipMemcpy(S->d_geoms, S->geoms.data(), sizeof(LfGeom) * n_fields, hipMemcpyHostToDevice);
         hipMemcpy(S->d_ptrs, S->ptrs.data(), sizeof(LfPtrs) * n_fields, hipMemcpyHostToDevice);
     }
-    const size_t wbytes = sizeof(int32_t) * (serve_fb_off(cfg->max_tiles) + 1 + (size_t)cfg->max_tiles);
+    const size_t wbytes = sizeof(int32_t) * (serve_fbl_off(cfg->max_tiles) + (size_t)cfg->max_tiles);
     S->streams.resize(cfg->n_streams);
     for (StreamCtx& sc : S->streams) {
         if (!ok) break;
         ok = hipStreamCreateWithFlags(&sc.s, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&sc.ev, hipEventDisableTiming) == hipSuccess &&
              hipHostMalloc(&sc.h_work, wbytes, hipHostMallocDefault) == hipSuccess &&
-             hipMalloc(&sc.d_work, wbytes) == hipSuccess;
+             hipMalloc(&sc.d_work, wbytes) == hipSuccess &&
+             hipMalloc(&sc.d_slots, sizeof(ServeSlot) * cfg->max_slots) == hipSuccess;
         if (ok) {
             memset(sc.h_work, 0, wbytes);
             if (cfg->use_graphs) ok = capture_graph(S, sc) == LF_OK;
@@ -475,11 +492,11 @@ extern "C" lf_status lf_server_destroy(lf_server* S)
         if (sc.ev) hipEventDestroy(sc.ev);
         if (sc.h_work) hipHostFree(sc.h_work);
         if (sc.d_work) hipFree(sc.d_work);
+        if (sc.d_slots) hipFree(sc.d_slots);
         if (sc.s) hipStreamDestroy(sc.s);
     }
     if (S->d_geoms) hipFree(S->d_geoms);
     if (S->d_ptrs) hipFree(S->d_ptrs);
-    if (S->d_slots) hipFree(S->d_slots);
     if (S->h_slots) hipHostFree(S->h_slots);
     delete S;
     return LF_OK;
