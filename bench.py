@@ -82,8 +82,9 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (views shard across GPUs "
-              "with no per-frame exchange; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (views are independent, so "
+              "each GPU would render its own chunks of views with no per-frame exchange). Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
