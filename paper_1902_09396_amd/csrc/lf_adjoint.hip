@@ -25,7 +25,13 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "lf_internal.h"
+
+#define AD_MAX_PARTS 1024  // partial maxima of the shift reduction
+#define AD_TILE 16         // reference tile side of the pull kernel
+#define AD_CAND_MAX 1536   // block records a tile stages in LDS
 
 __device__ __forceinline__ float ad_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
@@ -201,7 +207,7 @@ struct BwdLayout {
     int64_t n_pairs, n_samples;
     int end_bit;
     size_t sort_bytes;
-    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_gs, o_max, total;
+    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_gs, o_max, o_parts, total;
 };
 
 static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
@@ -228,7 +234,8 @@ static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayou
     B->o_sort = B->o_vout + pb;
     B->o_gs = B->o_sort + al256((int64_t)sb);
     B->o_max = B->o_gs + al256(3 * B->n_samples * 4);
-    B->total = B->o_max + 256;
+    B->o_parts = B->o_max + 256;
+    B->total = B->o_parts + al256(AD_MAX_PARTS * 4);
     return LF_OK;
 }
 
@@ -324,11 +331,28 @@ __global__ void k_ad_tree(LfGeom g, int l, const float* __restrict__ gs, int64_t
     }
 }
 
+// largest |shift| component: AD_MAX_PARTS workgroups write partial maxima,
+// then one workgroup reduces them (a maximum is exact in any order)
 __global__ void k_ad_maxshift(const float2* __restrict__ shift, int64_t n, float* __restrict__ out)
 {
     __shared__ float red[256];
     float m = 0.0f;
-    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) m = fmaxf(m, fmaxf(fabsf(shift[t].x), fabsf(shift[t].y)));
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fmaxf(fabsf(shift[t].x), fabsf(shift[t].y)));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+__global__ void k_ad_maxparts(const float* __restrict__ parts, int n, float* __restrict__ out)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) m = fmaxf(m, parts[t]);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -356,62 +380,139 @@ __device__ __forceinline__ void ad_tap_range(int X, int n, int fd, int o, int k0
     }
 }
 
-// reference residual gradient: own node gradient plus the phase-signed
-// bilinear transpose of every predictive sibling's gradient (pull form)
-__global__ void k_ad_reference(LfGeom g, LfPtrs p, const float2* __restrict__ shift, const float* __restrict__ maxshift,
-                               float* __restrict__ gres)
+// Phase and split shift of one predictive block: integer part (clamped to
+// [-w-1, w] / [-h-1, h], which leaves every clamped tap where it was) and
+// fractional part.
+struct AdRec {
+    int sg, ix, iy;
+    float fx, fy;
+};
+
+__device__ __forceinline__ AdRec ad_fetch(const LfGeom& g, const LfPtrs& p, const float2* __restrict__ shift, int c,
+                                          int l, int B, int A, int blk)
+{
+    AdRec d{0, 0, 0, 0.0f, 0.0f};
+    d.sg = ad_phase(g, p, c, l, B, A, blk);
+    if (!d.sg) return d;
+    const float2 s = shift[ad_record(g, c, l, B, A, blk)];
+    const float fdx = floorf(s.x), fdy = floorf(s.y);
+    d.fx = s.x - fdx;
+    d.fy = s.y - fdy;
+    d.ix = (int)fminf(fmaxf(fdx, (float)(-g.w - 1)), (float)g.w);
+    d.iy = (int)fminf(fmaxf(fdy, (float)(-g.h - 1)), (float)g.h);
+    return d;
+}
+
+// Gradient that reference pixel (X, Y) of the cluster with reference node
+// (Br, Ar) pulls from its predictive siblings' gradients: for every sibling
+// block whose shifted taps can reach the pixel, the bilinear weights of the
+// taps that land on it (phase-signed), added in sibling, block-row,
+// block-column order.  fetch(sib, B, A, ky, kx) returns the block's AdRec.
+template <class Fetch>
+__device__ inline float ad_pull(const LfGeom& g, const float* __restrict__ gres, int c, int l, int Br, int Ar, int X,
+                                int Y, int reach, Fetch fetch, float acc)
 {
     const int64_t plane = (int64_t)g.w * g.h;
-    const int64_t total = 3 * (int64_t)g.n_refs * plane;
+    const int kx0 = max(0, (X - reach) / g.bs), kx1 = min(g.nbx - 1, (X + reach) / g.bs);
+    const int nby = g.h / g.bs;
+    const int ky0 = max(0, (Y - reach) / g.bs), ky1 = min(nby - 1, (Y + reach) / g.bs);
+    for (int sib = 1; sib < 4; sib++) {
+        const int B = Br + (sib >> 1), A = Ar + (sib & 1);
+        if (B >= g.nb_l[l] || A >= g.na_l[l]) continue;
+        const float* gp = gres + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
+        for (int ky = ky0; ky <= ky1; ky++)
+            for (int kx = kx0; kx <= kx1; kx++) {
+                const AdRec d = fetch(sib, B, A, ky, kx);
+                if (!d.sg) continue;
+                float blk_acc = 0.0f;
+                for (int oy = 0; oy < 2; oy++) {
+                    int ylo, yhi;
+                    ad_tap_range(Y, g.h, d.iy, oy, ky * g.bs, ky * g.bs + g.bs - 1, ylo, yhi);
+                    if (ylo > yhi) continue;
+                    const float wy = oy ? d.fy : 1.0f - d.fy;
+                    for (int ox = 0; ox < 2; ox++) {
+                        int xlo, xhi;
+                        ad_tap_range(X, g.w, d.ix, ox, kx * g.bs, kx * g.bs + g.bs - 1, xlo, xhi);
+                        if (xlo > xhi) continue;
+                        const float wxy = wy * (ox ? d.fx : 1.0f - d.fx);
+                        float sum = 0.0f;
+                        for (int y = ylo; y <= yhi; y++)
+                            for (int x = xlo; x <= xhi; x++) sum += gp[y * g.w + x];
+                        blk_acc = fmaf(wxy, sum, blk_acc);
+                    }
+                }
+                acc += d.sg > 0 ? blk_acc : -blk_acc;
+            }
+    }
+    return acc;
+}
+
+
+// reference residual gradient: own node gradient plus the phase-signed
+// bilinear transpose of every predictive sibling's gradient (pull form).  A
+// workgroup takes 16x16 tiles of one reference plane; the blocks any pixel
+// of the tile can pull from are decoded once per tile into LDS (phase and
+// split shift), unless there are more than the LDS budget holds, in which
+// case every pixel decodes them itself.
+__global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const float2* __restrict__ shift,
+                                                      const float* __restrict__ maxshift, float* __restrict__ gres)
+{
+    __shared__ int4 rec[AD_CAND_MAX];
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int tiles_x = (g.w + AD_TILE - 1) / AD_TILE, tiles_y = (g.h + AD_TILE - 1) / AD_TILE;
+    const int64_t per_plane = (int64_t)tiles_x * tiles_y;
+    const int64_t n_tiles = 3 * (int64_t)g.n_refs * per_plane;
     const int reach = (int)ceilf(fminf(maxshift[0], (float)(g.w + g.h))) + 2;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t px = t % plane;
-        const int r = (int)((t / plane) % g.n_refs);
-        const int c = (int)(t / (plane * g.n_refs));
+    const int nby = g.h / g.bs;
+    for (int64_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
+        const int64_t rp = T / per_plane;
+        const int tt = (int)(T - rp * per_plane);
+        const int c = (int)(rp / g.n_refs), r = (int)(rp % g.n_refs);
         int l = 0;
         while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
         const int loc = r - g.ref_base[l];
         const int Br = 2 * (loc / g.na_l[l + 1]), Ar = 2 * (loc % g.na_l[l + 1]);
-        const int Y = (int)(px / g.w), X = (int)(px % g.w);
-        const int64_t rnode = g.node_base[l] + Br * g.na_l[l] + Ar;
-        float acc = gres[((int64_t)c * g.n_nodes + rnode) * plane + px];
-        const int kx0 = max(0, (X - reach) / g.bs), kx1 = min(g.nbx - 1, (X + reach) / g.bs);
-        const int nby = g.h / g.bs;
-        const int ky0 = max(0, (Y - reach) / g.bs), ky1 = min(nby - 1, (Y + reach) / g.bs);
-        for (int sib = 1; sib < 4; sib++) {
-            const int B = Br + (sib >> 1), A = Ar + (sib & 1);
-            if (B >= g.nb_l[l] || A >= g.na_l[l]) continue;
-            const float* gp = gres + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
-            for (int ky = ky0; ky <= ky1; ky++)
-                for (int kx = kx0; kx <= kx1; kx++) {
-                    const int blk = ky * g.nbx + kx;
-                    const int sg = ad_phase(g, p, c, l, B, A, blk);
-                    if (!sg) continue;
-                    const float2 d = shift[ad_record(g, c, l, B, A, blk)];
-                    const float fdx = floorf(d.x), fdy = floorf(d.y);
-                    const float fx = d.x - fdx, fy = d.y - fdy;
-                    const int ix = (int)fdx, iy = (int)fdy;
-                    float blk_acc = 0.0f;
-                    for (int oy = 0; oy < 2; oy++) {
-                        int ylo, yhi;
-                        ad_tap_range(Y, g.h, iy, oy, ky * g.bs, ky * g.bs + g.bs - 1, ylo, yhi);
-                        if (ylo > yhi) continue;
-                        const float wy = oy ? fy : 1.0f - fy;
-                        for (int ox = 0; ox < 2; ox++) {
-                            int xlo, xhi;
-                            ad_tap_range(X, g.w, ix, ox, kx * g.bs, kx * g.bs + g.bs - 1, xlo, xhi);
-                            if (xlo > xhi) continue;
-                            const float wxy = wy * (ox ? fx : 1.0f - fx);
-                            float sum = 0.0f;
-                            for (int y = ylo; y <= yhi; y++)
-                                for (int x = xlo; x <= xhi; x++) sum += gp[y * g.w + x];
-                            blk_acc = fmaf(wxy, sum, blk_acc);
-                        }
-                    }
-                    acc += sg > 0 ? blk_acc : -blk_acc;
+        const int tx0 = (tt % tiles_x) * AD_TILE, ty0 = (tt / tiles_x) * AD_TILE;
+        const int tx1 = min(tx0 + AD_TILE - 1, g.w - 1), ty1 = min(ty0 + AD_TILE - 1, g.h - 1);
+        const int ckx0 = max(0, (tx0 - reach) / g.bs), ckx1 = min(g.nbx - 1, (tx1 + reach) / g.bs);
+        const int cky0 = max(0, (ty0 - reach) / g.bs), cky1 = min(nby - 1, (ty1 + reach) / g.bs);
+        const int nkx = ckx1 - ckx0 + 1, nk = nkx * (cky1 - cky0 + 1);
+        const bool staged = 3 * nk <= AD_CAND_MAX;  // uniform
+        if (staged) {
+            for (int e = threadIdx.x; e < 3 * nk; e += blockDim.x) {
+                const int sib = 1 + e / nk, k = e - (sib - 1) * nk;
+                const int B = Br + (sib >> 1), A = Ar + (sib & 1);
+                int4 v = make_int4(0, 0, 0, 0);
+                if (B < g.nb_l[l] && A < g.na_l[l]) {
+                    const AdRec d =
+                        ad_fetch(g, p, shift, c, l, B, A, (cky0 + k / nkx) * g.nbx + ckx0 + k % nkx);
+                    v = make_int4(d.sg, (d.ix & 0xFFFF) | (d.iy << 16), __float_as_int(d.fx), __float_as_int(d.fy));
                 }
+                rec[e] = v;
+            }
         }
-        gres[((int64_t)c * g.n_nodes + rnode) * plane + px] = acc;
+        __syncthreads();
+        const int X = tx0 + (int)threadIdx.x % AD_TILE, Y = ty0 + (int)threadIdx.x / AD_TILE;
+        if (X <= tx1 && Y <= ty1) {
+            const int64_t own = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + Y * g.w + X;
+            float acc = gres[own];
+            if (staged)
+                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach,
+                              [&](int sib, int, int, int ky, int kx) {
+                                  const int4 v = rec[(sib - 1) * nk + (ky - cky0) * nkx + (kx - ckx0)];
+                                  return AdRec{v.x, (int)(int16_t)(v.y & 0xFFFF), v.y >> 16, __int_as_float(v.z),
+                                               __int_as_float(v.w)};
+                              },
+                              acc);
+            else
+                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach,
+                              [&](int, int B, int A, int ky, int kx) {
+                                  return ad_fetch(g, p, shift, c, l, B, A, ky * g.nbx + kx);
+                              },
+                              acc);
+            gres[own] = acc;
+        }
+        __syncthreads();  // rec is rewritten for the next tile
     }
 }
 
@@ -504,13 +605,18 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
                        height, d_grad_out, kout, vout, Bl.n_pairs, Bl.n_samples, gs);
     for (int l = 0; l < g.H; l++)
         hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, gs, Bl.n_samples, d_grad_residual);
-    hipLaunchKernelGGL(k_ad_maxshift, dim3(1), dim3(256), 0, s, (const float2*)d_shift, h->L.n_rec, mxs);
+    float* parts = (float*)(W + Bl.o_parts);
+    hipLaunchKernelGGL(k_ad_maxshift, dim3(AD_MAX_PARTS), dim3(256), 0, s, (const float2*)d_shift, h->L.n_rec, parts);
+    hipLaunchKernelGGL(k_ad_maxparts, dim3(1), dim3(256), 0, s, parts, AD_MAX_PARTS, mxs);
     // shift gradients read the predictive nodes' gradients, which the
     // reference pass leaves untouched; run them first to keep the order plain
     if (h->L.n_rec > 0)
         hipLaunchKernelGGL(k_ad_shift, dim3((unsigned)h->L.n_rec), dim3(256), 0, s, g, h->p, d_residual,
                            (const float2*)d_shift, d_grad_residual, (float2*)d_grad_shift);
-    hipLaunchKernelGGL(k_ad_reference, dim3(16384), dim3(256), 0, s, g, h->p, (const float2*)d_shift, mxs,
-                       d_grad_residual);
+    {
+        const int64_t n_tiles = 3 * (int64_t)g.n_refs * ((g.w + AD_TILE - 1) / AD_TILE) * ((g.h + AD_TILE - 1) / AD_TILE);
+        hipLaunchKernelGGL(k_ad_reference, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(n_tiles, 1), 65536)),
+                           dim3(256), 0, s, g, h->p, (const float2*)d_shift, mxs, d_grad_residual);
+    }
     return lf_check_launch("render_backward");
 }
