@@ -125,28 +125,72 @@ __device__ __forceinline__ float ad_bilerp(const float* __restrict__ R, int w, i
     return ad_lerp(ad_lerp(R[ya * w + xa], R[ya * w + xb], fx), ad_lerp(R[yb * w + xa], R[yb * w + xb], fx), fy);
 }
 
-__device__ inline float ad_channel(const LfGeom& g, const LfPtrs& p, const float* __restrict__ res,
-                                   const float2* __restrict__ shift, int c, int b, int a, int y, int x)
+// Relaxed SRV values of node (B, A) of level l, channel c, at the pixels
+// (ys[k >> 1], xs[k & 1]): the residual plus the phase-signed bilinear
+// prediction; the block's phase and shift are read once per block.
+__device__ inline void ad_srv_quad(const LfGeom& g, const LfPtrs& p, const float* __restrict__ res,
+                                   const float2* __restrict__ shift, int c, int l, int B, int A, const int ys[2],
+                                   const int xs[2], float v[4])
 {
     const int64_t plane = (int64_t)g.w * g.h;
-    float v = (float)p.root[((size_t)(c * g.root_nb + (b >> g.H)) * g.root_na + (a >> g.H)) * plane + y * g.w + x];
-    const int blk = (y / g.bs) * g.nbx + x / g.bs;
-    for (int l = 0; l < g.H; l++) {
-        const int B = b >> l, A = a >> l;
-        const int node = g.node_base[l] + B * g.na_l[l] + A;
-        float s = res[((int64_t)c * g.n_nodes + node) * plane + y * g.w + x];
-        if ((A | B) & 1) {
-            const int sg = ad_phase(g, p, c, l, B, A, blk);
+    const float* S = res + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
+    const bool pred = (A | B) & 1;
+    const float* R = res + ((int64_t)c * g.n_nodes + g.node_base[l] + (B & ~1) * g.na_l[l] + (A & ~1)) * plane;
+    int blk0 = -1, sg = 0;
+    float2 d = make_float2(0.0f, 0.0f);
+#pragma unroll 1
+    for (int k = 0; k < 4; k++) {
+        const int y = ys[k >> 1], x = xs[k & 1];
+        float sv = S[y * g.w + x];
+        if (pred) {
+            const int blk = (y / g.bs) * g.nbx + x / g.bs;
+            if (blk != blk0) {
+                sg = ad_phase(g, p, c, l, B, A, blk);
+                if (sg) d = shift[ad_record(g, c, l, B, A, blk)];
+                blk0 = blk;
+            }
             if (sg) {
-                const int rnode = g.node_base[l] + (B & ~1) * g.na_l[l] + (A & ~1);
-                const float q = ad_bilerp(res + ((int64_t)c * g.n_nodes + rnode) * plane, g.w, g.h, y, x,
-                                          shift[ad_record(g, c, l, B, A, blk)]);
-                s += sg > 0 ? q : -q;
+                const float q = ad_bilerp(R, g.w, g.h, y, x, d);
+                sv += sg > 0 ? q : -q;
             }
         }
-        v += s;
+        v[k] = sv;
     }
-    return v;
+}
+
+// One channel of the 16 samples of a ray (view k >> 2 = b0a0, b0a1, b1a0,
+// b1a1, pixel k & 3): root plus the relaxed SRVs of levels 0 .. H-1, added in
+// that order; views sharing a tree node share its evaluation.
+__device__ __forceinline__ void ad_ray_channel(const LfGeom& g, const LfPtrs& p, const float* __restrict__ res,
+                                               const float2* __restrict__ shift, const AdRay& r, int c, float acc[16])
+{
+    const int ys[2] = {r.y0, r.y1}, xs[2] = {r.x0, r.x1};
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int H = g.H;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int b = (q & 2) ? r.b1 : r.b0, a = (q & 1) ? r.a1 : r.a0;
+        const int16_t* rt = p.root + ((size_t)(c * g.root_nb + (b >> H)) * g.root_na + (a >> H)) * plane;
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[4 * q + k] = (float)rt[ys[k >> 1] * g.w + xs[k & 1]];
+    }
+    for (int l = 0; l < H; l++) {
+        const bool eqA = (r.a0 >> l) == (r.a1 >> l), eqB = (r.b0 >> l) == (r.b1 >> l);
+        float v[4][4];
+        ad_srv_quad(g, p, res, shift, c, l, r.b0 >> l, r.a0 >> l, ys, xs, v[0]);
+        if (!eqA) ad_srv_quad(g, p, res, shift, c, l, r.b0 >> l, r.a1 >> l, ys, xs, v[1]);
+        if (!eqB) ad_srv_quad(g, p, res, shift, c, l, r.b1 >> l, r.a0 >> l, ys, xs, v[2]);
+        if (!eqA && !eqB) ad_srv_quad(g, p, res, shift, c, l, r.b1 >> l, r.a1 >> l, ys, xs, v[3]);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (eqA) v[1][k] = v[0][k];
+            if (eqB) v[2][k] = v[0][k];
+            if (eqB) v[3][k] = v[1][k];
+            else if (eqA) v[3][k] = v[2][k];
+#pragma unroll
+            for (int q = 0; q < 4; q++) acc[4 * q + k] += v[q][k];
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_render_relaxed(LfGeom g, LfPtrs p, const float* __restrict__ res,
@@ -161,14 +205,14 @@ __global__ void __launch_bounds__(256) k_render_relaxed(LfGeom g, LfPtrs p, cons
     const int64_t px = r - (int64_t)v * npix;
     const int j = (int)(px / wo), i = (int)(px % wo);
     const AdRay ry = ad_ray(g, cams + 18 * v, i, j);
+    float Ys[16], Cos[16], Cgs[16];
+    ad_ray_channel(g, p, res, shift, ry, 0, Ys);
+    ad_ray_channel(g, p, res, shift, ry, 1, Cos);
+    ad_ray_channel(g, p, res, shift, ry, 2, Cgs);
     float sm[16][3];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-        const int b = (k & 8) ? ry.b1 : ry.b0, a = (k & 4) ? ry.a1 : ry.a0;
-        const int y = (k & 2) ? ry.y1 : ry.y0, x = (k & 1) ? ry.x1 : ry.x0;
-        const float Y = ad_channel(g, p, res, shift, 0, b, a, y, x);
-        const float Co = ad_channel(g, p, res, shift, 1, b, a, y, x);
-        const float Cg = ad_channel(g, p, res, shift, 2, b, a, y, x);
+        const float Y = Ys[k], Co = Cos[k], Cg = Cgs[k];
         sm[k][0] = Y + 0.5f * Co - 0.5f * Cg;
         sm[k][1] = Y + 0.5f * Cg;
         sm[k][2] = Y - 0.5f * Co - 0.5f * Cg;
