@@ -22,8 +22,10 @@
  *    "Host" pointers are ordinary process memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call that takes a stream only enqueues work on it; outputs are
- *    ready when the stream is synchronised.  Argument checks happen on the
- *    host before anything is enqueued.
+ *    ready when the stream is synchronised.  The exceptions say so: loading
+ *    (lf_load_compressed, lf_load_compressed_ex) and the device-assisted
+ *    encoder (lf_encode_device) wait for their work before returning.
+ *    Argument checks happen on the host before anything is enqueued.
  *  - Return value: LF_OK, or a negative lf_status; lf_last_error() gives a
  *    thread-local message for the last failure.
  *  - A handle is immutable after loading; calls that only read it may run
