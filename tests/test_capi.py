@@ -101,3 +101,27 @@ def test_sparse_residency_arena(tiny_lf, tiny_stream):
     with pytest.raises(lf.LFError) as e:  # unknown load flags
         lf.check(lf.lib().lf_query_arena_ex(s.ctypes.data_as(C.c_void_p), s.size, 6, C.byref(C.c_int64())))
     assert e.value.status == lf.LF_EINVAL
+
+
+def test_encode_workspace_bytes():
+    """Device-search workspace: the largest level's SRV and reconstructed
+    planes (int16), item list (3 int32) and results (4 int32), 256-aligned."""
+    from paper_1902_09396_amd import lf
+
+    import lfscene
+
+    al = lambda v: (v + 255) // 256 * 256  # noqa: E731
+    for name, over in (("tiny", {}), ("path512", {}), ("tiny", {"no_mc": True})):
+        cfg = lfscene.get_config(name, **over)
+        L, enc = cfg["lf"], cfg["enc"]
+        na, nb, h, w, bs, H = L["na"], L["nb"], L["h"], L["w"], enc["block"], enc["levels"]
+        expect = 0
+        if not enc.get("no_mc", False):
+            for _ in range(H):
+                npred = ((nb // 2) * na + ((nb + 1) // 2) * (na // 2)) * (w // bs) * (h // bs)
+                expect = max(expect, 2 * al(3 * na * nb * w * h * 2) + al(3 * npred * 12) + al(3 * npred * 16))
+                na, nb = (na + 1) // 2, (nb + 1) // 2
+        got = C.c_int64()
+        p = lf._encode_params(enc)
+        lf.check(lf.lib().lf_encode_workspace_bytes(L["nb"], L["na"], h, w, C.byref(p), C.byref(got)))
+        assert got.value == expect, name
