@@ -347,8 +347,11 @@ void lf_server::run()
         for (StreamCtx& sc : streams) inflight |= sc.busy;
         if (!launched) {
             if (inflight) {
+                // poll the launches in flight without sleeping: a timed sleep
+                // lasts tens of microseconds (timer slack), which a finished
+                // request would wait on top of its render
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(5));
+                std::this_thread::yield();
                 lk.lock();
             } else {
                 cv_work.wait_for(lk, std::chrono::milliseconds(2));
