@@ -454,8 +454,10 @@ __device__ __forceinline__ AdRec ad_fetch(const LfGeom& g, const LfPtrs& p, cons
 // block-column order.  fetch(sib, B, A, ky, kx) returns the block's AdRec.
 template <class Fetch>
 __device__ inline float ad_pull(const LfGeom& g, const float* __restrict__ gres, int c, int l, int Br, int Ar, int X,
-                                int Y, int reach, Fetch fetch, float acc)
+                                int Y, int reach, int lky0, int lky1, int lkx0, int lkx1, Fetch fetch, float acc)
 {
+    // the loops run over [lky0, lky1] x [lkx0, lkx1] (a tile's shared range,
+    // uniform across its pixels) and skip the blocks outside this pixel's range
     const int64_t plane = (int64_t)g.w * g.h;
     const int kx0 = max(0, (X - reach) / g.bs), kx1 = min(g.nbx - 1, (X + reach) / g.bs);
     const int nby = g.h / g.bs;
@@ -464,8 +466,9 @@ __device__ inline float ad_pull(const LfGeom& g, const float* __restrict__ gres,
         const int B = Br + (sib >> 1), A = Ar + (sib & 1);
         if (B >= g.nb_l[l] || A >= g.na_l[l]) continue;
         const float* gp = gres + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
-        for (int ky = ky0; ky <= ky1; ky++)
-            for (int kx = kx0; kx <= kx1; kx++) {
+        for (int ky = lky0; ky <= lky1; ky++)
+            for (int kx = lkx0; kx <= lkx1; kx++) {
+                if (ky < ky0 || ky > ky1 || kx < kx0 || kx > kx1) continue;
                 const AdRec d = fetch(sib, B, A, ky, kx);
                 if (!d.sg) continue;
                 float blk_acc = 0.0f;
@@ -541,7 +544,7 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const 
             const int64_t own = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + Y * g.w + X;
             float acc = gres[own];
             if (staged)
-                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach,
+                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach, cky0, cky1, ckx0, ckx1,
                               [&](int sib, int, int, int ky, int kx) {
                                   const int4 v = rec[(sib - 1) * nk + (ky - cky0) * nkx + (kx - ckx0)];
                                   return AdRec{v.x, (int)(int16_t)(v.y & 0xFFFF), v.y >> 16, __int_as_float(v.z),
@@ -549,7 +552,9 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const 
                               },
                               acc);
             else
-                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach,
+                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach, max(0, (Y - reach) / g.bs),
+                              min(nby - 1, (Y + reach) / g.bs), max(0, (X - reach) / g.bs),
+                              min(g.nbx - 1, (X + reach) / g.bs),
                               [&](int, int B, int A, int ky, int kx) {
                                   return ad_fetch(g, p, shift, c, l, B, A, ky * g.nbx + kx);
                               },
