@@ -46,6 +46,7 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
     return lf_check_launch("render_rays");
 }
 
+template <bool SMALL_BLOCKS>
 __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, int tiles_x, int tiles_y, int chunk, int fpg,
                                                      float* __restrict__ out)
@@ -65,7 +66,7 @@ __global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const f
     const int tt = (int)(work - (int64_t)vc * tiles_x * tiles_y);
     const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
     const int v0 = vc * chunk, nf = min(chunk, nv - v0);
-    lf_tile_views<false>(g, p, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
+    lf_tile_views<false, SMALL_BLOCKS>(g, p, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
 }
 
 // Per-ray rendering of the (view, tile) pairs the batched kernel marked.
@@ -165,16 +166,21 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int64_t n_work = (int64_t)tx * ty * ((nv + chunk - 1) / chunk);
     const int64_t grid = ((n_work + 7) / 8) * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
-    const size_t lds = LDS_DYN_BYTES;
-    static bool attr_set = false;
-    if (lds > 65536 && !attr_set) {
-        if (hipFuncSetAttribute((const void*)k_render_batch, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-            hipSuccess)
+    const bool small = h->L.g.bs < 16;
+    const size_t lds = small ? LDS_DYN_BYTES_SB : LDS_DYN_BYTES;
+    const void* kern = small ? (const void*)k_render_batch<true> : (const void*)k_render_batch<false>;
+    static bool attr_set[2] = {false, false};
+    if (lds > 65536 && !attr_set[small]) {
+        if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return lf_fail(LF_EDEVICE, "cannot reserve %zu bytes of LDS", lds);
-        attr_set = true;
+        attr_set[small] = true;
     }
-    hipLaunchKernelGGL(k_render_batch, dim3((unsigned)grid), dim3(NT), LDS_DYN_BYTES, s, h->L.g, h->p,
-                       d_cams, nv, wo, ho, tx, ty, chunk, fpg, d_out);
+    if (small)
+        hipLaunchKernelGGL(k_render_batch<true>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv, wo,
+                           ho, tx, ty, chunk, fpg, d_out);
+    else
+        hipLaunchKernelGGL(k_render_batch<false>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv,
+                           wo, ho, tx, ty, chunk, fpg, d_out);
     // marked pairs: workgroups each check a contiguous range.  With 16x16
     // blocks few tiles exceed the staging budget and 1024 workgroups keep the
     // pass short; smaller blocks mark many more tiles, which need the wider grid.
@@ -193,10 +199,9 @@ extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, in
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
-    // the tile kernel reads dense reference planes; with blocks below 8x8 a
-    // tile's footprint holds more block descriptors than its LDS budget, so
-    // nearly every tile would fall back to the per-ray pass anyway
-    if (h->L.g.bs < 8 || h->p.slots)
+    // the tile kernel decodes quads of 4 pixels inside one block and reads
+    // dense reference planes
+    if (h->L.g.bs < 4 || h->p.slots)
         return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
     return lf_launch_render_batch(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
 }

@@ -206,6 +206,14 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
 #define B_RGBA 4096
 #define B_SVAL 12288
 #define LDS_DYN_BYTES (B_DESC * 16 + B_RGBA * 4 + B_SVAL * 2)
+// Blocks smaller than 16x16: a tile's footprint spans four times as many
+// blocks per node at 8x8, so a single view can need more descriptors and
+// decoded values than the budgets above hold.  The small-block instance takes
+// larger budgets and runs two workgroups per CU instead of three.
+#define B_DESC_SB 1024
+#define B_RGBA_SB 6144
+#define B_SVAL_SB 16384
+#define LDS_DYN_BYTES_SB (B_DESC_SB * 16 + B_RGBA_SB * 4 + B_SVAL_SB * 2)
 
 // 16-bit packed min/max (both halves at once)
 typedef unsigned short lf_u16x2 __attribute__((ext_vector_type(2)));
@@ -557,13 +565,17 @@ struct TileLds {
 // FALLBACK_MARK at the tile origin for a per-ray pass; the return value says
 // whether any view was left so (the same in every thread).  Every thread of
 // the workgroup calls it; LDS contents do not carry over between calls.
-template <bool INLINE_FALLBACK>
+template <bool INLINE_FALLBACK, bool SMALL_BLOCKS = false>
 __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
                               int gmax, int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
 {
+    // budgets of this instance (the dynamic LDS the launch reserved)
+    constexpr int BD = SMALL_BLOCKS ? B_DESC_SB : B_DESC;
+    constexpr int BR = SMALL_BLOCKS ? B_RGBA_SB : B_RGBA;
+    constexpr int BSV = SMALL_BLOCKS ? B_SVAL_SB : B_SVAL;
     uint4* desc = S.desc;
-    uint32_t* rgba = S.rgba;
-    int16_t* sval = S.sval;
+    uint32_t* rgba = reinterpret_cast<uint32_t*>(S.desc + BD);
+    int16_t* sval = reinterpret_cast<int16_t*>(rgba + BR);
     uint32_t* red = rgba;  // phase-0 reduction scratch [FMAX][4][NT/64], before any sample is staged
     uint32_t (*fbox)[4] = S.fbox;
     GroupPlan& gp = *S.gpp;
@@ -679,7 +691,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const int nbkx = (xmax >> g.bsl) - bkx0 + 1, nbk = nbkx * ((ymax >> g.bsl) - bky0 + 1);
             const uint32_t bx0 = (uint32_t)xq0 | ((uint32_t)ymin << 16), bx1 = (uint32_t)nq | ((uint32_t)sy << 16);
             const bool same = gp.cbox0 == bx0 && gp.cbox1 == bx1;  // cached entries hold this box
-            const int cap0 = min(CMAX, B_RGBA / npix), cap1 = min(CMAX, B_SVAL / (3 * npix));
+            const int cap0 = min(CMAX, BR / npix), cap1 = min(CMAX, BSV / (3 * npix));
             const int nA0 = amax - amin + 1, nB0 = bmax - bmin + 1;
             int ok = nA0 * nB0 <= LMAX;
             // node maps start empty; cache entries that a node of this group
@@ -766,7 +778,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 if (l < g.H) nd += 3 * nbk * cnt[l];
             }
             const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
-            ok = ok && nnew1 <= __popcll(free1) && nd <= B_DESC && ns <= SLOT_MAX;
+            ok = ok && nnew1 <= __popcll(free1) && nd <= BD && ns <= SLOT_MAX;
             if (ok) {
                 // commit: entries of the new nodes, node maps, new-node lists, keys
                 if (!same && lane < CMAX) {
