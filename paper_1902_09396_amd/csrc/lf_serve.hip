@@ -55,6 +55,7 @@ struct ServeWork {  // one tile of one request
 __host__ __device__ inline size_t serve_fb_off(int max_tiles) { return 1 + 3 * (size_t)max_tiles; }
 __host__ __device__ inline size_t serve_fbl_off(int max_tiles) { return serve_fb_off(max_tiles) + 3; }
 
+template <bool SMALL_BLOCKS>
 __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict__ geoms, const LfPtrs* __restrict__ ptrs,
                                                     const ServeSlot* __restrict__ slots, int32_t* __restrict__ work,
                                                     int max_tiles, uint8_t* __restrict__ pool)
@@ -90,7 +91,7 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
             }
             __syncthreads();
         }
-        const bool left = lf_tile_views<false>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
+        const bool left = lf_tile_views<false, SMALL_BLOCKS>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
                                                reinterpret_cast<float*>(pool + sl->out_off), S);
         if (left && threadIdx.x == 0) work[serve_fbl_off(max_tiles) + atomicAdd(fb, 1)] = w;
     }
@@ -206,6 +207,9 @@ struct lf_server {
     int64_t pool_bytes = 0;
     lf_server_config cfg{};
     int grid = 0;
+    // a field with blocks below 16x16 needs the tile routine's larger LDS
+    // budgets (two workgroups per CU); the server then runs that instance
+    bool small = false;
     std::vector<StreamCtx> streams;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -232,8 +236,12 @@ static lf_status capture_graph(lf_server* S, StreamCtx& sc)
         return lf_fail(LF_EDEVICE, "stream capture failed");
     hipMemcpyAsync(sc.d_work, sc.h_work, wbytes, hipMemcpyHostToDevice, sc.s);
     hipMemcpyAsync(sc.d_slots, S->h_slots, sizeof(ServeSlot) * S->cfg.max_slots, hipMemcpyHostToDevice, sc.s);
-    hipLaunchKernelGGL(k_serve_tiles, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs, sc.d_slots,
-                       sc.d_work, S->cfg.max_tiles, S->pool);
+    if (S->small)
+        hipLaunchKernelGGL(k_serve_tiles<true>, dim3(S->grid), dim3(NT), LDS_DYN_BYTES_SB, sc.s, S->d_geoms, S->d_ptrs,
+                           sc.d_slots, sc.d_work, S->cfg.max_tiles, S->pool);
+    else
+        hipLaunchKernelGGL(k_serve_tiles<false>, dim3(S->grid), dim3(NT), LDS_DYN_BYTES, sc.s, S->d_geoms, S->d_ptrs,
+                           sc.d_slots, sc.d_work, S->cfg.max_tiles, S->pool);
     hipLaunchKernelGGL(k_serve_fallback, dim3(S->grid), dim3(NT), 0, sc.s, S->d_geoms, S->d_ptrs, sc.d_slots,
                        sc.d_work, S->cfg.max_tiles, S->pool);
     if (hipStreamEndCapture(sc.s, &sc.graph) != hipSuccess) return lf_fail(LF_EDEVICE, "end capture failed");
@@ -275,8 +283,12 @@ bool lf_server::launch(StreamCtx& sc)
         hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
         hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, 3 * sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
         hipMemcpyAsync(sc.d_slots, h_slots, sizeof(ServeSlot) * cfg.max_slots, hipMemcpyHostToDevice, sc.s);
-        hipLaunchKernelGGL(k_serve_tiles, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs, sc.d_slots,
-                           sc.d_work, cfg.max_tiles, pool);
+        if (small)
+            hipLaunchKernelGGL(k_serve_tiles<true>, dim3(grid), dim3(NT), LDS_DYN_BYTES_SB, sc.s, d_geoms, d_ptrs,
+                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
+        else
+            hipLaunchKernelGGL(k_serve_tiles<false>, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs,
+                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
         hipLaunchKernelGGL(k_serve_fallback, dim3(grid), dim3(NT), 0, sc.s, d_geoms, d_ptrs, sc.d_slots, sc.d_work,
                            cfg.max_tiles, pool);
     }
@@ -377,7 +389,13 @@ extern "C" lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    S->grid = cfg->grid > 0 ? cfg->grid : 3 * std::max(cus, 1);
+    for (int k = 0; k < n_fields; k++) S->small |= fields[k]->L.g.bs < 16;
+    S->grid = cfg->grid > 0 ? cfg->grid : (S->small ? 2 : 3) * std::max(cus, 1);
+    if (S->small && hipFuncSetAttribute((const void*)k_serve_tiles<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        LDS_DYN_BYTES_SB) != hipSuccess) {
+        delete S;
+        return lf_fail(LF_EDEVICE, "cannot reserve %d bytes of LDS", LDS_DYN_BYTES_SB);
+    }
     for (int k = 0; k < n_fields; k++) {
         S->geoms.push_back(fields[k]->L.g);
         S->ptrs.push_back(fields[k]->p);
