@@ -565,13 +565,15 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const 
     }
 }
 
-// shift gradients: one workgroup per motion record, fixed-order reduction
+// shift gradients: one wave64 per motion record (four per workgroup), each
+// lane summing its pixels in order, then a fixed butterfly across the wave
 __global__ void __launch_bounds__(256) k_ad_shift(LfGeom g, LfPtrs p, const float* __restrict__ res,
                                                   const float2* __restrict__ shift, const float* __restrict__ gres_pred,
-                                                  float2* __restrict__ gshift)
+                                                  float2* __restrict__ gshift, int64_t n_rec)
 {
-    __shared__ float rx[256], ryy[256];
-    const int64_t rec = blockIdx.x;
+    const int64_t rec = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (rec >= n_rec) return;  // uniform per wave
     int c = 0, l = g.H - 1;
     while (c < 2 && rec >= g.rec_base[c + 1][g.H - 1]) c++;
     while (l > 0 && rec >= g.rec_base[c][l - 1]) l--;
@@ -597,7 +599,7 @@ __global__ void __launch_bounds__(256) k_ad_shift(LfGeom g, LfPtrs p, const floa
         const float* R = res + ((int64_t)c * g.n_nodes + g.node_base[l] + (B & ~1) * na + (A & ~1)) * plane;
         const float* gp = gres_pred + ((int64_t)c * g.n_nodes + g.node_base[l] + B * na + A) * plane;
         const int by0 = (blk / g.nbx) * g.bs, bx0 = (blk % g.nbx) * g.bs;
-        for (int q = threadIdx.x; q < g.bs * g.bs; q += blockDim.x) {
+        for (int q = lane; q < g.bs * g.bs; q += 64) {
             const int y = by0 + q / g.bs, x = bx0 + q % g.bs;
             const int x0 = x + (int)fdx, y0 = y + (int)fdy;
             const int xa = lf_clampi(x0, 0, g.w - 1), xb = lf_clampi(x0 + 1, 0, g.w - 1);
@@ -608,17 +610,12 @@ __global__ void __launch_bounds__(256) k_ad_shift(LfGeom g, LfPtrs p, const floa
             sy = fmaf(gv, (1.0f - fx) * (t10 - t00) + fx * (t11 - t01), sy);
         }
     }
-    rx[threadIdx.x] = sx;
-    ryy[threadIdx.x] = sy;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            rx[threadIdx.x] += rx[threadIdx.x + s];
-            ryy[threadIdx.x] += ryy[threadIdx.x + s];
-        }
-        __syncthreads();
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        sx += __shfl_xor(sx, o, 64);
+        sy += __shfl_xor(sy, o, 64);
     }
-    if (threadIdx.x == 0) gshift[rec] = make_float2(rx[0], ryy[0]);
+    if (lane == 0) gshift[rec] = make_float2(sx, sy);
 }
 
 extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_residual, const float* d_shift,
@@ -660,8 +657,8 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     // shift gradients read the predictive nodes' gradients, which the
     // reference pass leaves untouched; run them first to keep the order plain
     if (h->L.n_rec > 0)
-        hipLaunchKernelGGL(k_ad_shift, dim3((unsigned)h->L.n_rec), dim3(256), 0, s, g, h->p, d_residual,
-                           (const float2*)d_shift, d_grad_residual, (float2*)d_grad_shift);
+        hipLaunchKernelGGL(k_ad_shift, dim3((unsigned)((h->L.n_rec + 3) / 4)), dim3(256), 0, s, g, h->p, d_residual,
+                           (const float2*)d_shift, d_grad_residual, (float2*)d_grad_shift, h->L.n_rec);
     {
         const int64_t n_tiles = 3 * (int64_t)g.n_refs * ((g.w + AD_TILE - 1) / AD_TILE) * ((g.h + AD_TILE - 1) / AD_TILE);
         hipLaunchKernelGGL(k_ad_reference, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(n_tiles, 1), 65536)),
