@@ -21,7 +21,7 @@
 //  4. node gradients are summed up the tree level by level in fixed order;
 //  5. each reference residual pulls the phase-signed bilinear transpose of
 //     its predictive siblings' gradients;
-//  6. each block's shift gradient is a fixed-order workgroup reduction.
+//  6. each block's shift gradient is a fixed-order wave64 reduction.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
