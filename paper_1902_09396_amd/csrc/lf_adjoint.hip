@@ -251,7 +251,7 @@ struct BwdLayout {
     int64_t n_pairs, n_samples;
     int end_bit;
     size_t sort_bytes;
-    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_gs, o_max, o_parts, total;
+    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_max, o_parts, total;
 };
 
 static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
@@ -276,8 +276,7 @@ static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayou
     B->o_vin = B->o_kout + pb;
     B->o_vout = B->o_vin + pb;
     B->o_sort = B->o_vout + pb;
-    B->o_gs = B->o_sort + al256((int64_t)sb);
-    B->o_max = B->o_gs + al256(3 * B->n_samples * 4);
+    B->o_max = B->o_sort + al256((int64_t)sb);
     B->o_parts = B->o_max + 256;
     B->total = B->o_parts + al256(AD_MAX_PARTS * 4);
     return LF_OK;
@@ -319,10 +318,13 @@ __global__ void k_ad_fill(float* __restrict__ p, int64_t n)
 }
 
 // one thread per run of equal keys: sum the run in ray order
+// The sample index ((b * na + a) * h + y) * w + x is also the offset of pixel
+// (y, x) in the level-0 node planes of a channel, so the YCoCg sample
+// gradients go straight into the residual gradient (channel stride cstride).
 __global__ void k_ad_segments(LfGeom g, const float* __restrict__ cams, int wo, int ho,
                               const float* __restrict__ grad_out, const uint32_t* __restrict__ keys,
-                              const uint32_t* __restrict__ vals, int64_t n_pairs, int64_t n_samples,
-                              float* __restrict__ gs /* [3][n_samples] YCoCg */)
+                              const uint32_t* __restrict__ vals, int64_t n_pairs, int64_t cstride,
+                              float* __restrict__ g0 /* level-0 planes of channel 0 */)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pairs) return;
@@ -343,13 +345,14 @@ __global__ void k_ad_segments(LfGeom g, const float* __restrict__ cams, int wo, 
         for (int c = 0; c < 3; c++) acc[c] = fmaf(w, grad_out[((int64_t)v * 3 + c) * npix + px], acc[c]);
     }
     // colour transpose of R = Y + Co/2 - Cg/2, G = Y + Cg/2, B = Y - Co/2 - Cg/2
-    gs[key] = acc[0] + acc[1] + acc[2];
-    gs[n_samples + key] = 0.5f * (acc[0] - acc[2]);
-    gs[2 * n_samples + key] = 0.5f * (acc[1] - acc[0] - acc[2]);
+    g0[key] = acc[0] + acc[1] + acc[2];
+    g0[cstride + key] = 0.5f * (acc[0] - acc[2]);
+    g0[2 * cstride + key] = 0.5f * (acc[1] - acc[0] - acc[2]);
 }
 
-// node gradients: level 0 copies the sample gradient, level l sums its children
-__global__ void k_ad_tree(LfGeom g, int l, const float* __restrict__ gs, int64_t n_samples, float* __restrict__ gres)
+// node gradients of level l >= 1: the sum of its children's (level 0 holds
+// the sample gradients themselves)
+__global__ void k_ad_tree(LfGeom g, int l, float* __restrict__ gres)
 {
     const int64_t plane = (int64_t)g.w * g.h;
     const int64_t nodes_l = (int64_t)g.na_l[l] * g.nb_l[l];
@@ -359,18 +362,13 @@ __global__ void k_ad_tree(LfGeom g, int l, const float* __restrict__ gs, int64_t
         const int64_t loc = (t / plane) % nodes_l;
         const int c = (int)(t / (plane * nodes_l));
         const int B = (int)(loc / g.na_l[l]), A = (int)(loc % g.na_l[l]);
-        float v;
-        if (l == 0) {
-            v = gs[c * n_samples + ((int64_t)B * g.na + A) * plane + px];
-        } else {
-            v = 0.0f;
-            for (int jj = 0; jj < 2; jj++)
-                for (int ii = 0; ii < 2; ii++) {
-                    const int Bc = 2 * B + jj, Ac = 2 * A + ii;
-                    if (Bc >= g.nb_l[l - 1] || Ac >= g.na_l[l - 1]) continue;
-                    v += gres[((int64_t)c * g.n_nodes + g.node_base[l - 1] + Bc * g.na_l[l - 1] + Ac) * plane + px];
-                }
-        }
+        float v = 0.0f;
+        for (int jj = 0; jj < 2; jj++)
+            for (int ii = 0; ii < 2; ii++) {
+                const int Bc = 2 * B + jj, Ac = 2 * A + ii;
+                if (Bc >= g.nb_l[l - 1] || Ac >= g.na_l[l - 1]) continue;
+                v += gres[((int64_t)c * g.n_nodes + g.node_base[l - 1] + Bc * g.na_l[l - 1] + Ac) * plane + px];
+            }
         gres[((int64_t)c * g.n_nodes + g.node_base[l] + loc) * plane + px] = v;
     }
 }
@@ -637,7 +635,6 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     uint8_t* W = (uint8_t*)d_workspace;
     uint32_t *kin = (uint32_t*)(W + Bl.o_kin), *kout = (uint32_t*)(W + Bl.o_kout);
     uint32_t *vin = (uint32_t*)(W + Bl.o_vin), *vout = (uint32_t*)(W + Bl.o_vout);
-    float* gs = (float*)(W + Bl.o_gs);
     float* mxs = (float*)(W + Bl.o_max);
     const int64_t rays = (int64_t)n_views * width * height;
     hipLaunchKernelGGL(k_ad_pairs, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, d_cams, n_views, width,
@@ -646,11 +643,15 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     if (hipcub::DeviceRadixSort::SortPairs(W + Bl.o_sort, sb, kin, kout, vin, vout, (int)Bl.n_pairs, 0, Bl.end_bit, s) !=
         hipSuccess)
         return lf_fail(LF_EDEVICE, "radix sort failed");
-    hipLaunchKernelGGL(k_ad_fill, dim3(4096), dim3(256), 0, s, gs, 3 * Bl.n_samples);
+    // level-0 node planes of each channel: the samples not reached stay zero
+    const int64_t plane = (int64_t)g.w * g.h, cstride = (int64_t)g.n_nodes * plane;
+    float* g0 = d_grad_residual + (int64_t)g.node_base[0] * plane;
+    for (int c = 0; c < 3; c++)
+        hipLaunchKernelGGL(k_ad_fill, dim3(4096), dim3(256), 0, s, g0 + c * cstride, Bl.n_samples);
     hipLaunchKernelGGL(k_ad_segments, dim3((unsigned)((Bl.n_pairs + 255) / 256)), dim3(256), 0, s, g, d_cams, width,
-                       height, d_grad_out, kout, vout, Bl.n_pairs, Bl.n_samples, gs);
-    for (int l = 0; l < g.H; l++)
-        hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, gs, Bl.n_samples, d_grad_residual);
+                       height, d_grad_out, kout, vout, Bl.n_pairs, cstride, g0);
+    for (int l = 1; l < g.H; l++)
+        hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, d_grad_residual);
     float* parts = (float*)(W + Bl.o_parts);
     hipLaunchKernelGGL(k_ad_maxshift, dim3(AD_MAX_PARTS), dim3(256), 0, s, (const float2*)d_shift, h->L.n_rec, parts);
     hipLaunchKernelGGL(k_ad_maxparts, dim3(1), dim3(256), 0, s, parts, AD_MAX_PARTS, mxs);
