@@ -251,7 +251,7 @@ struct BwdLayout {
     int64_t n_pairs, n_samples;
     int end_bit;
     size_t sort_bytes;
-    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_max, o_parts, total;
+    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_max, o_parts, o_rayf, total;
 };
 
 static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
@@ -278,7 +278,8 @@ static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayou
     B->o_sort = B->o_vout + pb;
     B->o_max = B->o_sort + al256((int64_t)sb);
     B->o_parts = B->o_max + 256;
-    B->total = B->o_parts + al256(AD_MAX_PARTS * 4);
+    B->o_rayf = B->o_parts + al256(AD_MAX_PARTS * 4);
+    B->total = B->o_rayf + al256(B->n_pairs / 16 * 16);  // one float4 per ray
     return LF_OK;
 }
 
@@ -294,7 +295,7 @@ extern "C" lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, 
 }
 
 __global__ void k_ad_pairs(LfGeom g, const float* __restrict__ cams, int nv, int wo, int ho, uint32_t* __restrict__ keys,
-                           uint32_t* __restrict__ vals)
+                           uint32_t* __restrict__ vals, float4* __restrict__ rayf)
 {
     const int64_t npix = (int64_t)wo * ho;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -302,6 +303,7 @@ __global__ void k_ad_pairs(LfGeom g, const float* __restrict__ cams, int nv, int
     const int v = (int)(r / npix);
     const int64_t px = r - (int64_t)v * npix;
     const AdRay ry = ad_ray(g, cams + 18 * v, (int)(px % wo), (int)(px / wo));
+    rayf[r] = make_float4(ry.fu, ry.fv, ry.fs, ry.ft);  // the blend fractions, for the segment pass
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         const int b = (k & 8) ? ry.b1 : ry.b0, a = (k & 4) ? ry.a1 : ry.a0;
@@ -321,10 +323,9 @@ __global__ void k_ad_fill(float* __restrict__ p, int64_t n)
 // The sample index ((b * na + a) * h + y) * w + x is also the offset of pixel
 // (y, x) in the level-0 node planes of a channel, so the YCoCg sample
 // gradients go straight into the residual gradient (channel stride cstride).
-__global__ void k_ad_segments(LfGeom g, const float* __restrict__ cams, int wo, int ho,
-                              const float* __restrict__ grad_out, const uint32_t* __restrict__ keys,
-                              const uint32_t* __restrict__ vals, int64_t n_pairs, int64_t cstride,
-                              float* __restrict__ g0 /* level-0 planes of channel 0 */)
+__global__ void k_ad_segments(const float4* __restrict__ rayf, int wo, int ho, const float* __restrict__ grad_out,
+                              const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n_pairs,
+                              int64_t cstride, float* __restrict__ g0 /* level-0 planes of channel 0 */)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pairs) return;
@@ -338,9 +339,9 @@ __global__ void k_ad_segments(LfGeom g, const float* __restrict__ cams, int wo, 
         const int k = (int)(val & 15u);
         const int v = (int)(ray / npix);
         const int64_t px = ray - (int64_t)v * npix;
-        const AdRay ry = ad_ray(g, cams + 18 * v, (int)(px % wo), (int)(px / wo));
-        const float w = ((k & 8) ? ry.fv : 1.0f - ry.fv) * ((k & 4) ? ry.fu : 1.0f - ry.fu) *
-                        ((k & 2) ? ry.ft : 1.0f - ry.ft) * ((k & 1) ? ry.fs : 1.0f - ry.fs) * (1.0f / 255.0f);
+        const float4 f = rayf[ray];  // (fu, fv, fs, ft)
+        const float w = ((k & 8) ? f.y : 1.0f - f.y) * ((k & 4) ? f.x : 1.0f - f.x) *
+                        ((k & 2) ? f.w : 1.0f - f.w) * ((k & 1) ? f.z : 1.0f - f.z) * (1.0f / 255.0f);
 #pragma unroll
         for (int c = 0; c < 3; c++) acc[c] = fmaf(w, grad_out[((int64_t)v * 3 + c) * npix + px], acc[c]);
     }
@@ -636,9 +637,10 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     uint32_t *kin = (uint32_t*)(W + Bl.o_kin), *kout = (uint32_t*)(W + Bl.o_kout);
     uint32_t *vin = (uint32_t*)(W + Bl.o_vin), *vout = (uint32_t*)(W + Bl.o_vout);
     float* mxs = (float*)(W + Bl.o_max);
+    float4* rayf = (float4*)(W + Bl.o_rayf);
     const int64_t rays = (int64_t)n_views * width * height;
     hipLaunchKernelGGL(k_ad_pairs, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, d_cams, n_views, width,
-                       height, kin, vin);
+                       height, kin, vin, rayf);
     size_t sb = Bl.sort_bytes;
     if (hipcub::DeviceRadixSort::SortPairs(W + Bl.o_sort, sb, kin, kout, vin, vout, (int)Bl.n_pairs, 0, Bl.end_bit, s) !=
         hipSuccess)
@@ -648,8 +650,8 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     float* g0 = d_grad_residual + (int64_t)g.node_base[0] * plane;
     for (int c = 0; c < 3; c++)
         hipLaunchKernelGGL(k_ad_fill, dim3(4096), dim3(256), 0, s, g0 + c * cstride, Bl.n_samples);
-    hipLaunchKernelGGL(k_ad_segments, dim3((unsigned)((Bl.n_pairs + 255) / 256)), dim3(256), 0, s, g, d_cams, width,
-                       height, d_grad_out, kout, vout, Bl.n_pairs, cstride, g0);
+    hipLaunchKernelGGL(k_ad_segments, dim3((unsigned)((Bl.n_pairs + 255) / 256)), dim3(256), 0, s, rayf, width, height,
+                       d_grad_out, kout, vout, Bl.n_pairs, cstride, g0);
     for (int l = 1; l < g.H; l++)
         hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, d_grad_residual);
     float* parts = (float*)(W + Bl.o_parts);
