@@ -13,11 +13,12 @@
 // fraction (floor(x + dx) = x + floor(dx)), which both directions use.
 //
 // Adjoint, deterministic and without atomics:
-//  1. every ray emits (sample index, ray * 16 + corner) pairs;
-//  2. a stable radix sort groups them by sample;
-//  3. a segmented reduction walks each sample's run in ray order, recomputes
-//     each ray's blend weight from its camera (nothing of the forward is
-//     stored) and applies the colour transpose;
+//  1. every ray emits (sample index, ray * 16 + corner) pairs and its four
+//     blend fractions;
+//  2. a stable radix sort groups the pairs by sample;
+//  3. a segmented reduction walks each sample's run in ray order, forms each
+//     ray's blend weight from its fractions and applies the colour transpose,
+//     writing the sample gradients into the level-0 node planes;
 //  4. node gradients are summed up the tree level by level in fixed order;
 //  5. each reference residual pulls the phase-signed bilinear transpose of
 //     its predictive siblings' gradients;
