@@ -126,14 +126,13 @@ static int better(int64_t c, int mx, int my, int64_t bc, int bmx, int bmy)
     return mx < bmx;
 }
 
-/* quarter-pel cost with early abandon: stops (returning a value above
- * `bound`) once the partial sum exceeds it, which cannot change a ranking
- * that only keeps candidates with cost <= bound */
-static int64_t block_cost_bounded(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
-                                  int mx, int my, int sigma, int64_t bound)
+/* Eq. 1 (sigma = +1) and Eq. 2 (sigma = -1) cost of one candidate: the sum
+ * over the block of |P - sigma * Q(R; mx, my)|. */
+static int64_t block_cost(const int32_t* p, const int32_t* r, int w, int h, int by0, int bx0, int bs,
+                          int mx, int my, int sigma)
 {
     int64_t s = 0;
-    for (int y = by0; y < by0 + bs && s <= bound; y++)
+    for (int y = by0; y < by0 + bs; y++)
         for (int x = bx0; x < bx0 + bs; x++) {
             int32_t pred = sigma * orc_qpel(r, w, h, y, x, mx, my);
             s += iabs(p[(int64_t)y * w + x] - pred);
@@ -145,48 +144,42 @@ int64_t orc_mc_search(const int32_t* p, const int32_t* r, int w, int h, int by0,
                       int win, int subpel, int zero_phase, int* mx, int* my, int* sigma)
 {
     /* index 0: sigma = +1 (Eq. 1, subtractive error), index 1: sigma = -1 (Eq. 2, additive error) */
-    int64_t best_cost[2] = {INT64_MAX, INT64_MAX};
-    int best_mx[2] = {0, 0}, best_my[2] = {0, 0};
+    int64_t best_cost[2];
+    int best_mx[2], best_my[2];
     const int sig[2] = {+1, -1};
-    /* integer positions: Q with fx = fy = 0 is the clamped tap itself, so both
-     * errors are summed directly from the taps in one pass */
-    for (int dy = -win; dy <= win; dy++)
-        for (int dx = -win; dx <= win; dx++) {
-            int64_t cp = 0, cm = 0;
-            for (int y = by0; y < by0 + bs && (cp <= best_cost[0] || cm <= best_cost[1]); y++) {
-                int yy = orc_clampi(y + dy, 0, h - 1);
-                for (int x = bx0; x < bx0 + bs; x++) {
-                    int xx = orc_clampi(x + dx, 0, w - 1);
-                    int32_t pv = p[(int64_t)y * w + x], rv = r[(int64_t)yy * w + xx];
-                    cp += iabs(pv - rv);
-                    cm += iabs(pv + rv);
+    for (int si = 0; si < 2; si++) {
+        /* every whole-pixel shift in [-W, W]^2 */
+        int64_t bc = INT64_MAX;
+        int bmx = 0, bmy = 0;
+        for (int dy = -win; dy <= win; dy++)
+            for (int dx = -win; dx <= win; dx++) {
+                int64_t c = block_cost(p, r, w, h, by0, bx0, bs, 4 * dx, 4 * dy, sig[si]);
+                if (bc == INT64_MAX || better(c, 4 * dx, 4 * dy, bc, bmx, bmy)) {
+                    bc = c;
+                    bmx = 4 * dx;
+                    bmy = 4 * dy;
                 }
             }
-            int64_t c2[2] = {cp, cm};
-            for (int si = 0; si < 2; si++)
-                if (best_cost[si] == INT64_MAX || better(c2[si], 4 * dx, 4 * dy, best_cost[si], best_mx[si], best_my[si])) {
-                    best_cost[si] = c2[si];
-                    best_mx[si] = 4 * dx;
-                    best_my[si] = 4 * dy;
-                }
-        }
-    /* quarter-pel refinement around each phase's integer best */
-    if (subpel)
-        for (int si = 0; si < 2; si++) {
-            int cmx = best_mx[si], cmy = best_my[si];
+        /* then the quarter-pel positions within +-3 of that phase's whole-pixel best */
+        if (subpel) {
+            const int cmx = bmx, cmy = bmy;
             for (int ey = -3; ey <= 3; ey++)
                 for (int ex = -3; ex <= 3; ex++) {
                     int qx = cmx + ex, qy = cmy + ey;
                     if (qx < -4 * win || qx > 4 * win || qy < -4 * win || qy > 4 * win) continue;
-                    if ((qx & 3) == 0 && (qy & 3) == 0) continue; /* integer positions already ranked */
-                    int64_t c = block_cost_bounded(p, r, w, h, by0, bx0, bs, qx, qy, sig[si], best_cost[si]);
-                    if (better(c, qx, qy, best_cost[si], best_mx[si], best_my[si])) {
-                        best_cost[si] = c;
-                        best_mx[si] = qx;
-                        best_my[si] = qy;
+                    if ((qx & 3) == 0 && (qy & 3) == 0) continue; /* whole-pixel positions already ranked */
+                    int64_t c = block_cost(p, r, w, h, by0, bx0, bs, qx, qy, sig[si]);
+                    if (better(c, qx, qy, bc, bmx, bmy)) {
+                        bc = c;
+                        bmx = qx;
+                        bmy = qy;
                     }
                 }
         }
+        best_cost[si] = bc;
+        best_mx[si] = bmx;
+        best_my[si] = bmy;
+    }
     int pick = best_cost[1] < best_cost[0] ? 1 : 0;
     *mx = best_mx[pick];
     *my = best_my[pick];

@@ -123,3 +123,92 @@ def test_search_window_brute_force_integer():
                     best = (key, 4 * dx, 4 * dy, sgn)
     cost, mx, my, sg = oracle.mc_search(P, R, by0, bx0, bs, win=win, subpel=False)
     assert (cost, mx, my, sg) == (best[0][0], best[1], best[2], best[3])
+
+
+# ---------------------------------------------------------------------------
+# Brute force over every quarter-pel position of the window (Eq. 1 and 2 with
+# the sub-pel prediction of Future Work).  The prediction is evaluated here on
+# an edge-padded copy of the reference (np.pad, mode "edge"), not by clamping
+# indices; it is pinned on closed forms first.
+
+def _qpel_all(R, by0, bx0, bs, mx, my):
+    """sigma-free quarter-pel prediction of the block at (by0, bx0)."""
+    pad = 64
+    Rp = np.pad(R.astype(np.int64), pad, mode="edge")
+    ys = 4 * np.arange(by0, by0 + bs)[:, None] + my
+    xs = 4 * np.arange(bx0, bx0 + bs)[None, :] + mx
+    y0, x0 = np.floor_divide(ys, 4), np.floor_divide(xs, 4)
+    fy, fx = ys - 4 * y0, xs - 4 * x0
+    t00 = Rp[y0 + pad, x0 + pad]
+    t01 = Rp[y0 + pad, x0 + 1 + pad]
+    t10 = Rp[y0 + 1 + pad, x0 + pad]
+    t11 = Rp[y0 + 1 + pad, x0 + 1 + pad]
+    acc = (4 - fx) * (4 - fy) * t00 + fx * (4 - fy) * t01 + (4 - fx) * fy * t10 + fx * fy * t11
+    return np.floor_divide(acc + 8, 16)
+
+
+def test_bruteforce_prediction_closed_forms():
+    # a linear plane is reproduced exactly at every quarter-pel shift (bilinear
+    # interpolation of a linear function is exact, the weights sum to 16)
+    yy, xx = np.mgrid[0:16, 0:16]
+    R = 16 * xx - 32 * yy + 5
+    for mx in range(-6, 7):
+        for my in range(-6, 7):
+            got = _qpel_all(R, 4, 4, 8, mx, my)
+            want = 16 * (xx[4:12, 4:12] + mx / 4) - 32 * (yy[4:12, 4:12] + my / 4) + 5
+            assert np.array_equal(got, want.astype(np.int64))
+    # beyond the border the edge sample is replicated
+    C = _plane(9, 8, 8)
+    assert np.array_equal(_qpel_all(C, 0, 0, 8, -40, -40), np.full((8, 8), C[0, 0]))
+
+
+def _search_by_definition(P, R, by0, bx0, bs, win, zero_phase=False):
+    """Per phase: the key-minimum over whole-pixel shifts, then over those plus
+    the quarter-pel shifts within +-3 of it (inside the window); phase -1 only
+    on a strictly lower cost; the zero phase only when strictly cheaper."""
+    lim = 4 * win
+    blk = P[by0:by0 + bs, bx0:bx0 + bs].astype(np.int64)
+    pred = {(mx, my): _qpel_all(R, by0, bx0, bs, mx, my)
+            for my in range(-lim, lim + 1) for mx in range(-lim, lim + 1)}
+    best = []
+    for sgn in (1, -1):
+        cost = {m: int(np.abs(blk - sgn * q).sum()) for m, q in pred.items()}
+        key = lambda m: (cost[m], abs(m[0]) + abs(m[1]), m[1], m[0])  # noqa: E731
+        whole = [m for m in cost if m[0] % 4 == 0 and m[1] % 4 == 0]
+        c0 = min(whole, key=key)
+        near = [m for m in cost if abs(m[0] - c0[0]) <= 3 and abs(m[1] - c0[1]) <= 3]
+        b = min(whole + near, key=key)
+        best.append((cost[b], b[0], b[1], sgn, min(cost.values())))
+    r = best[1] if best[1][0] < best[0][0] else best[0]
+    if zero_phase and int(np.abs(blk).sum()) < r[0]:
+        return (int(np.abs(blk).sum()), 0, 0, 0), None
+    return r[:4], r[4]
+
+
+@pytest.mark.parametrize("seed,by0,bx0,bs,win", [
+    (20, 4, 4, 4, 2), (21, 0, 0, 4, 2), (22, 12, 8, 4, 1), (23, 6, 10, 2, 3), (24, 0, 12, 4, 2)])
+def test_search_bruteforce_quarter_pel(seed, by0, bx0, bs, win):
+    # noisy planes: ties and near-ties are common, so every branch of the rule runs
+    R = _plane(seed, 16, 16, -9, 9)
+    P = _plane(seed + 100, 16, 16, -9, 9)
+    want, _ = _search_by_definition(P, R, by0, bx0, bs, win)
+    assert oracle.mc_search(P, R, by0, bx0, bs, win=win) == want
+    want0, _ = _search_by_definition(P, R, by0, bx0, bs, win, zero_phase=True)
+    assert oracle.mc_search(P, R, by0, bx0, bs, win=win, zero_phase=True) == want0
+
+
+@pytest.mark.parametrize("mx,my,sign", [(5, -3, 1), (-6, 7, -1), (2, 2, 1), (-1, -7, -1), (7, 1, 1)])
+def test_search_global_quarter_pel_optimum(mx, my, sign):
+    # A smooth reference and a block that is its phase-signed quarter-pel shift:
+    # the global minimum over every quarter-pel position of the window is 0 at
+    # the true shift, and the search reaches it.
+    rng = np.random.default_rng(30 + mx)
+    R = np.cumsum(np.cumsum(rng.integers(-2, 3, size=(24, 24)), 0), 1).astype(np.int32) * 3
+    by0, bx0, bs, win = 8, 8, 4, 2
+    P = np.zeros_like(R)
+    P[by0:by0 + bs, bx0:bx0 + bs] = sign * _qpel_all(R, by0, bx0, bs, mx, my)
+    want, global_min = _search_by_definition(P, R, by0, bx0, bs, win)
+    assert global_min == 0 and want[0] == 0 and want[3] == sign
+    got = oracle.mc_search(P, R, by0, bx0, bs, win=win)
+    assert got == want
+    assert np.array_equal(got[3] * _qpel_all(R, by0, bx0, bs, got[1], got[2]), P[by0:by0 + bs, bx0:bx0 + bs])
