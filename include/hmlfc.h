@@ -23,8 +23,8 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *    Every call that takes a stream only enqueues work on it; outputs are
  *    ready when the stream is synchronised.  The exceptions say so: loading
- *    (lf_load_compressed, lf_load_compressed_ex) and the device-assisted
- *    encoder (lf_encode_device) wait for their work before returning.
+ *    (lf_load_compressed, lf_load_compressed_ex) and the encoder
+ *    (lf_encode_device) wait for their work before returning.
  *    Argument checks happen on the host before anything is enqueued.
  *  - Return value: LF_OK, or a negative lf_status; lf_last_error() gives a
  *    thread-local message for the last failure.
@@ -79,6 +79,10 @@ typedef struct {
     int64_t payload_bytes;   /* block payload section size                    */
     int64_t ref_bytes;       /* device bytes of the resident reference SRVs   */
     int32_t sparse_refs;     /* 1: loaded with LF_LOAD_SPARSE_REFS            */
+    int64_t clamped_coords;  /* decode requests (lf_decode_pixels, _lod) with
+                                a coordinate outside the grid, clamped to it,
+                                since load (Random Access for Interactive
+                                Rendering: requests are grid positions)       */
 } lf_info;
 
 /* Load flag: keep the reference SRVs block-sparse (only significant blocks,
@@ -127,6 +131,9 @@ lf_status lf_load_compressed_ex(const void* host_stream, size_t nbytes, int32_t 
 /* Release the host-side handle (the arena stays the caller's). */
 lf_status lf_free(lf_handle* h);
 
+/* Fills *out.  Reads the clamp counter with a synchronous copy on the null
+ * stream: decode calls still running on other streams may not be counted
+ * yet (synchronise their stream first).  Errors: LF_EINVAL, LF_EDEVICE. */
 lf_status lf_get_info(const lf_handle* h, lf_info* out);
 
 /* ---------------------------------------------------------------------- */
@@ -137,8 +144,10 @@ lf_status lf_get_info(const lf_handle* h, lf_info* out);
 /* transform.                                                              */
 /* ---------------------------------------------------------------------- */
 
-/* d_coords: device int32 [n][4] = (b, a, y, x); coordinates outside the
- * grid are clamped to it.  d_rgb: device uint8 [n][3].  n = 0 is a no-op. */
+/* d_coords: device int32 [n][4] = (b, a, y, x), 16-byte aligned (else
+ * LF_EINVAL); coordinates outside the grid are clamped to it, and each
+ * clamped request adds one to lf_info.clamped_coords.  d_rgb: device uint8
+ * [n][3].  n = 0 is a no-op. */
 lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t n, uint8_t* d_rgb, void* stream);
 
 /* Progressive decoding (claimed in the Introduction's contributions and the
@@ -147,8 +156,8 @@ lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t 
  * images (the root RKV plus the SRVs of levels level .. H-1).  level = 0 is
  * lf_decode_pixels; level = H is the root RKV alone.  d_coords: device int32
  * [n][4] = (B, A, y, x) with (B, A) a node of that level (0 <= B <
- * ceil(nb / 2^level), likewise A); coordinates outside are clamped.  Must be
- * 16-byte aligned.  d_rgb: device uint8 [n][3].  LF_EINVAL for level outside
+ * ceil(nb / 2^level), likewise A); coordinates outside are clamped (and
+ * counted in lf_info.clamped_coords).  Must be 16-byte aligned.  d_rgb: device uint8 [n][3].  LF_EINVAL for level outside
  * 0 .. H. */
 lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, const int32_t* d_coords, int64_t n,
                                uint8_t* d_rgb, void* stream);
@@ -233,7 +242,9 @@ lf_status lf_export_params(const lf_handle* h, float* d_residual, float* d_shift
 lf_status lf_render_relaxed(const lf_handle* h, const float* d_residual, const float* d_shift, const float* d_cams,
                             int32_t n_views, int32_t width, int32_t height, float* d_out, void* stream);
 
-/* Device workspace bytes lf_render_backward needs for this view batch. */
+/* Device workspace bytes lf_render_backward needs for this view batch.
+ * Host-only.  LF_EINVAL for batches above 2^27 - 1 rays (n_views * width *
+ * height; each ray contributes 16 pairs to a sort whose count is an int). */
 lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, int32_t width, int32_t height, int64_t* bytes);
 
 /* Adjoint of lf_render_relaxed: given d_grad_out = dL/d(out) (same layout
@@ -304,50 +315,59 @@ lf_status lf_serve_baseline(lf_handle* const* fields, int32_t n_fields, int64_t 
                             int64_t out_bytes, double* latency_ms, double* makespan_s);
 
 /* ---------------------------------------------------------------------- */
-/* Encoding (host, OpenMP; not on the render path).  Follows the paper's   */
-/* pipeline: reversible YCoCg, RLFC hierarchy of 2x2-cluster rounded-mean  */
-/* RKVs, top-down closed loop with phase-shifted quarter-pel motion        */
-/* compensation of the non-reference SRVs of every cluster (Eq. 1-2),      */
-/* uniform quantisation with the two block thresholds, and bounded-integer */
-/* sequence coding in breadth-first node order.                            */
+/* Encoding on the GPU (not on the render path).  Follows the paper's      */
+/* pipeline (Fig. 1): reversible YCoCg, the RLFC hierarchy of 2x2-cluster  */
+/* rounded-mean RKVs, a top-down closed loop with phase-shifted quarter-pel */
+/* motion compensation of the non-reference SRVs of every cluster (Eq.     */
+/* 1-2), uniform quantisation with the two block thresholds (Compressing   */
+/* HMLFC tree), and bounded-integer-sequence coding in breadth-first node  */
+/* order (Compressed Stream Structure).                                    */
 /* ---------------------------------------------------------------------- */
 
 typedef struct {
     int32_t levels;      /* tree height H (1..8)                                   */
-    int32_t block;       /* block size Bs (1..64, divides width and height)        */
-    int32_t step[8];     /* quantisation step per level (1 = lossless)             */
+    int32_t block;       /* block size Bs (1..64, a power of two dividing width
+                            and height; at least 2 unless no_mc)                   */
+    int32_t step[8];     /* quantisation step per level (1..4096; 1 = lossless)    */
     int32_t t_ref[8];    /* block threshold for reference SRVs                     */
     int32_t t_pred[8];   /* block threshold for motion-compensated residuals       */
-    int32_t win[8];      /* search window W per level, whole pixels                */
+    int32_t win[8];      /* search window W per level, whole pixels (0..255,
+                            block + 2W + 1 <= 96 unless no_mc)                     */
     int32_t subpel;      /* 1: quarter-pel refinement around the integer best      */
     int32_t zero_phase;  /* 1: allow "no prediction" when it is strictly cheaper   */
     int32_t no_mc;       /* 1: no motion compensation (plain hierarchy)            */
 } lf_encode_params;
 
-/* host_lf: host uint8 [nb][na][height][width][3] RGB.  On success
- * *out_stream is a malloc'ed stream of *out_bytes bytes, released with
- * lf_encode_free.  threads <= 0 uses the OpenMP default.  With the
- * environment variable HMLFC_ENCODE_PROGRESS=1 it prints a line on stderr
- * after every tenth of each level's predictive blocks.  Errors: LF_EINVAL
- * (geometry, parameters, or values outside the stream's integer ranges). */
-lf_status lf_encode(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
-                    const lf_encode_params* params, int32_t threads, uint8_t** out_stream, size_t* out_bytes);
-void lf_encode_free(uint8_t* stream);
-
-/* The same encoder with the phase-shifted motion search (its costly step)
- * on the GPU: per level, the SRV planes and the reconstructed reference
- * planes are uploaded to d_work and every predictive block is searched by
- * lf_mc_search; quantisation, thresholds and packing stay on the host.
- * The stream is byte-identical to lf_encode's.  d_work: caller-owned device
- * workspace of at least lf_encode_workspace_bytes bytes.  Synchronous: the
- * call waits for its work on `stream` before returning.  Extra errors:
- * LF_EINVAL for block sizes other than 2..64 in powers of two and windows
- * with block + 2W + 1 > 96; LF_ENOMEM for a short workspace; LF_EDEVICE. */
+/* Device workspace lf_encode_device needs, in bytes: 256-byte aligned
+ * sections for the uploaded light field (3 bytes per sample), the int16
+ * YCoCg planes of every tree level (2 bytes per sample and channel, levels
+ * 0..H), the coded SRV planes of level 0, the quantised values of every
+ * block (2 bytes per value), per-block extremes, word counts, payload
+ * offsets and table entries (28 bytes per block), the motion records (16
+ * bytes each), the level-0 search items (12 bytes each), a payload bound of
+ * 16 bits per value, and the motion-vector section.  LF_EINVAL for
+ * parameters lf_encode_device rejects. */
 lf_status lf_encode_workspace_bytes(int32_t nb, int32_t na, int32_t height, int32_t width,
                                     const lf_encode_params* params, int64_t* bytes);
+
+/* host_lf: host uint8 [nb][na][height][width][3] RGB.  Every stage runs on
+ * the GPU in d_work (caller-owned, 256-byte aligned, at least
+ * lf_encode_workspace_bytes bytes; its contents are scratch): colour
+ * transform, hierarchy, per level the SRVs, the reference blocks, the
+ * motion search of every predictive block (lf_mc_search's kernel and
+ * decisions), the predictive residuals and the reconstruction, then the
+ * block modes, payload offsets (device prefix sum), table, payload and
+ * motion-vector packing.  On success *out_stream is a malloc'ed stream of
+ * *out_bytes bytes (header written on the host, sections copied back),
+ * released with lf_encode_free.  Synchronous: waits for its work on
+ * `stream`.  Errors: LF_EINVAL (geometry, parameters, or a quantised value,
+ * coded SRV or reconstruction outside int16, which 8-bit input never
+ * produces), LF_ENOMEM (workspace too small, or no host memory for the
+ * stream), LF_EDEVICE. */
 lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_t na, int32_t height, int32_t width,
-                           const lf_encode_params* params, int32_t threads, void* d_work, int64_t work_bytes,
-                           void* stream, uint8_t** out_stream, size_t* out_bytes);
+                           const lf_encode_params* params, void* d_work, int64_t work_bytes, void* stream,
+                           uint8_t** out_stream, size_t* out_bytes);
+void lf_encode_free(uint8_t* stream);
 
 /* Phase-shifted motion search (Phase-shifted Motion Compensation, Eq. 1 and
  * 2) of n blocks on the GPU.  d_pred: device int16 [n_pred][height][width]

@@ -152,6 +152,24 @@ def _shift_sample(tex: np.ndarray, margin: int, h: int, w: int, sx: float, sy: f
     return top + fy * (bot - top)
 
 
+def _shift_window(tex: np.ndarray, margin: int, bx0: int, by0: int, ww: int, hh: int, sx: float,
+                  sy: float) -> np.ndarray:
+    """Rows by0 .. by0 + hh - 1, columns bx0 .. bx0 + ww - 1 of ``_shift_sample`` (same arithmetic per pixel)."""
+    fx0 = np.floor(-sx)
+    fy0 = np.floor(-sy)
+    fx = np.float32(-sx - fx0)
+    fy = np.float32(-sy - fy0)
+    x0 = margin + int(fx0) + bx0
+    y0 = margin + int(fy0) + by0
+    t00 = tex[y0:y0 + hh, x0:x0 + ww]
+    t01 = tex[y0:y0 + hh, x0 + 1:x0 + 1 + ww]
+    t10 = tex[y0 + 1:y0 + 1 + hh, x0:x0 + ww]
+    t11 = tex[y0 + 1:y0 + 1 + hh, x0 + 1:x0 + 1 + ww]
+    top = t00 + fx * (t01 - t00)
+    bot = t10 + fx * (t11 - t10)
+    return top + fy * (bot - top)
+
+
 def _gather_sample(tex: np.ndarray, margin: int, srcx: np.ndarray, srcy: np.ndarray) -> np.ndarray:
     th, tw = tex.shape[:2]
     X = np.clip(srcx + margin, 0, tw - 1.001)
@@ -180,22 +198,29 @@ def render_view(scene: dict, b: int, a: int, h: int, w: int) -> np.ndarray:
         img = _gather_sample(bg["tex"], m, xs - d * ox, ys - d * oy)
     else:
         img = _shift_sample(bg["tex"], m, h, w, bg["d"] * ox, bg["d"] * oy)
-    xs = np.arange(w, dtype=np.float64)[None, :]
-    ys = np.arange(h, dtype=np.float64)[:, None]
     for L in scene["layers"]:
         sx, sy = L["d"] * ox, L["d"] * oy
+        # pixels outside the layer's bounding box (one pixel of slack) are not
+        # covered; inside it the mask and samples are evaluated per pixel
         if L["kind"] == "rect":
-            x0, y0, x1, y1 = L["geom"]
-            mx = ((xs - sx) >= x0) & ((xs - sx) < x1)
-            my = ((ys - sy) >= y0) & ((ys - sy) < y1)
-            mask = mx & my
+            gx0, gy0, gx1, gy1 = L["geom"]
         else:
             cx, cy, r = L["geom"]
+            gx0, gy0, gx1, gy1 = cx - r, cy - r, cx + r, cy + r
+        bx0, bx1 = max(0, int(np.floor(gx0 + sx)) - 1), min(w, int(np.ceil(gx1 + sx)) + 2)
+        by0, by1 = max(0, int(np.floor(gy0 + sy)) - 1), min(h, int(np.ceil(gy1 + sy)) + 2)
+        if bx0 >= bx1 or by0 >= by1:
+            continue
+        xs = np.arange(bx0, bx1, dtype=np.float64)[None, :]
+        ys = np.arange(by0, by1, dtype=np.float64)[:, None]
+        if L["kind"] == "rect":
+            mask = (((xs - sx) >= gx0) & ((xs - sx) < gx1)) & (((ys - sy) >= gy0) & ((ys - sy) < gy1))
+        else:
             mask = ((xs - sx - cx) ** 2 + (ys - sy - cy) ** 2) < r * r
         if not mask.any():
             continue
-        layer_img = _shift_sample(L["tex"], m, h, w, sx, sy)
-        np.copyto(img, layer_img, where=mask[..., None])
+        layer_img = _shift_window(L["tex"], m, bx0, by0, bx1 - bx0, by1 - by0, sx, sy)
+        np.copyto(img[by0:by1, bx0:bx1], layer_img, where=mask[..., None])
     return img
 
 

@@ -56,6 +56,7 @@ def lib():
             "orc_bise_unpack": (None, [P, C.c_int, C.c_int, P]),
             "orc_encode": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, P, C.c_int, P, P]),
             "orc_free": (None, [P]),
+            "orc_set_threads": (C.c_int, [C.c_int]),
             "orc_open": (C.c_int, [P, C.c_size_t, P]),
             "orc_close": (None, [P]),
             "orc_info": (None, [P, P]),
@@ -113,6 +114,11 @@ def _params(enc: dict) -> _Params:
 
 
 # ---------------------------------------------------------------- pieces
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's OpenMP loops from now on (n <= 0: all); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
+
 
 def ycocg_fwd(rgb: np.ndarray) -> np.ndarray:
     rgb = np.ascontiguousarray(rgb, dtype=np.int32).reshape(-1, 3)

@@ -97,6 +97,9 @@ int orc_decode_full_ycocg(const orc_lf* lf, int32_t* out);     /* [3][nb][na][h]
 /* per-level decoded SRV planes S_hat: [3][n_nodes][h][w] (BFS node order) */
 int orc_decode_srv(const orc_lf* lf, int32_t* out);
 
+/* ---- threads of the OpenMP loops (n <= 0: all processors); returns the count in effect ---- */
+int orc_set_threads(int n);
+
 /* ---- renderer ---- */
 int orc_ray_coords(const float* cam, int wo, int ho, int i, int j, float* uvst4);
 int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int nthreads, double* out);

@@ -13,6 +13,7 @@
  * binary64.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -90,6 +91,14 @@ static double blend16(const double s[2][2][2][2], const footprint* fp)
     double r0 = lerp(view[0][0], view[0][1], fp->fu);
     double r1 = lerp(view[1][0], view[1][1], fp->fu);
     return lerp(r0, r1, fp->fv);
+}
+
+/* Threads of every OpenMP loop that follows (n <= 0: one per processor);
+ * returns the count now in effect.  For timing the oracle on n cores. */
+int orc_set_threads(int n)
+{
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+    return omp_get_max_threads();
 }
 
 int orc_render(const orc_lf* lf, const float* cams, int nv, int wo, int ho, int nthreads, double* out)

@@ -262,7 +262,9 @@ static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayou
     const LfGeom& g = h->L.g;
     B->n_pairs = (int64_t)nv * wo * ho * 16;
     B->n_samples = (int64_t)g.na * g.nb * g.w * g.h;
-    if (B->n_pairs > 0xFFFFFFFFll || B->n_samples > 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many rays or samples");
+    // the pair sort takes an int count: at most 2^31 - 1 pairs (134,217,727 rays per call)
+    if (B->n_pairs > 0x7FFFFFFFll) return lf_fail(LF_EINVAL, "too many rays for one backward call (at most 2^27 - 1)");
+    if (B->n_samples > 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many light-field samples");
     int eb = 1;
     while (eb < 32 && ((int64_t)1 << eb) < B->n_samples) eb++;
     B->end_bit = eb;

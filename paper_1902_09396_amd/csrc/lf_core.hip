@@ -56,6 +56,12 @@ static int64_t bise_bits_host(int mode, int64_t n)
 
 static int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 
+// Largest dequantised residual magnitude a block's mode may hold.  With at
+// most 8 levels, a root value (int16) and reference taps of at most
+// LF_REF_LIMIT, every int32 sum of the decoders stays far from overflow.
+// A stream of 8-bit content has residuals of a few thousand at most.
+#define LF_RES_LIMIT (1 << 24)
+
 lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
 {
     memset(L, 0, sizeof *L);
@@ -132,17 +138,31 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
         (L->mv_bytes & 3) || L->payload_bytes < 8 || L->mv_bytes < 8)
         return lf_fail(LF_EFORMAT, "misaligned section");
     const int64_t pwords = (int64_t)(L->payload_bytes / 4), mwords = (int64_t)(L->mv_bytes / 4);
-    // block payloads: every 64-bit read window must stay inside the payload section
+    // block payloads: every 64-bit read window must stay inside the payload
+    // section, and every value the mode can hold, (min + v) * step, must
+    // stay within LF_RES_LIMIT so that the decoders' int32 sums cannot wrap
     const uint8_t* tab = s + L->table_off;
-    const int64_t nent = 3 * nodes * g.nblk;
-    for (int64_t e = 0; e < nent; e++) {
-        const uint8_t* t = tab + 8 * e;
-        int mode = t[6];
-        if (mode == LF_MODE_ZERO) continue;
-        if ((mode >> 5) > 2 || (mode & 31) > 20) return lf_fail(LF_EFORMAT, "bad block mode at entry %lld", (long long)e);
-        int64_t words = (bise_bits_host(mode, (int64_t)g.bs * g.bs) + 31) / 32;
-        if ((int64_t)rd32(t) + words + 1 > pwords) return lf_fail(LF_EFORMAT, "block payload out of range");
-    }
+    for (int c = 0; c < 3; c++)
+        for (int l = g.H - 1; l >= 0; l--) {
+            const int64_t first = ((int64_t)c * nodes + g.node_base[l]) * g.nblk;
+            const int64_t count = (int64_t)g.na_l[l] * g.nb_l[l] * g.nblk;
+            for (int64_t e = first; e < first + count; e++) {
+                const uint8_t* t = tab + 8 * e;
+                const int mode = t[6];
+                if (mode == LF_MODE_ZERO) continue;
+                if ((mode >> 5) > 2 || (mode & 31) > 20)
+                    return lf_fail(LF_EFORMAT, "bad block mode at entry %lld", (long long)e);
+                const int64_t words = (bise_bits_host(mode, (int64_t)g.bs * g.bs) + 31) / 32;
+                if ((int64_t)rd32(t) + words + 1 > pwords) return lf_fail(LF_EFORMAT, "block payload out of range");
+                int16_t mn;
+                memcpy(&mn, t + 4, 2);
+                const int64_t cap = (int64_t)(2 * (mode >> 5) + 1) << (mode & 31);  // values 0 .. cap - 1
+                const int64_t lo = (int64_t)mn * g.step[l], hi = ((int64_t)mn + cap - 1) * g.step[l];
+                if (std::max(std::llabs(lo), std::llabs(hi)) > LF_RES_LIMIT)
+                    return lf_fail(LF_EFORMAT, "block residual range beyond %d at entry %lld", LF_RES_LIMIT,
+                                   (long long)e);
+            }
+        }
     int64_t rec = 0;
     for (int c = 0; c < 3; c++)
         for (int l = g.H - 1; l >= 0; l--) {
@@ -252,6 +272,11 @@ extern "C" lf_status lf_query_arena(const void* host_stream, size_t nbytes, int6
 // 16-weighted prediction sums of them in 16-bit lanes.  SRVs of 8-bit
 // content stay near +-520; a larger value flags the stream as malformed.
 #define LF_REF_LIMIT 2047
+#define LF_SAMPLE_LIMIT 8191
+// load status bits
+#define LF_ST_REF 1     // a reference SRV beyond LF_REF_LIMIT
+#define LF_ST_MV 2      // a motion vector beyond 12 signed bits
+#define LF_ST_SAMPLE 4  // a decoded sample channel beyond LF_SAMPLE_LIMIT
 
 __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int* __restrict__ status)
 {
@@ -274,7 +299,7 @@ __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int*
         bad |= v < -LF_REF_LIMIT || v > LF_REF_LIMIT;
         refs[t] = (int16_t)v;
     }
-    if (bad) atomicOr(status, 1);
+    if (bad) atomicOr(status, LF_ST_REF);
 }
 
 // Sparse residency: the tile of every significant reference block.
@@ -300,13 +325,17 @@ __global__ void k_load_tiles(LfGeom g, LfPtrs p, int16_t* __restrict__ tiles, in
         bad |= v < -LF_REF_LIMIT || v > LF_REF_LIMIT;
         tiles[(int64_t)tile * n + i] = (int16_t)v;
     }
-    if (bad) atomicOr(status, 1);
+    if (bad) atomicOr(status, LF_ST_REF);
 }
 
-// Block descriptors of every (channel, node, block), BFS node order.
-__global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc)
+// Block descriptors of every (channel, node, block), BFS node order.  A
+// descriptor holds each vector component in 12 signed bits: a motion vector
+// beyond +-2047 quarter pixels (a stream can code one when 4W + 2047 is
+// below its sequence's range) is flagged.
+__global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc, int* __restrict__ status)
 {
     const int64_t total = 3 * (int64_t)g.n_nodes * g.nblk;
+    bool bad = false;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int blk = (int)(t % g.nblk);
         const int node = (int)((t / g.nblk) % g.n_nodes);
@@ -314,8 +343,38 @@ __global__ void k_load_desc(LfGeom g, LfPtrs p, uint4* __restrict__ desc)
         int l = 0;
         while (l + 1 < g.H && node < g.node_base[l]) l++;  // levels are stored H-1 first
         const int local = node - g.node_base[l];
-        desc[t] = lf_make_desc(g, p, c, l, local / g.na_l[l], local % g.na_l[l], blk);
+        const int B = local / g.na_l[l], A = local % g.na_l[l];
+        desc[t] = lf_make_desc(g, p, c, l, B, A, blk);
+        if ((A | B) & 1) {
+            int mx, my, sg;
+            lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
+            bad |= mx < -2047 || mx > 2047 || my < -2047 || my > 2047;
+        }
     }
+    if (bad) atomicOr(status, LF_ST_MV);
+}
+
+// Every decoded sample's Y, Co and Cg must lie within +-LF_SAMPLE_LIMIT:
+// the tile renderer adds a sample's SRVs in 16-bit lanes, which is exact
+// modulo 2^16, and its colour inverse (two halvings, sums of at most three
+// terms) stays inside int16 from such values, so its result then equals the
+// int32 decode.  Decoded values of 8-bit content are within 255 + step / 2
+// of the source.  One thread per sample of every leaf view, all channels.
+__global__ void k_load_check(LfGeom g, LfPtrs p, int* __restrict__ status)
+{
+    const int64_t plane = (int64_t)g.w * g.h;
+    const int64_t total = (int64_t)g.na * g.nb * plane;
+    bool bad = false;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t view = t / plane, px = t - view * plane;
+        const int b = (int)(view / g.na), a = (int)(view - (int64_t)b * g.na);
+        const int y = (int)(px / g.w), x = (int)(px - (int64_t)y * g.w);
+        for (int c = 0; c < 3; c++) {
+            const int v = lf_decode_channel<false>(g, p, c, b, a, y, x);
+            bad |= v < -LF_SAMPLE_LIMIT || v > LF_SAMPLE_LIMIT;
+        }
+    }
+    if (bad) atomicOr(status, LF_ST_SAMPLE);
 }
 
 extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbytes, int32_t flags, void* d_arena,
@@ -388,7 +447,12 @@ extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbyte
     if (!L.sparse) {
         const int64_t nd = 3 * (int64_t)L.g.n_nodes * L.g.nblk;
         const int64_t dblocks = std::min<int64_t>((nd + 255) / 256, 65536);
-        hipLaunchKernelGGL(k_load_desc, dim3((unsigned)dblocks), dim3(256), 0, s, L.g, h->p, (uint4*)(A + L.a_desc));
+        hipLaunchKernelGGL(k_load_desc, dim3((unsigned)dblocks), dim3(256), 0, s, L.g, h->p, (uint4*)(A + L.a_desc),
+                           status);
+        // the range check reads reference planes: only meaningful when they are in range
+        const int64_t ns = (int64_t)L.g.na * L.g.nb * L.g.w * L.g.h;
+        const int64_t cblocks = std::min<int64_t>((ns + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_load_check, dim3((unsigned)cblocks), dim3(256), 0, s, L.g, h->p, status);
         st = lf_check_launch("load_desc");
         if (st != LF_OK) {
             delete h;
@@ -404,7 +468,9 @@ extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbyte
     }
     if (flag) {
         delete h;
-        return lf_fail(LF_EFORMAT, "reference residual magnitude above %d", LF_REF_LIMIT);
+        if (flag & LF_ST_REF) return lf_fail(LF_EFORMAT, "reference residual magnitude above %d", LF_REF_LIMIT);
+        if (flag & LF_ST_MV) return lf_fail(LF_EFORMAT, "motion vector beyond +-2047 quarter pixels");
+        return lf_fail(LF_EFORMAT, "decoded sample channel value beyond +-%d", LF_SAMPLE_LIMIT);
     }
     *out = h;
     return LF_OK;
@@ -420,6 +486,13 @@ extern "C" lf_status lf_free(lf_handle* h)
 {
     delete h;
     return LF_OK;
+}
+
+// Requested coordinates outside the grid are clamped and counted: one
+// 64-bit counter at byte 8 of the status section, cleared at load.
+static unsigned long long* lf_clamp_counter(const lf_handle* h)
+{
+    return reinterpret_cast<unsigned long long*>(h->arena + h->L.a_status + 8);
 }
 
 extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
@@ -442,6 +515,10 @@ extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
     o->payload_bytes = (int64_t)h->L.payload_bytes;
     o->sparse_refs = h->L.sparse;
     o->ref_bytes = h->L.sparse ? h->L.a_status - h->L.a_refs : h->L.a_desc - h->L.a_refs;
+    unsigned long long clamps = 0;
+    if (hipMemcpy(&clamps, lf_clamp_counter(h), sizeof clamps, hipMemcpyDeviceToHost) != hipSuccess)
+        return lf_fail(LF_EDEVICE, "reading the clamp counter failed");
+    o->clamped_coords = (int64_t)clamps;
     return LF_OK;
 }
 
@@ -449,15 +526,23 @@ extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
 // random-access sample decoding
 // ---------------------------------------------------------------------------
 
+// each wave adds its clamped lanes to the counter with one atomic
+__device__ __forceinline__ void lf_count_clamps(unsigned long long* counter, bool clamped)
+{
+    const unsigned long long m = __ballot(clamped);
+    if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1)) atomicAdd(counter, (unsigned long long)__popcll(m));
+}
+
 template <bool SPARSE>
 __global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ coords, int64_t n,
-                                uint8_t* __restrict__ rgb)
+                                uint8_t* __restrict__ rgb, unsigned long long* __restrict__ clamps)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int4 q = reinterpret_cast<const int4*>(coords)[k];
     int b = lf_clampi(q.x, 0, g.nb - 1), a = lf_clampi(q.y, 0, g.na - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
+    lf_count_clamps(clamps, b != q.x || a != q.y || y != q.z || x != q.w);
     int Y = lf_decode_channel<SPARSE>(g, p, 0, b, a, y, x);
     int Co = lf_decode_channel<SPARSE>(g, p, 1, b, a, y, x);
     int Cg = lf_decode_channel<SPARSE>(g, p, 2, b, a, y, x);
@@ -478,20 +563,21 @@ extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coord
     int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
     hipLaunchKernelGGL(h->p.slots ? k_decode_pixels<true> : k_decode_pixels<false>, dim3((unsigned)blocks), dim3(256),
-                       0, (hipStream_t)stream, h->L.g, h->p, d_coords, n, d_rgb);
+                       0, (hipStream_t)stream, h->L.g, h->p, d_coords, n, d_rgb, lf_clamp_counter(h));
     return lf_check_launch("decode_pixels");
 }
 
 // Progressive decode: samples of the level-`lod` node images.
 template <bool SPARSE>
 __global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __restrict__ coords, int64_t n,
-                               uint8_t* __restrict__ rgb)
+                               uint8_t* __restrict__ rgb, unsigned long long* __restrict__ clamps)
 {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     int4 q = reinterpret_cast<const int4*>(coords)[k];
     int B = lf_clampi(q.x, 0, g.nb_l[lod] - 1), A = lf_clampi(q.y, 0, g.na_l[lod] - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
+    lf_count_clamps(clamps, B != q.x || A != q.y || y != q.z || x != q.w);
     int Y = lf_decode_channel<SPARSE>(g, p, 0, B << lod, A << lod, y, x, lod);
     int Co = lf_decode_channel<SPARSE>(g, p, 1, B << lod, A << lod, y, x, lod);
     int Cg = lf_decode_channel<SPARSE>(g, p, 2, B << lod, A << lod, y, x, lod);
@@ -512,7 +598,7 @@ extern "C" lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, con
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
     hipLaunchKernelGGL(h->p.slots ? k_decode_nodes<true> : k_decode_nodes<false>, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, h->L.g, h->p, (int)level, d_coords, n, d_rgb);
+                       (hipStream_t)stream, h->L.g, h->p, (int)level, d_coords, n, d_rgb, lf_clamp_counter(h));
     return lf_check_launch("decode_pixels_lod");
 }
 

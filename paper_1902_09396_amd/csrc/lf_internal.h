@@ -30,11 +30,8 @@ lf_status lf_fail(lf_status s, const char* fmt, ...);
 lf_status lf_check_launch(const char* what);
 lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L);
 
-// Device motion search for the encoder (lf_search.hip): uploads one level's
-// SRV planes S and reconstructed planes Shat (n_planes each, [plane][h][w]),
-// searches every item (pred plane, ref plane, block) and copies the results
-// (mx, my, sigma, cost) to the host buffer out; synchronous on stream.
-int64_t lf_search_work_bytes(int64_t n_planes, int w, int h, int64_t n_items);
-lf_status lf_search_level_device(const int16_t* S, const int16_t* Shat, int64_t n_planes, int w, int h, int bs,
-                                 int win, int subpel, int zero_phase, const int32_t* items, int64_t n_items,
-                                 int32_t* out, void* d_work, int64_t work_bytes, void* stream);
+// Phase-shifted motion search (lf_search.hip) on device planes, for the
+// device encoder: checks the sizes, enqueues k_mc_search on `stream`.
+lf_status lf_search_launch(const int16_t* pred, const int16_t* ref, int64_t n_pred, int64_t n_ref, int w, int h,
+                           int bs, int win, int subpel, int zero_phase, const int32_t* items, int64_t n, int32_t* out,
+                           void* stream);

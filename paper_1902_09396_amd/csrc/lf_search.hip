@@ -308,8 +308,6 @@ lf_status launch_any(const int16_t* pred, const int16_t* ref, int64_t n_pred, in
     return lf_check_launch("mc_search");
 }
 
-inline int64_t align256(int64_t v) { return (v + 255) & ~(int64_t)255; }
-
 }  // namespace
 
 extern "C" lf_status lf_mc_search(const int16_t* d_pred, int64_t n_pred, const int16_t* d_ref, int64_t n_ref,
@@ -325,36 +323,12 @@ extern "C" lf_status lf_mc_search(const int16_t* d_pred, int64_t n_pred, const i
                       n, d_out, (hipStream_t)stream);
 }
 
-int64_t lf_search_work_bytes(int64_t n_planes, int w, int h, int64_t n_items)
+lf_status lf_search_launch(const int16_t* pred, const int16_t* ref, int64_t n_pred, int64_t n_ref, int w, int h,
+                           int bs, int win, int subpel, int zero_phase, const int32_t* items, int64_t n, int32_t* out,
+                           void* stream)
 {
-    const int64_t planes = align256(n_planes * (int64_t)w * h * 2);
-    return 2 * planes + align256(n_items * 12) + align256(n_items * 16);
-}
-
-lf_status lf_search_level_device(const int16_t* S, const int16_t* Shat, int64_t n_planes, int w, int h, int bs,
-                                 int win, int subpel, int zero_phase, const int32_t* items, int64_t n_items,
-                                 int32_t* out, void* d_work, int64_t work_bytes, void* stream)
-{
-    lf_status st = search_args(w, h, bs, win, n_items);
-    if (st != LF_OK) return st;
-    if (n_items == 0) return LF_OK;
-    if (lf_search_work_bytes(n_planes, w, h, n_items) > work_bytes) return lf_fail(LF_ENOMEM, "workspace too small");
-    const int64_t pb = align256(n_planes * (int64_t)w * h * 2);
-    uint8_t* base = (uint8_t*)d_work;
-    int16_t* dS = (int16_t*)base;
-    int16_t* dR = (int16_t*)(base + pb);
-    int32_t* dI = (int32_t*)(base + 2 * pb);
-    int32_t* dO = (int32_t*)(base + 2 * pb + align256(n_items * 12));
-    hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = (size_t)(n_planes * (int64_t)w * h * 2);
-    if (hipMemcpyAsync(dS, S, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(dR, Shat, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(dI, items, (size_t)n_items * 12, hipMemcpyHostToDevice, s) != hipSuccess)
-        return lf_fail(LF_EDEVICE, "upload failed");
-    st = launch_any(dS, dR, n_planes, n_planes, w, h, bs, win, subpel, zero_phase, dI, n_items, dO, s);
-    if (st != LF_OK) return st;
-    if (hipMemcpyAsync(out, dO, (size_t)n_items * 16, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return lf_fail(LF_EDEVICE, "search failed");
-    return LF_OK;
+    lf_status st = search_args(w, h, bs, win, n);
+    if (st != LF_OK || n == 0) return st;
+    return launch_any(pred, ref, n_pred, n_ref, w, h, bs, win, subpel != 0, zero_phase != 0, items, n, out,
+                      (hipStream_t)stream);
 }

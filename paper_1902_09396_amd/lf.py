@@ -32,7 +32,7 @@ class LfInfo(C.Structure):
                 ("levels", C.c_int32), ("block", C.c_int32), ("root_na", C.c_int32), ("root_nb", C.c_int32),
                 ("n_nodes", C.c_int64), ("n_pred_records", C.c_int64), ("n_refs", C.c_int64),
                 ("arena_bytes", C.c_int64), ("stream_bytes", C.c_int64), ("payload_bytes", C.c_int64),
-                ("ref_bytes", C.c_int64), ("sparse_refs", C.c_int32)]
+                ("ref_bytes", C.c_int64), ("sparse_refs", C.c_int32), ("clamped_coords", C.c_int64)]
 
 
 _lib = None
@@ -58,10 +58,9 @@ SIGNATURES = {
     "lf_render_relaxed": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_backward_workspace": (C.c_int, [_P, _I32, _I32, _I32, _P]),
     "lf_render_backward": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P, _P, _P, _I64, _P]),
-    "lf_encode": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _P]),
     "lf_encode_free": (None, [_P]),
     "lf_encode_workspace_bytes": (C.c_int, [_I32, _I32, _I32, _I32, _P, _P]),
-    "lf_encode_device": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _I32, _P, _I64, _P, _P, _P]),
+    "lf_encode_device": (C.c_int, [_P, _I32, _I32, _I32, _I32, _P, _P, _I64, _P, _P, _P]),
     "lf_mc_search": (C.c_int, [_P, _I64, _P, _I64, _I32, _I32, _I32, _I32, _I32, _I32, _P, _I64, _P, _P]),
     "lf_last_error": (C.c_char_p, []),
 }
@@ -136,6 +135,13 @@ class LightField:
         self.na, self.nb = info.na, info.nb
         self.width, self.height = info.width, info.height
         self.levels, self.block = info.levels, info.block
+
+    def clamped_coords(self) -> int:
+        """Decode requests clamped to the grid since load (after this device's current stream finishes)."""
+        torch.cuda.current_stream(self.device).synchronize()
+        info = LfInfo()
+        check(lib().lf_get_info(self._h, C.byref(info)))
+        return int(info.clamped_coords)
 
     @property
     def handle(self):
@@ -260,25 +266,19 @@ class EncodeParams(C.Structure):
                 ("no_mc", C.c_int32)]
 
 
-def encode(light_field: np.ndarray, enc: dict, threads: int = 0, device: bool = False) -> np.ndarray:
-    """Encode a uint8 [nb][na][h][w][3] light field; returns the stream bytes.
-
-    device=True runs the motion search on the current GPU (same stream bytes)."""
+def encode(light_field: np.ndarray, enc: dict) -> np.ndarray:
+    """Encode a uint8 [nb][na][h][w][3] light field on the current GPU; returns the stream bytes."""
     lf = np.ascontiguousarray(light_field, dtype=np.uint8)
     nb, na, h, w, _ = lf.shape
     p = _encode_params(enc)
     out = C.c_void_p()
     n = C.c_size_t()
-    if device:
-        need = C.c_int64()
-        check(lib().lf_encode_workspace_bytes(nb, na, h, w, C.byref(p), C.byref(need)))
-        work = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device="cuda")
-        check(lib().lf_encode_device(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads,
-                                     _ptr(work), work.numel(), _stream(), C.byref(out), C.byref(n)))
-        del work
-    else:
-        check(lib().lf_encode(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), threads, C.byref(out),
-                              C.byref(n)))
+    need = C.c_int64()
+    check(lib().lf_encode_workspace_bytes(nb, na, h, w, C.byref(p), C.byref(need)))
+    work = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device="cuda")
+    check(lib().lf_encode_device(lf.ctypes.data_as(C.c_void_p), nb, na, h, w, C.byref(p), _ptr(work), work.numel(),
+                                 _stream(), C.byref(out), C.byref(n)))
+    del work
     buf = np.ctypeslib.as_array(C.cast(out, C.POINTER(C.c_uint8)), shape=(n.value,)).copy()
     lib().lf_encode_free(out)
     return buf

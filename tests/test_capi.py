@@ -104,24 +104,87 @@ def test_sparse_residency_arena(tiny_lf, tiny_stream):
 
 
 def test_encode_workspace_bytes():
-    """Device-search workspace: the largest level's SRV and reconstructed
-    planes (int16), item list (3 int32) and results (4 int32), 256-aligned."""
+    """Encoder workspace, as the header states it: 256-aligned sections for the
+    uploaded field, the YCoCg planes of every level, level-0 coded SRVs,
+    quantised values, 28 bytes per block of bookkeeping, prefix-sum tiles,
+    motion records, level-0 search items, the 16-bit payload bound and the
+    motion-vector words."""
     from paper_1902_09396_amd import lf
 
     import lfscene
 
     al = lambda v: (v + 255) // 256 * 256  # noqa: E731
-    for name, over in (("tiny", {}), ("path512", {}), ("tiny", {"no_mc": True})):
+    for name, over in (("tiny", {}), ("path512", {}), ("tiny", {"no_mc": True}), ("tiny", {"block": 2})):
         cfg = lfscene.get_config(name, **over)
         L, enc = cfg["lf"], cfg["enc"]
         na, nb, h, w, bs, H = L["na"], L["nb"], L["h"], L["w"], enc["block"], enc["levels"]
-        expect = 0
-        if not enc.get("no_mc", False):
-            for _ in range(H):
-                npred = ((nb // 2) * na + ((nb + 1) // 2) * (na // 2)) * (w // bs) * (h // bs)
-                expect = max(expect, 2 * al(3 * na * nb * w * h * 2) + al(3 * npred * 12) + al(3 * npred * 16))
-                na, nb = (na + 1) // 2, (nb + 1) // 2
+        n, nblk, plane = bs * bs, (w // bs) * (h // bs), w * h
+        grids = [(na, nb)]
+        for _ in range(H):
+            grids.append(((grids[-1][0] + 1) // 2, (grids[-1][1] + 1) // 2))
+        views = [a * b for a, b in grids]
+        nent = 3 * sum(views[:H]) * nblk
+        npred = [((b // 2) * a + ((b + 1) // 2) * (a // 2)) * nblk for a, b in grids[:H]]
+        mv_words = 0
+        for _ in range(3):
+            for l in range(H):
+                vmax, cnt = 8 * enc["win"][l], 2 * npred[l]
+                sizes = []
+                for fam, m in enumerate((1, 3, 5)):
+                    b = (vmax // m).bit_length()
+                    sizes.append(cnt * b if fam == 0 else (-(-cnt // 5) * (8 + 5 * b) if fam == 1
+                                                           else -(-cnt // 3) * (7 + 3 * b)))
+                mv_words += -(-min(sizes) // 32) + -(-cnt // 32)
+        tiles = -(-nent // 4096)
+        expect = (al(256) + al(views[0] * plane * 3) + sum(al(3 * v * plane * 2) for v in views)
+                  + al(3 * views[0] * plane * 2) + al(nent * n * 2) + al(nent * 8) + al(nent * 4) + al(nent * 8)
+                  + al(nent * 8) + al((tiles + 1) * 8) + al(3 * sum(npred) * 16) + al(3 * npred[0] * 12)
+                  + al(nent * (-(-16 * n // 32)) * 4) + al(mv_words * 4))
         got = C.c_int64()
         p = lf._encode_params(enc)
         lf.check(lf.lib().lf_encode_workspace_bytes(L["nb"], L["na"], h, w, C.byref(p), C.byref(got)))
-        assert got.value == expect, name
+        assert got.value == expect, (name, over)
+
+
+def test_encode_rejects_on_the_host():
+    """Parameter checks happen before any device work."""
+    from paper_1902_09396_amd import lf
+
+    import lfscene
+
+    cfg = lfscene.get_config("tiny")
+    L = cfg["lf"]
+    for over in ({"block": 3}, {"block": 128}, {"step": 0}, {"step": 5000}, {"win": 60}, {"win": 300},
+                 {"block": 1}):
+        enc = lfscene.get_config("tiny", **over)["enc"]
+        p = lf._encode_params(enc)
+        with pytest.raises(lf.LFError) as e:
+            lf.check(lf.lib().lf_encode_workspace_bytes(L["nb"], L["na"], L["h"], L["w"], C.byref(p),
+                                                        C.byref(C.c_int64())))
+        assert e.value.status == lf.LF_EINVAL, over
+
+
+def test_parse_bounds_residual_ranges():
+    """A block whose mode can hold a dequantised residual beyond 2^24 is a
+    format error (the decoders' int32 sums could wrap); the bound counts
+    every value the mode can hold, (min + cap - 1) * step, not only the
+    stored ones.  Streams written from the format alone (tests/streamkit)."""
+    from paper_1902_09396_amd import lf
+    from streamkit import Craft
+
+    def stream(mn, b, step):
+        k = Craft(na=2, nb=2, w=8, h=8, levels=1, block=4, step=[step], win=[2])
+        k.set_block_raw(0, 0, 0, 1, 0, mn, b, np.zeros(16, dtype=np.int64))
+        return k.build()
+
+    def arena(s):
+        need = C.c_int64()
+        lf.check(lf.lib().lf_query_arena(s.ctypes.data_as(C.c_void_p), s.size, C.byref(need)))
+        return need.value
+
+    assert arena(stream(0, 12, 4096)) > 0          # (2^12 - 1) * 4096 < 2^24
+    assert arena(stream(-4096, 0, 4096)) > 0        # |min * step| = 2^24 exactly
+    for mn, b, step in ((0, 20, 4096), (0, 13, 4096), (-4097, 0, 4096), (-32768, 10, 1024), (32000, 15, 1024)):
+        with pytest.raises(lf.LFError) as e:
+            arena(stream(mn, b, step))
+        assert e.value.status == lf.LF_EFORMAT, (mn, b, step)

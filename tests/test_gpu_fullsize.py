@@ -1,6 +1,7 @@
 """Full-size GPU parity on the benchmark workload: a 17x17 grid of 512x512
 views, 4-level tree, 16x16 blocks, step 4, rendered as the 120-frame 512x512
-orbit path in the same single launch the benchmark times.  The oracle checks
+orbit path in the same single launch the benchmark times (the stream from the
+GPU encoder, as the benchmark encodes it).  The oracle checks
 sampled outputs one by one: 10^6 random decoded samples (bit-exact) and
 30000 random rays plus three whole rows (<= 1e-5)."""
 
@@ -22,8 +23,8 @@ def full():
     cfg = lfscene.get_config("path512")
     L = cfg["lf"]
     light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
-    stream = oracle.encode(light, cfg["enc"])
-    o = oracle.OracleLF(stream)
+    stream = lf.encode(light, cfg["enc"])  # parity is on decoding a given stream; the GPU encoder
+    o = oracle.OracleLF(stream)                # equals the oracle's byte for byte (test_gpu_encoder)
     field = lf.LightField(stream, device="cuda:0")
     cams = lfscene.make_views(cfg)
     return torch, cfg, o, field, cams

@@ -1,8 +1,7 @@
-"""GPU phase-shifted motion search (Eq. 1-2) against the oracle's search, and
-the GPU-assisted encoder against the oracle's encoder.
+"""GPU phase-shifted motion search (Eq. 1-2) against the oracle's search.
 
 Every decision is integer: (mx, my, sigma, cost) must equal the oracle's for
-every block, and the encoder's stream must be byte-identical.
+every block.
 """
 
 import numpy as np
@@ -130,34 +129,6 @@ def test_search_errors(torch_mod):
             lf.mc_search(P, R, I, bs, win)
         assert e.value.status == lf.LF_EINVAL
     assert lf.mc_search(P, R, I[:0], 16, 4).shape == (0, 4)
-
-
-@pytest.mark.parametrize("over", [{}, {"step": 1}, {"zero_phase": True}, {"no_mc": True},
-                                  {"step": 8, "t_ref": 200, "t_pred": 400}, {"subpel": False}])
-def test_device_encoder_tiny(torch_mod, tiny_lf, over):
-    from paper_1902_09396_amd import lf
-
-    enc = lfscene.get_config("tiny", **over)["enc"]
-    assert np.array_equal(lf.encode(tiny_lf, enc, device=True), stream_for("tiny", tiny_lf, **over))
-
-
-def test_device_encoder_mid(torch_mod, mid_lf, mid_stream):
-    from paper_1902_09396_amd import lf
-
-    assert np.array_equal(lf.encode(mid_lf, lfscene.get_config("path512")["enc"], device=True), mid_stream)
-
-
-def test_device_encoder_odd_grid(torch_mod):
-    from paper_1902_09396_amd import lf
-
-    x = crop_lf("tiny", 7, 5, 16, 24)
-    enc = lfscene.get_config("tiny")["enc"]
-    enc.update(levels=3, block=4, step=[3, 2, 5], win=[2, 1, 3], t_ref=[10, 0, 0], t_pred=[30, 5, 0])
-    assert np.array_equal(lf.encode(x, enc, device=True), oracle.encode(x, enc))
-    enc.update(win=[2, 1, 60])  # 4 + 121 > 96
-    with pytest.raises(lf.LFError) as e:
-        lf.encode(x, enc, device=True)
-    assert e.value.status == lf.LF_EINVAL
 
 
 def test_rd_point_lossless_and_lossy(torch_mod, tiny_lf):
