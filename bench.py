@@ -159,7 +159,7 @@ def main():
     lat = np.array(lat)
 
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    counters = load_counters()
+    counters = load_counters() if args.workload == "path512" else None  # counters were taken on that workload
     traffic = counters.get("bytes_per_launch") if counters else None
     result = {
         "metric": METRIC,
@@ -177,10 +177,11 @@ def main():
         "views_per_chunk": lf.render_config(V, wo, ho)[1],
         "data": "synthetic",
         "config": {
-            "workload": "%dx%d views of %dx%d RGB, %d-level tree, %dx%d blocks, step %d, quarter-pel MVs; "
-                        "%d-frame %dx%d orbit path per step" % (L["na"], L["nb"], L["w"], L["h"],
-                                                                 cfg["enc"]["levels"], cfg["enc"]["block"],
-                                                                 cfg["enc"]["block"], cfg["enc"]["step"][0], V, wo, ho),
+            "workload": "%dx%d views of %dx%d RGB, %d-level tree, %dx%d blocks, step %d, quarter-pel MVs; %s" % (
+                L["na"], L["nb"], L["w"], L["h"], cfg["enc"]["levels"], cfg["enc"]["block"], cfg["enc"]["block"],
+                cfg["enc"]["step"][0],
+                ("%d-frame %dx%d orbit path per step" % (V, wo, ho)) if cfg["views"]["kind"] == "orbit" else
+                ("a batch of %d random %dx%d pinhole cameras per step" % (V, wo, ho))),
             "views_per_step": V,
             "width": wo,
             "height": ho,
@@ -197,7 +198,7 @@ def main():
                     "time; below the algorithmic bytes because views of a chunk share decoded values in LDS"},
         "latency_ms": None if not len(lat) else {
             "p50": round(float(np.percentile(lat, 50)), 4), "p99": round(float(np.percentile(lat, 99)), 4),
-            "unit": "ms per 512x512 view, one view per launch"},
+            "unit": "ms per %dx%d view, one view per launch" % (wo, ho)},
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),
@@ -334,6 +335,14 @@ def grad_bench(args):
     g = 2.0 * (out - target)
     bwd_ms, (g_res, g_sh) = timed(lambda: field.render_backward(res, sh, cams, wo, ho, g))
     rays = V * wo * ho
+    # compulsory bytes of one backward: every residual gradient and shift
+    # gradient written once; the output gradient, the reference residual
+    # planes (the shift gradients' taps) and the shifts read once
+    info = field.info
+    plane = field.width * field.height
+    bwd_bytes = (4 * res.numel() + 8 * sh.shape[0] + 4 * V * 3 * wo * ho + 4 * 3 * info["n_refs"] * plane
+                 + 8 * sh.shape[0])
+    achieved = bwd_bytes / (bwd_ms * 1e-3) / 1e9
     print(json.dumps({
         "metric": "relaxed render + adjoint: rays/s through forward and backward",
         "value": round(rays / ((fwd_ms + bwd_ms) * 1e-3) / 1e9, 4), "unit": "Grays/s", "higher_is_better": True,
@@ -343,6 +352,9 @@ def grad_bench(args):
         "forward_ms": round(fwd_ms, 3), "backward_ms": round(bwd_ms, 3),
         "gradient_bytes": int((res.numel() + sh.numel()) * 4),
         "nonzero_residual_grads": int((g_res != 0).sum().item()),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "lf_render_backward (all kernels)",
+                     "compulsory_bytes": int(bwd_bytes)},
     }), flush=True)
 
 
@@ -519,10 +531,10 @@ def rd_bench(args):
 
 
 def residency_point(cfg, light, enc, args):
-    """Dense against sparse reference residency for one stream: resident
-    reference bytes, arena bytes, and the 120-frame 512x512 orbit rendered
-    with each (tile kernel on the dense handle, one thread per ray on the
-    sparse one)."""
+    """Reference residencies for one stream: dense planes, block tiles and
+    per-pixel compressed sparse rows; resident reference bytes, arena bytes,
+    and the 120-frame 512x512 orbit rendered with each (the tile kernel, and
+    one thread per ray on every residency)."""
     import torch
 
     import lfscene
@@ -533,16 +545,17 @@ def residency_point(cfg, light, enc, args):
     cams = torch.from_numpy(cams_np).cuda()
     wo, ho = cfg["views"]["wo"], cfg["views"]["ho"]
     out = {}
-    for name, sparse in (("dense", False), ("sparse", True)):
-        field = lf.LightField(stream, device="cuda:0", sparse_refs=sparse)
+    for name, kw, per_ray in (("dense", {}, False), ("dense_per_ray", {}, True),
+                              ("sparse", {"sparse_refs": True}, True), ("csr", {"csr_refs": True}, True)):
+        field = lf.LightField(stream, device="cuda:0", **kw)
         img = torch.empty((cams.shape[0], 3, ho, wo), dtype=torch.float32, device="cuda")
         for _ in range(2):
-            field.render_views(cams, wo, ho, out=img)
+            field.render_views(cams, wo, ho, out=img, per_ray=per_ray)
         torch.cuda.synchronize()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record()
         for _ in range(args.steps):
-            field.render_views(cams, wo, ho, out=img)
+            field.render_views(cams, wo, ho, out=img, per_ray=per_ray)
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / args.steps
@@ -604,7 +617,7 @@ def cpu_baseline(stream, cams_np, wo, ho, n_rays):
     td = time.perf_counter() - t0
     o.close()
     return {"value": round(n / dt / 1e9, 6), "unit": "Grays/s", "cores": cores, "kind": "oracle",
-            "sample": "%d uniformly random rays of the 120-frame path (seed 7), OpenMP over rays, %.1f s" % (n, dt),
+            "sample": "%d uniformly random rays of the step's views (seed 7), OpenMP over rays, %.1f s" % (n, dt),
             "cpu_model": cpu_model(),
             "single_thread": {"value": round(n1 / t1 / 1e9, 8), "unit": "Grays/s",
                               "sample": "%d random rays, %.1f s" % (n1, t1)},

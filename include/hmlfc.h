@@ -78,11 +78,13 @@ typedef struct {
     int64_t stream_bytes;    /* compressed stream size                        */
     int64_t payload_bytes;   /* block payload section size                    */
     int64_t ref_bytes;       /* device bytes of the resident reference SRVs   */
-    int32_t sparse_refs;     /* 1: loaded with LF_LOAD_SPARSE_REFS            */
+    int32_t sparse_refs;     /* 0 dense planes, 1 LF_LOAD_SPARSE_REFS tiles,
+                                2 LF_LOAD_CSR_REFS sparse rows                */
     int64_t clamped_coords;  /* decode requests (lf_decode_pixels, _lod) with
                                 a coordinate outside the grid, clamped to it,
                                 since load (Random Access for Interactive
                                 Rendering: requests are grid positions)       */
+    int32_t chroma420;       /* 1: Co and Cg coded at half width and height   */
 } lf_info;
 
 /* Load flag: keep the reference SRVs block-sparse (only significant blocks,
@@ -92,6 +94,16 @@ typedef struct {
  * lf_render_views(_per_ray, _lod) (one thread per ray) and the relaxed
  * render and adjoint; the serving loop rejects it. */
 #define LF_LOAD_SPARSE_REFS 1
+
+/* Load flag: keep the reference SRVs as a per-pixel sparse matrix in
+ * compressed sparse rows (the paper's reference storage, Decompression
+ * Analysis): per reference row, the columns (uint16) and values (int16) of
+ * its nonzero pixels in increasing column order, and the row starts (uint32
+ * [3][n_refs][height] + 1).  A tap binary-searches its row.  Same results
+ * and same calls as LF_LOAD_SPARSE_REFS (not combinable with it); the arena
+ * reserves values and columns for every pixel of the significant reference
+ * blocks, lf_info.ref_bytes reports what the nonzeros use. */
+#define LF_LOAD_CSR_REFS 2
 
 /* ---------------------------------------------------------------------- */
 /* Loading (Decompression Memory Overhead: the top-level RKVs and every    */
@@ -118,8 +130,9 @@ lf_status lf_query_arena(const void* host_stream, size_t nbytes, int64_t* arena_
 lf_status lf_load_compressed(const void* host_stream, size_t nbytes, void* d_arena, int64_t arena_bytes,
                              void* stream, lf_handle** out);
 
-/* lf_query_arena / lf_load_compressed with load flags (0 or
- * LF_LOAD_SPARSE_REFS; other bits: LF_EINVAL).  Sparse arena sections:
+/* lf_query_arena / lf_load_compressed with load flags (0, LF_LOAD_SPARSE_REFS
+ * or LF_LOAD_CSR_REFS; other bits or both: LF_EINVAL; either with a 4:2:0
+ * stream: LF_EINVAL).  Sparse arena sections:
  * root, block table, payload, motion vectors, reference tiles (int16
  * [n_tiles][Bs][Bs], significant reference blocks in (channel, reference
  * node, block) order), tile index (int32 [3][n_refs][n_blocks], -1 for a
@@ -336,6 +349,9 @@ typedef struct {
     int32_t subpel;      /* 1: quarter-pel refinement around the integer best      */
     int32_t zero_phase;  /* 1: allow "no prediction" when it is strictly cheaper   */
     int32_t no_mc;       /* 1: no motion compensation (plain hierarchy)            */
+    int32_t chroma420;   /* 1: Co and Cg sub-sampled 4:2:0 (2x2 rounded mean) and
+                            coded at half width and height; the image sides must
+                            be multiples of twice the block size                   */
 } lf_encode_params;
 
 /* Device workspace lf_encode_device needs, in bytes: 256-byte aligned

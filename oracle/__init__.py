@@ -60,6 +60,9 @@ def lib():
             "orc_open": (C.c_int, [P, C.c_size_t, P]),
             "orc_close": (None, [P]),
             "orc_info": (None, [P, P]),
+            "orc_decode_channel_at": (C.c_int, [P, C.c_int, C.c_int, P, i64, P]),
+            "orc_chroma_down": (None, [P, C.c_int, C.c_int, P]),
+            "orc_chroma_up": (None, [P, C.c_int, C.c_int, P]),
             "orc_decode_at": (C.c_int, [P, P, i64, P]),
             "orc_decode_at_ycocg": (C.c_int, [P, P, i64, P]),
             "orc_decode_node": (C.c_int, [P, C.c_int, P, i64, P]),
@@ -95,7 +98,7 @@ class _Params(C.Structure):
     _fields_ = [("levels", C.c_int32), ("block", C.c_int32), ("step", C.c_int32 * MAX_LEVELS),
                 ("t_ref", C.c_int32 * MAX_LEVELS), ("t_pred", C.c_int32 * MAX_LEVELS),
                 ("win", C.c_int32 * MAX_LEVELS), ("subpel", C.c_int32), ("zero_phase", C.c_int32),
-                ("no_mc", C.c_int32)]
+                ("no_mc", C.c_int32), ("chroma420", C.c_int32)]
 
 
 def _params(enc: dict) -> _Params:
@@ -110,6 +113,7 @@ def _params(enc: dict) -> _Params:
     p.subpel = int(enc.get("subpel", True))
     p.zero_phase = int(enc.get("zero_phase", False))
     p.no_mc = int(enc.get("no_mc", False))
+    p.chroma420 = int(enc.get("chroma420", False))
     return p
 
 
@@ -224,10 +228,10 @@ class OracleLF:
         if rc != 0:
             raise ValueError("oracle: malformed stream (%d)" % rc)
         self._h = h
-        info = np.zeros(10, dtype=np.int64)
+        info = np.zeros(11, dtype=np.int64)
         lib().orc_info(self._h, _p(info))
         (self.na, self.nb, self.w, self.h, self.levels, self.block, self.n_nodes, self.n_pred,
-         self.root_na, self.root_nb) = (int(v) for v in info)
+         self.root_na, self.root_nb, self.chroma420) = (int(v) for v in info)
 
     def close(self):
         if self._h:
@@ -268,6 +272,14 @@ class OracleLF:
         out = np.empty((cams.shape[0], 3, ho, wo), dtype=np.float64)
         if lib().orc_render_lod(self._h, int(level), _p(cams), cams.shape[0], wo, ho, _p(out)) != 0:
             raise ValueError("level out of range")
+        return out
+
+    def decode_channel(self, c: int, coords: np.ndarray, lod: int = 0) -> np.ndarray:
+        """Channel c at its own resolution (half size for 4:2:0 chroma): coords (b, a, y, x) -> int32."""
+        coords = np.ascontiguousarray(coords, dtype=np.int32).reshape(-1, 4)
+        out = np.empty(coords.shape[0], dtype=np.int32)
+        if lib().orc_decode_channel_at(self._h, int(c), int(lod), _p(coords), coords.shape[0], _p(out)) != 0:
+            raise ValueError("channel, level or coordinate out of range")
         return out
 
     def decode_full(self) -> np.ndarray:

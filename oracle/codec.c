@@ -360,115 +360,106 @@ static uint64_t get64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v
 
 void orc_free(void* p) { free(p); }
 
-int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params* p,
-               int nthreads, uint8_t** out, size_t* out_len)
+/* Channel geometry: luma at full resolution; with 4:2:0 chroma (Compressing
+ * HMLFC tree: the chroma channels are sub-sampled) Co and Cg are coded at
+ * half the width and height. */
+static void channel_dims(int w, int h, int chroma420, int c, int* wc, int* hc)
 {
-    (void)nthreads;
-    const int H = p->levels, bs = p->block;
-    if (H < 1 || H > ORC_MAX_LEVELS || bs < 1 || bs > 64 || w % bs || h % bs || na < 1 || nb < 1) return -1;
-    for (int l = 0; l < H; l++)
-        if (p->step[l] < 1 || p->win[l] < 0) return -1;
-    int na_l[ORC_MAX_LEVELS + 1], nb_l[ORC_MAX_LEVELS + 1];
-    orc_level_grid(na, nb, H, na_l, nb_l);
-    const int64_t plane = (int64_t)w * h;
-    const int nbx = w / bs, nby = h / bs, nblk = nbx * nby, n = bs * bs;
+    *wc = (chroma420 && c > 0) ? w / 2 : w;
+    *hc = (chroma420 && c > 0) ? h / 2 : h;
+}
 
-    /* 1. colour transform, I[0][c][b][a] planes */
-    int32_t* I[ORC_MAX_LEVELS + 1];
-    for (int l = 0; l <= H; l++) I[l] = (int32_t*)malloc(sizeof(int32_t) * 3 * na_l[l] * nb_l[l] * plane);
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int b = 0; b < nb; b++)
-        for (int a = 0; a < na; a++)
-            for (int64_t px = 0; px < plane; px++) {
-                const uint8_t* s = lf + (((int64_t)b * na + a) * plane + px) * 3;
-                int Y, Co, Cg;
-                orc_ycocg_fwd(s[0], s[1], s[2], &Y, &Co, &Cg);
-                int64_t vi = (int64_t)b * na + a;
-                I[0][(0 * (int64_t)nb * na + vi) * plane + px] = Y;
-                I[0][(1 * (int64_t)nb * na + vi) * plane + px] = Co;
-                I[0][(2 * (int64_t)nb * na + vi) * plane + px] = Cg;
-            }
+/* 2x2 rounded mean of a full-resolution chroma plane: the half-resolution
+ * sample (Y, X) covers full-resolution rows 2Y, 2Y+1 and columns 2X, 2X+1;
+ * floor((sum + 2) / 4), the RKV rule for four members. */
+void orc_chroma_down(const int32_t* full, int w, int h, int32_t* half)
+{
+    for (int Y = 0; Y < h / 2; Y++)
+        for (int X = 0; X < w / 2; X++) {
+            int sum = full[(int64_t)(2 * Y) * w + 2 * X] + full[(int64_t)(2 * Y) * w + 2 * X + 1] +
+                      full[(int64_t)(2 * Y + 1) * w + 2 * X] + full[(int64_t)(2 * Y + 1) * w + 2 * X + 1];
+            half[(int64_t)Y * (w / 2) + X] = orc_fdiv(sum + 2, 4);
+        }
+}
 
-    /* 2. representative key views: rounded mean over each 2x2 cluster */
-    for (int l = 0; l < H; l++) {
-        int64_t nv0 = (int64_t)na_l[l] * nb_l[l], nv1 = (int64_t)na_l[l + 1] * nb_l[l + 1];
-#pragma omp parallel for collapse(3) schedule(static)
-        for (int c = 0; c < 3; c++)
-            for (int B = 0; B < nb_l[l + 1]; B++)
-                for (int A = 0; A < na_l[l + 1]; A++) {
-                    int32_t* dst = I[l + 1] + (c * nv1 + (int64_t)B * na_l[l + 1] + A) * plane;
-                    for (int64_t px = 0; px < plane; px++) {
-                        int sum = 0, cnt = 0;
-                        for (int j = 0; j < 2; j++)
-                            for (int i = 0; i < 2; i++) {
-                                int bb = 2 * B + j, aa = 2 * A + i;
-                                if (bb >= nb_l[l] || aa >= na_l[l]) continue;
-                                sum += I[l][(c * nv0 + (int64_t)bb * na_l[l] + aa) * plane + px];
-                                cnt++;
-                            }
-                        dst[px] = orc_fdiv(sum + cnt / 2, cnt);
-                    }
-                }
-    }
-
-    /* BFS node numbering: level H-1 first, raster within a level */
-    int64_t node_base[ORC_MAX_LEVELS];
-    int64_t n_nodes = 0;
-    for (int l = H - 1; l >= 0; l--) {
-        node_base[l] = n_nodes;
-        n_nodes += (int64_t)na_l[l] * nb_l[l];
-    }
-    int32_t* qall = (int32_t*)calloc((size_t)3 * n_nodes * nblk * n, sizeof(int32_t));
-    mvrec* mvs[3][ORC_MAX_LEVELS];
+/* Per-channel coding state of one encode. */
+typedef struct {
+    int w, h, nbx, nblk, n;
+    int64_t plane;
+    int32_t* I[ORC_MAX_LEVELS + 1]; /* original planes per level [views][h][w] */
+    int32_t* q;                     /* quantised values [n_nodes][nblk][n] */
+    mvrec* mvs[ORC_MAX_LEVELS];
     int64_t npred[ORC_MAX_LEVELS];
-    for (int l = 0; l < H; l++) {
-        npred[l] = orc_pred_nodes(na_l[l], nb_l[l]) * nblk;
-        for (int c = 0; c < 3; c++) mvs[c][l] = (mvrec*)calloc((size_t)(npred[l] > 0 ? npred[l] : 1), sizeof(mvrec));
-    }
+} chan_state;
 
-    /* 3. closed-loop top-down coding; Irec holds the reconstruction of the
-     *    level above, starting from the lossless root */
-    int32_t* Irec_up = (int32_t*)malloc(sizeof(int32_t) * 3 * na_l[H] * nb_l[H] * plane);
-    memcpy(Irec_up, I[H], sizeof(int32_t) * 3 * na_l[H] * nb_l[H] * plane);
+/* The tree of one channel (RLFC hierarchy, then the top-down closed loop
+ * with phase-shifted motion compensation), given its level-0 planes. */
+static int code_channel(chan_state* S, const orc_params* p, const int* na_l, const int* nb_l,
+                        const int64_t* node_base, int64_t n_nodes)
+{
+    const int H = p->levels, bs = p->block, w = S->w, h = S->h, nbx = S->nbx, nblk = S->nblk, n = S->n;
+    const int64_t plane = S->plane;
+    /* representative key views: rounded mean over each 2x2 cluster */
+    for (int l = 0; l < H; l++) {
+        S->I[l + 1] = (int32_t*)malloc(sizeof(int32_t) * na_l[l + 1] * nb_l[l + 1] * plane);
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int B = 0; B < nb_l[l + 1]; B++)
+            for (int A = 0; A < na_l[l + 1]; A++) {
+                int32_t* dst = S->I[l + 1] + ((int64_t)B * na_l[l + 1] + A) * plane;
+                for (int64_t px = 0; px < plane; px++) {
+                    int sum = 0, cnt = 0;
+                    for (int j = 0; j < 2; j++)
+                        for (int i = 0; i < 2; i++) {
+                            int bb = 2 * B + j, aa = 2 * A + i;
+                            if (bb >= nb_l[l] || aa >= na_l[l]) continue;
+                            sum += S->I[l][((int64_t)bb * na_l[l] + aa) * plane + px];
+                            cnt++;
+                        }
+                    dst[px] = orc_fdiv(sum + cnt / 2, cnt);
+                }
+            }
+    }
+    S->q = (int32_t*)calloc((size_t)n_nodes * nblk * n, sizeof(int32_t));
+    for (int l = 0; l < H; l++) {
+        S->npred[l] = orc_pred_nodes(na_l[l], nb_l[l]) * nblk;
+        S->mvs[l] = (mvrec*)calloc((size_t)(S->npred[l] > 0 ? S->npred[l] : 1), sizeof(mvrec));
+    }
+    /* closed loop from the lossless root */
+    int32_t* Irec_up = (int32_t*)malloc(sizeof(int32_t) * na_l[H] * nb_l[H] * plane);
+    memcpy(Irec_up, S->I[H], sizeof(int32_t) * na_l[H] * nb_l[H] * plane);
     for (int l = H - 1; l >= 0; l--) {
         const int nal = na_l[l], nbl = nb_l[l], nau = na_l[l + 1], nbu = nb_l[l + 1];
         const int64_t nv = (int64_t)nal * nbl, nvu = (int64_t)nau * nbu;
-        int32_t* S = (int32_t*)malloc(sizeof(int32_t) * 3 * nv * plane);     /* SRVs          */
-        int32_t* Shat = (int32_t*)malloc(sizeof(int32_t) * 3 * nv * plane);  /* decoded SRVs  */
-        /* SRV = view - reconstructed parent RKV (SRV sign: view minus RKV) */
-        for (int c = 0; c < 3; c++)
-            for (int B = 0; B < nbl; B++)
-                for (int A = 0; A < nal; A++) {
-                    const int32_t* src = I[l] + (c * nv + (int64_t)B * nal + A) * plane;
-                    const int32_t* par = Irec_up + (c * nvu + (int64_t)(B / 2) * nau + A / 2) * plane;
-                    int32_t* dst = S + (c * nv + (int64_t)B * nal + A) * plane;
-                    for (int64_t px = 0; px < plane; px++) dst[px] = src[px] - par[px];
-                }
-        /* reference SRVs: the (even, even) member of each cluster */
-#pragma omp parallel for schedule(dynamic) collapse(2)
-        for (int c = 0; c < 3; c++)
-            for (int64_t ci = 0; ci < nvu; ci++) {
-                int B = 2 * (int)(ci / nau), A = 2 * (int)(ci % nau);
-                int64_t vi = (int64_t)B * nal + A;
-                int32_t e[4096], q[4096];
-                for (int k = 0; k < nblk; k++) {
-                    int by0 = (k / nbx) * bs, bx0 = (k % nbx) * bs;
-                    for (int i = 0; i < n; i++)
-                        e[i] = S[(c * nv + vi) * plane + (int64_t)(by0 + i / bs) * w + bx0 + i % bs];
-                    code_block(e, n, p->step[l], p->t_ref[l], q);
-                    int64_t node = node_base[l] + vi;
-                    memcpy(qall + (((int64_t)c * n_nodes + node) * nblk + k) * n, q, sizeof(int32_t) * n);
-                    for (int i = 0; i < n; i++)
-                        Shat[(c * nv + vi) * plane + (int64_t)(by0 + i / bs) * w + bx0 + i % bs] = q[i] * p->step[l];
-                }
+        int32_t* Sv = (int32_t*)malloc(sizeof(int32_t) * nv * plane);   /* SRVs          */
+        int32_t* Shat = (int32_t*)malloc(sizeof(int32_t) * nv * plane); /* decoded SRVs  */
+        /* SRV = view - reconstructed parent RKV */
+        for (int B = 0; B < nbl; B++)
+            for (int A = 0; A < nal; A++) {
+                const int32_t* src = S->I[l] + ((int64_t)B * nal + A) * plane;
+                const int32_t* par = Irec_up + ((int64_t)(B / 2) * nau + A / 2) * plane;
+                int32_t* dst = Sv + ((int64_t)B * nal + A) * plane;
+                for (int64_t px = 0; px < plane; px++) dst[px] = src[px] - par[px];
             }
+        /* reference SRVs: the (even, even) member of each cluster */
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t ci = 0; ci < nvu; ci++) {
+            int B = 2 * (int)(ci / nau), A = 2 * (int)(ci % nau);
+            int64_t vi = (int64_t)B * nal + A;
+            int32_t e[4096], q[4096];
+            for (int k = 0; k < nblk; k++) {
+                int by0 = (k / nbx) * bs, bx0 = (k % nbx) * bs;
+                for (int i = 0; i < n; i++) e[i] = Sv[vi * plane + (int64_t)(by0 + i / bs) * w + bx0 + i % bs];
+                code_block(e, n, p->step[l], p->t_ref[l], q);
+                int64_t node = node_base[l] + vi;
+                memcpy(S->q + (node * nblk + k) * n, q, sizeof(int32_t) * n);
+                for (int i = 0; i < n; i++)
+                    Shat[vi * plane + (int64_t)(by0 + i / bs) * w + bx0 + i % bs] = q[i] * p->step[l];
+            }
+        }
         /* predictive SRVs: phase-shifted motion compensation against the
          * decoded reference of the same cluster, then the residual is coded */
-        int64_t total = 3 * npred[l];
 #pragma omp parallel for schedule(dynamic, 16)
-        for (int64_t it = 0; it < total; it++) {
-            int c = (int)(it / npred[l]);
-            int64_t j = it % npred[l];
+        for (int64_t j = 0; j < S->npred[l]; j++) {
             int64_t pord = j / nblk;
             int k = (int)(j % nblk);
             /* invert the predictive ordinal by scanning (plain, not fast) */
@@ -482,15 +473,15 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
                     }
             int64_t vi = (int64_t)B * nal + A;
             int64_t ri = (int64_t)(B & ~1) * nal + (A & ~1);
-            const int32_t* P = S + (c * nv + vi) * plane;
-            const int32_t* R = Shat + (c * nv + ri) * plane;
+            const int32_t* P = Sv + vi * plane;
+            const int32_t* R = Shat + ri * plane;
             int by0 = (k / nbx) * bs, bx0 = (k % nbx) * bs;
             int mx = 0, my = 0, sg = 0;
             if (!p->no_mc)
                 orc_mc_search(P, R, w, h, by0, bx0, bs, p->win[l], p->subpel, p->zero_phase, &mx, &my, &sg);
-            mvs[c][l][j].mx = mx;
-            mvs[c][l][j].my = my;
-            mvs[c][l][j].sigma = sg;
+            S->mvs[l][j].mx = mx;
+            S->mvs[l][j].my = my;
+            S->mvs[l][j].sigma = sg;
             int32_t e[4096], q[4096], pred[4096];
             for (int i = 0; i < n; i++) {
                 int y = by0 + i / bs, x = bx0 + i % bs;
@@ -499,72 +490,136 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
             }
             code_block(e, n, p->step[l], p->t_pred[l], q);
             int64_t node = node_base[l] + vi;
-            memcpy(qall + (((int64_t)c * n_nodes + node) * nblk + k) * n, q, sizeof(int32_t) * n);
-            int32_t* dst = Shat + (c * nv + vi) * plane;
-            for (int i = 0; i < n; i++)
-                dst[(int64_t)(by0 + i / bs) * w + bx0 + i % bs] = pred[i] + q[i] * p->step[l];
+            memcpy(S->q + (node * nblk + k) * n, q, sizeof(int32_t) * n);
+            int32_t* dst = Shat + vi * plane;
+            for (int i = 0; i < n; i++) dst[(int64_t)(by0 + i / bs) * w + bx0 + i % bs] = pred[i] + q[i] * p->step[l];
         }
         /* reconstruction of this level: parent RKV + decoded SRV */
-        int32_t* Irec = (int32_t*)malloc(sizeof(int32_t) * 3 * nv * plane);
-        for (int c = 0; c < 3; c++)
-            for (int B = 0; B < nbl; B++)
-                for (int A = 0; A < nal; A++) {
-                    const int32_t* par = Irec_up + (c * nvu + (int64_t)(B / 2) * nau + A / 2) * plane;
-                    const int32_t* sh = Shat + (c * nv + (int64_t)B * nal + A) * plane;
-                    int32_t* dst = Irec + (c * nv + (int64_t)B * nal + A) * plane;
-                    for (int64_t px = 0; px < plane; px++) dst[px] = par[px] + sh[px];
-                }
+        int32_t* Irec = (int32_t*)malloc(sizeof(int32_t) * nv * plane);
+        for (int B = 0; B < nbl; B++)
+            for (int A = 0; A < nal; A++) {
+                const int32_t* par = Irec_up + ((int64_t)(B / 2) * nau + A / 2) * plane;
+                const int32_t* sh = Shat + ((int64_t)B * nal + A) * plane;
+                int32_t* dst = Irec + ((int64_t)B * nal + A) * plane;
+                for (int64_t px = 0; px < plane; px++) dst[px] = par[px] + sh[px];
+            }
         free(Irec_up);
         Irec_up = Irec;
-        free(S);
+        free(Sv);
         free(Shat);
     }
     free(Irec_up);
+    return 0;
+}
 
-    /* 4. block payloads (BFS node order), table entries */
-    int64_t nent = (int64_t)3 * n_nodes * nblk;
+int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params* p,
+               int nthreads, uint8_t** out, size_t* out_len)
+{
+    (void)nthreads;
+    const int H = p->levels, bs = p->block, c420 = p->chroma420 != 0;
+    if (H < 1 || H > ORC_MAX_LEVELS || bs < 1 || bs > 64 || w % bs || h % bs || na < 1 || nb < 1) return -1;
+    if (c420 && (w % (2 * bs) || h % (2 * bs))) return -1; /* chroma planes must hold whole blocks */
+    for (int l = 0; l < H; l++)
+        if (p->step[l] < 1 || p->win[l] < 0) return -1;
+    int na_l[ORC_MAX_LEVELS + 1], nb_l[ORC_MAX_LEVELS + 1];
+    orc_level_grid(na, nb, H, na_l, nb_l);
+    const int64_t nv0 = (int64_t)na * nb;
+    int64_t node_base[ORC_MAX_LEVELS];
+    int64_t n_nodes = 0;
+    for (int l = H - 1; l >= 0; l--) {
+        node_base[l] = n_nodes;
+        n_nodes += (int64_t)na_l[l] * nb_l[l];
+    }
+    chan_state S[3];
+    memset(S, 0, sizeof S);
+    for (int c = 0; c < 3; c++) {
+        channel_dims(w, h, c420, c, &S[c].w, &S[c].h);
+        S[c].nbx = S[c].w / bs;
+        S[c].nblk = S[c].nbx * (S[c].h / bs);
+        S[c].n = bs * bs;
+        S[c].plane = (int64_t)S[c].w * S[c].h;
+        S[c].I[0] = (int32_t*)malloc(sizeof(int32_t) * nv0 * S[c].plane);
+    }
+    /* 1. colour transform (and chroma sub-sampling) */
+    const int64_t fplane = (int64_t)w * h;
+    int32_t* tmp = c420 ? (int32_t*)malloc(sizeof(int32_t) * fplane * 2) : NULL;
+    for (int64_t v = 0; v < nv0; v++) {
+        for (int64_t px = 0; px < fplane; px++) {
+            const uint8_t* s = lf + (v * fplane + px) * 3;
+            int Y, Co, Cg;
+            orc_ycocg_fwd(s[0], s[1], s[2], &Y, &Co, &Cg);
+            S[0].I[0][v * fplane + px] = Y;
+            if (c420) {
+                tmp[px] = Co;
+                tmp[fplane + px] = Cg;
+            } else {
+                S[1].I[0][v * fplane + px] = Co;
+                S[2].I[0][v * fplane + px] = Cg;
+            }
+        }
+        if (c420) {
+            orc_chroma_down(tmp, w, h, S[1].I[0] + v * S[1].plane);
+            orc_chroma_down(tmp + fplane, w, h, S[2].I[0] + v * S[2].plane);
+        }
+    }
+    free(tmp);
+    /* 2-3. hierarchy and closed-loop coding, channel by channel */
+    for (int c = 0; c < 3; c++) code_channel(&S[c], p, na_l, nb_l, node_base, n_nodes);
+
+    /* 4. block payloads (channel, BFS node, block order), table entries */
+    int64_t tbase[3], nent = 0;
+    for (int c = 0; c < 3; c++) {
+        tbase[c] = nent;
+        nent += n_nodes * S[c].nblk;
+    }
     uint8_t* table = (uint8_t*)calloc((size_t)nent, 8);
     int* modes = (int*)malloc(sizeof(int) * nent);
     int16_t* mins = (int16_t*)malloc(sizeof(int16_t) * nent);
     int64_t* woff = (int64_t*)malloc(sizeof(int64_t) * nent);
     int64_t pw = 0;
     int status = 0;
-    for (int64_t e = 0; e < nent; e++) {
-        const int32_t* q = qall + e * n;
-        int32_t qmin = q[0], nz = 0;
-        for (int i = 0; i < n; i++) {
-            if (q[i] < qmin) qmin = q[i];
-            if (q[i]) nz = 1;
+    for (int c = 0; c < 3; c++)
+        for (int64_t e0 = 0; e0 < n_nodes * S[c].nblk; e0++) {
+            const int n = S[c].n;
+            const int64_t e = tbase[c] + e0;
+            const int32_t* q = S[c].q + e0 * n;
+            int32_t qmin = q[0], nz = 0;
+            for (int i = 0; i < n; i++) {
+                if (q[i] < qmin) qmin = q[i];
+                if (q[i]) nz = 1;
+            }
+            if (!nz) {
+                modes[e] = ORC_INSIGNIFICANT;
+                mins[e] = 0;
+                woff[e] = 0;
+                continue;
+            }
+            if (qmin < -32768 || qmin > 32767) status = -2;
+            uint32_t v[4096];
+            for (int i = 0; i < n; i++) v[i] = (uint32_t)(q[i] - qmin);
+            int mode = orc_bise_choose(v, n);
+            if (mode < 0) status = -2;
+            modes[e] = mode;
+            mins[e] = (int16_t)qmin;
+            woff[e] = pw;
+            pw += (orc_bise_bits(mode, n) + 31) / 32;
         }
-        if (!nz) {
-            modes[e] = ORC_INSIGNIFICANT;
-            mins[e] = 0;
-            woff[e] = 0;
-            continue;
-        }
-        if (qmin < -32768 || qmin > 32767) status = -2;
-        uint32_t v[4096];
-        for (int i = 0; i < n; i++) v[i] = (uint32_t)(q[i] - qmin);
-        int mode = orc_bise_choose(v, n);
-        if (mode < 0) status = -2;
-        modes[e] = mode;
-        mins[e] = (int16_t)qmin;
-        woff[e] = pw;
-        pw += (orc_bise_bits(mode, n) + 31) / 32;
-    }
     if (pw > 0xFFFFFFFFll) status = -2;
     int64_t payload_words = pw + 2; /* >= 8 bytes of trailing slack */
     uint32_t* payload = (uint32_t*)calloc((size_t)payload_words, 4);
-    for (int64_t e = 0; e < nent && status == 0; e++) {
-        if (modes[e] == ORC_INSIGNIFICANT) continue;
-        const int32_t* q = qall + e * n;
-        uint32_t v[4096];
-        for (int i = 0; i < n; i++) v[i] = (uint32_t)(q[i] - mins[e]);
-        orc_bise_pack(v, n, modes[e], payload + woff[e]);
-        put32(table + e * 8, (uint32_t)woff[e]);
-        memcpy(table + e * 8 + 4, &mins[e], 2);
-        table[e * 8 + 6] = (uint8_t)modes[e];
-    }
+    for (int c = 0; c < 3 && status == 0; c++)
+        for (int64_t e0 = 0; e0 < n_nodes * S[c].nblk; e0++) {
+            const int n = S[c].n;
+            const int64_t e = tbase[c] + e0;
+            if (modes[e] == ORC_INSIGNIFICANT) continue;
+            const int32_t* q = S[c].q + e0 * n;
+            uint32_t v[4096];
+            for (int i = 0; i < n; i++) v[i] = (uint32_t)(q[i] - mins[e]);
+            orc_bise_pack(v, n, modes[e], payload + woff[e]);
+            put32(table + e * 8, (uint32_t)woff[e]);
+            memcpy(table + e * 8 + 4, &mins[e], 2);
+            table[e * 8 + 6] = (uint8_t)modes[e];
+        }
     for (int64_t e = 0; e < nent; e++)
         if (modes[e] == ORC_INSIGNIFICANT) table[e * 8 + 6] = ORC_INSIGNIFICANT;
 
@@ -575,32 +630,36 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
     int64_t mw = 0;
     for (int c = 0; c < 3; c++)
         for (int l = H - 1; l >= 0; l--) {
-            mv_mode[c][l] = choose_mode((uint32_t)(8 * p->win[l]), (int)(npred[l] > 0 ? 2 * npred[l] : 2));
+            const int64_t np = S[c].npred[l];
+            mv_mode[c][l] = choose_mode((uint32_t)(8 * p->win[l]), (int)(np > 0 ? 2 * np : 2));
             mv_word[c][l] = (uint32_t)mw;
-            mw += (orc_bise_bits(mv_mode[c][l], (int)(2 * npred[l])) + 31) / 32;
+            mw += (orc_bise_bits(mv_mode[c][l], (int)(2 * np)) + 31) / 32;
             sig_word[c][l] = (uint32_t)mw;
-            mw += (2 * npred[l] + 31) / 32;
+            mw += (2 * np + 31) / 32;
         }
     int64_t mv_words = mw + 2;
     uint32_t* mvsec = (uint32_t*)calloc((size_t)mv_words, 4);
     for (int c = 0; c < 3; c++)
         for (int l = 0; l < H; l++) {
-            if (npred[l] == 0) continue;
-            uint32_t* vals = (uint32_t*)malloc(sizeof(uint32_t) * 2 * npred[l]);
-            for (int64_t j = 0; j < npred[l]; j++) {
-                int mxv = mvs[c][l][j].mx + 4 * p->win[l], myv = mvs[c][l][j].my + 4 * p->win[l];
+            const int64_t np = S[c].npred[l];
+            if (np == 0) continue;
+            uint32_t* vals = (uint32_t*)malloc(sizeof(uint32_t) * 2 * np);
+            for (int64_t j = 0; j < np; j++) {
+                const mvrec* m = &S[c].mvs[l][j];
+                int mxv = m->mx + 4 * p->win[l], myv = m->my + 4 * p->win[l];
                 if (mxv < 0 || myv < 0 || mxv > 8 * p->win[l] || myv > 8 * p->win[l]) status = -3;
                 vals[2 * j] = (uint32_t)mxv;
                 vals[2 * j + 1] = (uint32_t)myv;
-                uint32_t code = mvs[c][l][j].sigma == 1 ? 0u : (mvs[c][l][j].sigma == -1 ? 1u : 2u);
+                uint32_t code = m->sigma == 1 ? 0u : (m->sigma == -1 ? 1u : 2u);
                 write_bits(mvsec + sig_word[c][l], 2 * j, 2, code);
             }
-            orc_bise_pack(vals, (int)(2 * npred[l]), mv_mode[c][l], mvsec + mv_word[c][l]);
+            orc_bise_pack(vals, (int)(2 * np), mv_mode[c][l], mvsec + mv_word[c][l]);
             free(vals);
         }
 
     /* 6. assemble: header, root, table, payload, mv */
-    int64_t root_bytes = (int64_t)3 * na_l[H] * nb_l[H] * plane * 2;
+    int64_t root_bytes = 0;
+    for (int c = 0; c < 3; c++) root_bytes += (int64_t)na_l[H] * nb_l[H] * S[c].plane * 2;
     int64_t off_root = ORC_HDR_BYTES;
     int64_t off_table = off_root + root_bytes;
     int64_t off_payload = off_table + nent * 8;
@@ -629,23 +688,28 @@ int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params
             uint8_t* d = s + 176 + (c * ORC_MAX_LEVELS + l) * 16;
             put32(d, mv_word[c][l]);
             put32(d + 4, sig_word[c][l]);
-            put32(d + 8, (uint32_t)npred[l]);
+            put32(d + 8, (uint32_t)S[c].npred[l]);
             d[12] = (uint8_t)mv_mode[c][l];
         }
-    /* root: the level-H representative key views, stored losslessly */
+    put32(s + ORC_HDR_CHROMA, (uint32_t)c420);
+    /* root: the level-H representative key views of each channel, stored losslessly */
     int16_t* root = (int16_t*)(s + off_root);
-    for (int64_t i = 0; i < (int64_t)3 * na_l[H] * nb_l[H] * plane; i++) {
-        if (I[H][i] < -32768 || I[H][i] > 32767) status = -2;
-        root[i] = (int16_t)I[H][i];
+    for (int c = 0; c < 3; c++) {
+        const int64_t cnt = (int64_t)na_l[H] * nb_l[H] * S[c].plane;
+        for (int64_t i = 0; i < cnt; i++) {
+            if (S[c].I[H][i] < -32768 || S[c].I[H][i] > 32767) status = -2;
+            *root++ = (int16_t)S[c].I[H][i];
+        }
     }
     memcpy(s + off_table, table, (size_t)nent * 8);
     memcpy(s + off_payload, payload, (size_t)payload_words * 4);
     memcpy(s + off_mv, mvsec, (size_t)mv_words * 4);
 
-    for (int l = 0; l <= H; l++) free(I[l]);
-    for (int l = 0; l < H; l++)
-        for (int c = 0; c < 3; c++) free(mvs[c][l]);
-    free(qall);
+    for (int c = 0; c < 3; c++) {
+        for (int l = 0; l <= H; l++) free(S[c].I[l]);
+        for (int l = 0; l < H; l++) free(S[c].mvs[l]);
+        free(S[c].q);
+    }
     free(table);
     free(modes);
     free(mins);
@@ -698,11 +762,26 @@ int orc_open(const uint8_t* st, size_t len, orc_lf** out)
     lf->nbx = lf->w / lf->bs;
     lf->nby = lf->h / lf->bs;
     lf->nblk = lf->nbx * lf->nby;
+    lf->chroma420 = (int)get32(st + ORC_HDR_CHROMA);
+    if (lf->chroma420 > 1 || (lf->chroma420 && (lf->w % (2 * lf->bs) || lf->h % (2 * lf->bs)))) {
+        free(lf);
+        return -3;
+    }
+    int64_t tb_expect = 0, rb_expect = 0;
+    for (int c = 0; c < 3; c++) {
+        channel_dims(lf->w, lf->h, lf->chroma420, c, &lf->cw[c], &lf->ch[c]);
+        lf->cnbx[c] = lf->cw[c] / lf->bs;
+        lf->cnblk[c] = lf->cnbx[c] * (lf->ch[c] / lf->bs);
+        lf->tbase[c] = tb_expect;
+        lf->rbase[c] = rb_expect;
+        tb_expect += lf->n_nodes * lf->cnblk[c];
+        rb_expect += (int64_t)lf->na_l[lf->H] * lf->nb_l[lf->H] * lf->cw[c] * lf->ch[c];
+    }
     uint64_t ro = get64(st + 112), rb = get64(st + 120), to = get64(st + 128), tb = get64(st + 136);
     uint64_t po = get64(st + 144), pb = get64(st + 152), mo = get64(st + 160), mb = get64(st + 168);
     int64_t plane = (int64_t)lf->w * lf->h;
-    if (rb != (uint64_t)3 * lf->na_l[lf->H] * lf->nb_l[lf->H] * plane * 2 ||
-        tb != (uint64_t)3 * lf->n_nodes * lf->nblk * 8 || ro + rb > len || to + tb > len || po + pb > len ||
+    (void)plane;
+    if (rb != (uint64_t)rb_expect * 2 || tb != (uint64_t)tb_expect * 8 || ro + rb > len || to + tb > len || po + pb > len ||
         mo + mb > len || pb < 8 || mb < 8 || (po & 3) || (mo & 3) || (ro & 1)) {
         free(lf);
         return -3;
@@ -721,7 +800,7 @@ int orc_open(const uint8_t* st, size_t len, orc_lf** out)
             lf->sig_word[c][l] = get32(d + 4);
             lf->mv_count[c][l] = get32(d + 8);
             lf->mv_mode[c][l] = d[12];
-            int64_t expect = orc_pred_nodes(lf->na_l[l], lf->nb_l[l]) * lf->nblk;
+            int64_t expect = orc_pred_nodes(lf->na_l[l], lf->nb_l[l]) * lf->cnblk[c];
             if ((int64_t)lf->mv_count[c][l] != expect) {
                 free(lf);
                 return -3;
@@ -738,7 +817,7 @@ int orc_open(const uint8_t* st, size_t len, orc_lf** out)
         }
     lf->n_pred_total = sb;
     /* every block payload must lie inside the payload section */
-    for (int64_t e = 0; e < 3 * lf->n_nodes * lf->nblk; e++) {
+    for (int64_t e = 0; e < tb_expect; e++) {
         const uint8_t* t = lf->table + e * 8;
         int mode = t[6];
         if (mode == ORC_INSIGNIFICANT) continue;
@@ -770,6 +849,7 @@ void orc_info(const orc_lf* lf, int64_t* o)
     o[7] = lf->n_pred_total;
     o[8] = lf->na_l[lf->H];
     o[9] = lf->nb_l[lf->H];
+    o[10] = lf->chroma420;
 }
 
 /* ------------------------------------------------------------------ */
@@ -780,9 +860,9 @@ void orc_info(const orc_lf* lf, int64_t* o)
 int32_t orc_srv_value(const orc_lf* lf, int c, int l, int B, int A, int y, int x)
 {
     int64_t node = lf->node_base[l] + (int64_t)B * lf->na_l[l] + A;
-    int blk = (y / lf->bs) * lf->nbx + x / lf->bs;
+    int blk = (y / lf->bs) * lf->cnbx[c] + x / lf->bs;
     int i = (y % lf->bs) * lf->bs + x % lf->bs;
-    const uint8_t* t = lf->table + (((int64_t)c * lf->n_nodes + node) * lf->nblk + blk) * 8;
+    const uint8_t* t = lf->table + (lf->tbase[c] + node * lf->cnblk[c] + blk) * 8;
     int mode = t[6];
     if (mode == ORC_INSIGNIFICANT) return 0;
     int16_t mn;
@@ -793,7 +873,7 @@ int32_t orc_srv_value(const orc_lf* lf, int c, int l, int B, int A, int y, int x
 
 void orc_mv_record(const orc_lf* lf, int c, int l, int B, int A, int blk, int* mx, int* my, int* sigma)
 {
-    int64_t j = orc_pred_ordinal(lf->na_l[l], B, A) * lf->nblk + blk;
+    int64_t j = orc_pred_ordinal(lf->na_l[l], B, A) * lf->cnblk[c] + blk;
     int mode = lf->mv_mode[c][l];
     *mx = (int)orc_bise_get(lf->mv + lf->mv_word[c][l], mode, (int)(2 * j)) - 4 * lf->win[l];
     *my = (int)orc_bise_get(lf->mv + lf->mv_word[c][l], mode, (int)(2 * j + 1)) - 4 * lf->win[l];
@@ -804,16 +884,16 @@ void orc_mv_record(const orc_lf* lf, int c, int l, int B, int A, int blk, int* m
 int32_t orc_root_value(const orc_lf* lf, int c, int b, int a, int y, int x)
 {
     int Bh = b >> lf->H, Ah = a >> lf->H;
-    int64_t idx = (((int64_t)c * lf->nb_l[lf->H] + Bh) * lf->na_l[lf->H] + Ah) * lf->w * lf->h +
-                  (int64_t)y * lf->w + x;
+    int64_t idx = lf->rbase[c] + ((int64_t)Bh * lf->na_l[lf->H] + Ah) * lf->cw[c] * lf->ch[c] +
+                  (int64_t)y * lf->cw[c] + x;
     return lf->root[idx];
 }
 
 /* Reference-plane value with clamped coordinates, for re-compensation. */
 static int32_t ref_tap(const orc_lf* lf, int c, int l, int Br, int Ar, int y, int x)
 {
-    y = orc_clampi(y, 0, lf->h - 1);
-    x = orc_clampi(x, 0, lf->w - 1);
+    y = orc_clampi(y, 0, lf->ch[c] - 1);
+    x = orc_clampi(x, 0, lf->cw[c] - 1);
     return orc_srv_value(lf, c, l, Br, Ar, y, x);
 }
 
@@ -842,7 +922,7 @@ static int32_t decode_channel_lod(const orc_lf* lf, int c, int b, int a, int y, 
         int32_t r = orc_srv_value(lf, c, l, B, A, y, x);
         if ((A | B) & 1) {
             int mx, my, sg;
-            int blk = (y / lf->bs) * lf->nbx + x / lf->bs;
+            int blk = (y / lf->bs) * lf->cnbx[c] + x / lf->bs;
             orc_mv_record(lf, c, l, B, A, blk, &mx, &my, &sg);
             if (sg) r += sg * qpel_stream(lf, c, l, B & ~1, A & ~1, y, x, mx, my);
         }
@@ -851,9 +931,61 @@ static int32_t decode_channel_lod(const orc_lf* lf, int c, int b, int a, int y, 
     return v;
 }
 
+/* Channel c of full-resolution sample (y, x): luma, and chroma of a 4:4:4
+ * stream, directly; 4:2:0 chroma by the centred bilinear up-sampling of the
+ * four half-resolution samples around it (weights 9, 3, 3, 1 / 16). */
+static int32_t sample_channel(const orc_lf* lf, int c, int b, int a, int y, int x, int lod)
+{
+    if (c == 0 || !lf->chroma420) return decode_channel_lod(lf, c, b, a, y, x, lod);
+    const int hy = y >> 1, hx = x >> 1;
+    const int ry[2] = {(y & 1) ? hy : hy - 1, (y & 1) ? hy + 1 : hy};
+    const int rx[2] = {(x & 1) ? hx : hx - 1, (x & 1) ? hx + 1 : hx};
+    const int wy[2] = {(y & 1) ? 3 : 1, (y & 1) ? 1 : 3};
+    const int wx[2] = {(x & 1) ? 3 : 1, (x & 1) ? 1 : 3};
+    int32_t acc = 0;
+    for (int j = 0; j < 2; j++)
+        for (int i = 0; i < 2; i++) {
+            const int yy = orc_clampi(ry[j], 0, lf->ch[c] - 1), xx = orc_clampi(rx[i], 0, lf->cw[c] - 1);
+            acc += wy[j] * wx[i] * decode_channel_lod(lf, c, b, a, yy, xx, lod);
+        }
+    return orc_asr(acc + 8, 4);
+}
+
 static int32_t decode_channel(const orc_lf* lf, int c, int b, int a, int y, int x)
 {
-    return decode_channel_lod(lf, c, b, a, y, x, 0);
+    return sample_channel(lf, c, b, a, y, x, 0);
+}
+
+void orc_chroma_up(const int32_t* half, int w, int h, int32_t* full)
+{
+    const int hw = w / 2, hh = h / 2;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            const int hy = y >> 1, hx = x >> 1;
+            const int ry[2] = {(y & 1) ? hy : hy - 1, (y & 1) ? hy + 1 : hy};
+            const int rx[2] = {(x & 1) ? hx : hx - 1, (x & 1) ? hx + 1 : hx};
+            const int wy[2] = {(y & 1) ? 3 : 1, (y & 1) ? 1 : 3};
+            const int wx[2] = {(x & 1) ? 3 : 1, (x & 1) ? 1 : 3};
+            int32_t acc = 0;
+            for (int j = 0; j < 2; j++)
+                for (int i = 0; i < 2; i++)
+                    acc += wy[j] * wx[i] *
+                           half[(int64_t)orc_clampi(ry[j], 0, hh - 1) * hw + orc_clampi(rx[i], 0, hw - 1)];
+            full[(int64_t)y * w + x] = orc_asr(acc + 8, 4);
+        }
+}
+
+int orc_decode_channel_at(const orc_lf* lf, int c, int lod, const int32_t* coords, int64_t n, int32_t* out)
+{
+    if (c < 0 || c > 2 || lod < 0 || lod > lf->H) return -1;
+    for (int64_t k = 0; k < n; k++) {
+        const int32_t* q = coords + 4 * k;
+        if (q[0] < 0 || q[0] >= lf->nb || q[1] < 0 || q[1] >= lf->na || q[2] < 0 || q[2] >= lf->ch[c] || q[3] < 0 ||
+            q[3] >= lf->cw[c])
+            return -1;
+        out[k] = decode_channel_lod(lf, c, q[0], q[1], q[2], q[3], lod);
+    }
+    return 0;
 }
 
 /* Node images at level `level` (0 .. H): coords[k] = (B, A, y, x) with B, A
@@ -871,7 +1003,7 @@ int orc_decode_node(const orc_lf* lf, int level, const int32_t* coords, int64_t 
             continue;
         }
         int ch[3];
-        for (int c = 0; c < 3; c++) ch[c] = decode_channel_lod(lf, c, b, a, q[2], q[3], level);
+        for (int c = 0; c < 3; c++) ch[c] = sample_channel(lf, c, b, a, q[2], q[3], level);
         int r, g, bl;
         orc_ycocg_inv(ch[0], ch[1], ch[2], &r, &g, &bl);
         rgb[3 * k] = (uint8_t)(r < 0 ? 0 : (r > 255 ? 255 : r));
@@ -927,70 +1059,99 @@ int orc_decode_at(const orc_lf* lf, const int32_t* coords, int64_t n, uint8_t* r
 /* reference planes, and each view is the root plus the path sum.      */
 /* ------------------------------------------------------------------ */
 
+/* Decoded SRV planes of every node, channel by channel at the channel's
+ * resolution: channel c starts at sum over c' < c of n_nodes * w_c' * h_c'
+ * (for a 4:4:4 stream, [3][n_nodes][h][w]). */
+static int64_t srv_base(const orc_lf* lf, int c)
+{
+    int64_t b = 0;
+    for (int k = 0; k < c; k++) b += lf->n_nodes * (int64_t)lf->cw[k] * lf->ch[k];
+    return b;
+}
+
 int orc_decode_srv(const orc_lf* lf, int32_t* out)
 {
     const int bs = lf->bs, n = bs * bs;
-    const int64_t plane = (int64_t)lf->w * lf->h;
     uint32_t v[4096];
     /* pass 1: dequantised residual planes of every node */
-    for (int c = 0; c < 3; c++)
+    for (int c = 0; c < 3; c++) {
+        const int w = lf->cw[c];
+        const int64_t plane = (int64_t)w * lf->ch[c];
         for (int64_t node = 0; node < lf->n_nodes; node++) {
-            int32_t* dst = out + ((int64_t)c * lf->n_nodes + node) * plane;
+            int32_t* dst = out + srv_base(lf, c) + node * plane;
             int l = 0;
             while (l + 1 < lf->H && node < lf->node_base[l]) l++;
-            for (int k = 0; k < lf->nblk; k++) {
-                const uint8_t* t = lf->table + (((int64_t)c * lf->n_nodes + node) * lf->nblk + k) * 8;
+            for (int k = 0; k < lf->cnblk[c]; k++) {
+                const uint8_t* t = lf->table + (lf->tbase[c] + node * lf->cnblk[c] + k) * 8;
                 int mode = t[6];
                 int16_t mn;
                 memcpy(&mn, t + 4, 2);
                 if (mode != ORC_INSIGNIFICANT) orc_bise_unpack(lf->payload + get32(t), mode, n, v);
-                int by0 = (k / lf->nbx) * bs, bx0 = (k % lf->nbx) * bs;
+                int by0 = (k / lf->cnbx[c]) * bs, bx0 = (k % lf->cnbx[c]) * bs;
                 for (int i = 0; i < n; i++)
-                    dst[(int64_t)(by0 + i / bs) * lf->w + bx0 + i % bs] =
+                    dst[(int64_t)(by0 + i / bs) * w + bx0 + i % bs] =
                         mode == ORC_INSIGNIFICANT ? 0 : ((int32_t)mn + (int32_t)v[i]) * lf->step[l];
             }
         }
+    }
     /* pass 2: add the phase-signed prediction to predictive blocks */
-    for (int c = 0; c < 3; c++)
+    for (int c = 0; c < 3; c++) {
+        const int w = lf->cw[c], h = lf->ch[c];
+        const int64_t plane = (int64_t)w * h;
         for (int l = 0; l < lf->H; l++)
             for (int B = 0; B < lf->nb_l[l]; B++)
                 for (int A = 0; A < lf->na_l[l]; A++) {
                     if (!((A | B) & 1)) continue;
                     int64_t node = lf->node_base[l] + (int64_t)B * lf->na_l[l] + A;
                     int64_t rnode = lf->node_base[l] + (int64_t)(B & ~1) * lf->na_l[l] + (A & ~1);
-                    int32_t* dst = out + ((int64_t)c * lf->n_nodes + node) * plane;
-                    const int32_t* ref = out + ((int64_t)c * lf->n_nodes + rnode) * plane;
-                    for (int k = 0; k < lf->nblk; k++) {
+                    int32_t* dst = out + srv_base(lf, c) + node * plane;
+                    const int32_t* ref = out + srv_base(lf, c) + rnode * plane;
+                    for (int k = 0; k < lf->cnblk[c]; k++) {
                         int mx, my, sg;
                         orc_mv_record(lf, c, l, B, A, k, &mx, &my, &sg);
                         if (!sg) continue;
-                        int by0 = (k / lf->nbx) * bs, bx0 = (k % lf->nbx) * bs;
+                        int by0 = (k / lf->cnbx[c]) * bs, bx0 = (k % lf->cnbx[c]) * bs;
                         for (int y = by0; y < by0 + bs; y++)
                             for (int x = bx0; x < bx0 + bs; x++)
-                                dst[(int64_t)y * lf->w + x] += sg * orc_qpel(ref, lf->w, lf->h, y, x, mx, my);
+                                dst[(int64_t)y * w + x] += sg * orc_qpel(ref, w, h, y, x, mx, my);
                     }
                 }
+    }
     return 0;
 }
 
+/* Full decode, [3][nb][na][h][w] at full resolution: each channel's views
+ * at its own resolution (root + path sum of the SRV planes), 4:2:0 chroma
+ * then up-sampled. */
 int orc_decode_full_ycocg(const orc_lf* lf, int32_t* out)
 {
-    const int64_t plane = (int64_t)lf->w * lf->h;
-    int32_t* srv = (int32_t*)malloc(sizeof(int32_t) * 3 * lf->n_nodes * plane);
-    if (!srv) return -2;
+    const int64_t fplane = (int64_t)lf->w * lf->h;
+    int32_t* srv = (int32_t*)malloc(sizeof(int32_t) * srv_base(lf, 3));
+    int32_t* view = (int32_t*)malloc(sizeof(int32_t) * fplane);
+    if (!srv || !view) {
+        free(srv);
+        free(view);
+        return -2;
+    }
     orc_decode_srv(lf, srv);
-    for (int c = 0; c < 3; c++)
+    for (int c = 0; c < 3; c++) {
+        const int w = lf->cw[c];
+        const int64_t plane = (int64_t)w * lf->ch[c];
         for (int b = 0; b < lf->nb; b++)
             for (int a = 0; a < lf->na; a++) {
-                int32_t* dst = out + (((int64_t)c * lf->nb + b) * lf->na + a) * plane;
+                int32_t* dst = out + (((int64_t)c * lf->nb + b) * lf->na + a) * fplane;
+                int32_t* cv = (plane == fplane) ? dst : view;
                 for (int64_t px = 0; px < plane; px++)
-                    dst[px] = orc_root_value(lf, c, b, a, (int)(px / lf->w), (int)(px % lf->w));
+                    cv[px] = orc_root_value(lf, c, b, a, (int)(px / w), (int)(px % w));
                 for (int l = 0; l < lf->H; l++) {
                     int64_t node = lf->node_base[l] + (int64_t)(b >> l) * lf->na_l[l] + (a >> l);
-                    const int32_t* s = srv + ((int64_t)c * lf->n_nodes + node) * plane;
-                    for (int64_t px = 0; px < plane; px++) dst[px] += s[px];
+                    const int32_t* sv = srv + srv_base(lf, c) + node * plane;
+                    for (int64_t px = 0; px < plane; px++) cv[px] += sv[px];
                 }
+                if (cv != dst) orc_chroma_up(cv, lf->w, lf->h, dst);
             }
+    }
+    free(view);
     free(srv);
     return 0;
 }

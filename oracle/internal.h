@@ -10,13 +10,15 @@
  *   48  i32 step[8]             80  i32 win[8]
  *  112  u64 root_off, root_bytes, table_off, table_bytes, payload_off, payload_bytes, mv_off, mv_bytes
  *  176  mv directory [3][8] x 16 bytes: u32 mv_word, u32 sigma_word, u32 records, u8 mode, u8 pad[3]
- * Sections:
- *   root    int16 [3][nb_H][na_H][height][width]
- *   table   8-byte entries [3][n_nodes][n_blocks]: u32 payload word, i16 min, u8 mode, u8 0
+ *  560  u32 chroma format: 0 = every channel at full size, 1 = 4:2:0 (Co, Cg at width/2 x height/2)
+ * Sections (w_c x h_c and n_blocks_c: channel c's plane and block grid):
+ *   root    int16, per channel c: [nb_H][na_H][h_c][w_c]
+ *   table   8-byte entries, per channel c: [n_nodes][n_blocks_c]: u32 payload word, i16 min, u8 mode, u8 0
  *   payload u32 words (block payloads start on word boundaries), then >= 8 zero bytes
  *   mv      u32 words; per (channel, level): BISE motion vectors, then 2-bit phase codes
  */
 #define ORC_HDR_BYTES 1024
+#define ORC_HDR_CHROMA 560
 #define ORC_INSIGNIFICANT 0xFF
 
 struct orc_lf {
@@ -27,7 +29,11 @@ struct orc_lf {
     int na_l[ORC_MAX_LEVELS + 1], nb_l[ORC_MAX_LEVELS + 1];
     int64_t node_base[ORC_MAX_LEVELS];
     int64_t n_nodes;
-    int nbx, nby, nblk;
+    int nbx, nby, nblk;          /* luma (channel 0) block grid */
+    int chroma420;
+    int cw[3], ch[3], cnbx[3], cnblk[3]; /* per-channel plane and block grid */
+    int64_t tbase[3];            /* first table entry of each channel */
+    int64_t rbase[3];            /* first root sample of each channel */
     const int16_t* root;
     const uint8_t* table;
     const uint32_t* payload;

@@ -54,6 +54,7 @@ typedef struct {
     int32_t subpel;                   /* 1: quarter-pel refinement after integer search */
     int32_t zero_phase;               /* 1: also allow "no prediction" (sigma = 0)     */
     int32_t no_mc;                    /* 1: disable motion compensation (plain RLFC)   */
+    int32_t chroma420;                /* 1: Co and Cg coded at half width and height   */
 } orc_params;
 
 typedef struct orc_lf orc_lf;
@@ -77,6 +78,16 @@ void orc_bise_pack(const uint32_t* v, int n, int mode, uint32_t* words); /* word
 uint32_t orc_bise_get(const uint32_t* words, int mode, int i);   /* random access         */
 void orc_bise_unpack(const uint32_t* words, int mode, int n, uint32_t* v); /* sequential */
 
+/* 4:2:0 chroma (Compressing HMLFC tree: chroma channels are sub-sampled):
+ * the half-resolution plane is the 2x2 rounded mean, floor((sum + 2) / 4);
+ * decoding brings it back to full resolution with centred bilinear weights
+ * (sample (Y, X) sits at full-resolution position (2Y + 1/2, 2X + 1/2)):
+ * full-resolution row y reads half-resolution rows (y/2 - 1, y/2) with
+ * weights (1, 3) when y is even and (y/2, y/2 + 1) with (3, 1) when odd,
+ * clamped to the plane, columns likewise, (sum of w * v + 8) >> 4. */
+void orc_chroma_down(const int32_t* full, int w, int h, int32_t* half);
+void orc_chroma_up(const int32_t* half, int w, int h, int32_t* full);  /* w, h: full size */
+
 /* ---- encoder ---- */
 int orc_encode(const uint8_t* lf, int nb, int na, int h, int w, const orc_params* p,
                int nthreads, uint8_t** out, size_t* out_len);
@@ -85,8 +96,12 @@ void orc_free(void* p);
 /* ---- stream ---- */
 int orc_open(const uint8_t* stream, size_t len, orc_lf** out);  /* borrows stream */
 void orc_close(orc_lf* lf);
-/* na, nb, w, h, levels, block, n_nodes, n_pred_total, root_na, root_nb */
-void orc_info(const orc_lf* lf, int64_t* out10);
+/* na, nb, w, h, levels, block, n_nodes, n_pred_total, root_na, root_nb, chroma420 */
+void orc_info(const orc_lf* lf, int64_t* out11);
+/* decoded value of channel c at its own resolution (half size for 4:2:0
+ * chroma): coords[k] = (b, a, y, x) in that channel's plane; lod as in
+ * orc_decode_node (0: leaf views) */
+int orc_decode_channel_at(const orc_lf* lf, int c, int lod, const int32_t* coords, int64_t n, int32_t* out);
 
 /* ---- decoders ---- */
 int orc_decode_at(const orc_lf* lf, const int32_t* coords, int64_t n, uint8_t* rgb);

@@ -235,6 +235,7 @@ int orc_render_dense(const uint8_t* L, int nb, int na, int h, int w, const float
 
 int orc_footprint_bytes(const orc_lf* lf, const float* cams, int nv, int wo, int ho, double* out)
 {
+    if (lf->chroma420) return -4; /* full-size chroma planes only */
     const int64_t nent = 3 * lf->n_nodes * lf->nblk;
     const int64_t nroot = (int64_t)3 * lf->na_l[lf->H] * lf->nb_l[lf->H] * lf->nblk;
     uint8_t* pred = (uint8_t*)malloc((size_t)nent);
@@ -439,6 +440,7 @@ static void relaxed_ray(const relax_ctx* x, const float* cam, int wo, int ho, in
 
 int orc_export_params(const orc_lf* lf, float* residual, float* shift)
 {
+    if (lf->chroma420) return -4; /* full-size chroma planes only */
     const int64_t plane = (int64_t)lf->w * lf->h;
     for (int c = 0; c < 3; c++)
         for (int l = 0; l < lf->H; l++)
@@ -464,6 +466,7 @@ int orc_export_params(const orc_lf* lf, float* residual, float* shift)
 int orc_render_relaxed(const orc_lf* lf, const float* residual, const float* shift, const float* cams, int nv,
                        int wo, int ho, int nthreads, double* out)
 {
+    if (lf->chroma420) return -4; /* full-size chroma planes only */
     (void)nthreads;
     relax_ctx x = {lf, residual, shift, -1, 0, 0.0};
     const int64_t npix = (int64_t)wo * ho;
@@ -480,6 +483,7 @@ int orc_render_relaxed(const orc_lf* lf, const float* residual, const float* shi
 double orc_relaxed_loss(const orc_lf* lf, const float* residual, const float* shift, const float* cams, int nv,
                         int wo, int ho, const float* target, int nthreads)
 {
+    if (lf->chroma420) return NAN; /* full-size chroma planes only */
     (void)nthreads;
     relax_ctx x = {lf, residual, shift, -1, 0, 0.0};
     const int64_t npix = (int64_t)wo * ho;
@@ -515,6 +519,7 @@ int64_t orc_param_check(const orc_lf* lf, const float* residual, const float* sh
                         int wo, int ho, const float* target, int kind, int64_t index, double eps, double* fd,
                         double* fwd)
 {
+    if (lf->chroma420) return -4; /* full-size chroma planes only */
     const int64_t plane = (int64_t)lf->w * lf->h, npix = (int64_t)wo * ho;
     int c, l = 0, B, A, py = 0, px = 0, blk = 0;
     if (kind == 0) {
@@ -596,6 +601,7 @@ int64_t orc_param_check(const orc_lf* lf, const float* residual, const float* sh
 int orc_relaxed_grad(const orc_lf* lf, const float* residual, const float* shift, const float* cams, int nv, int wo,
                      int ho, const double* grad_out, double* g_res, double* g_shift)
 {
+    if (lf->chroma420) return -4; /* full-size chroma planes only */
     const int64_t plane = (int64_t)lf->w * lf->h, npix = (int64_t)wo * ho;
     const int64_t nviews = (int64_t)lf->na * lf->nb;
     double* gs = (double*)calloc((size_t)(nviews * plane * 3), sizeof(double)); /* [b][a][y][x][rgb] */

@@ -102,6 +102,7 @@ __global__ void k_export_shift(LfGeom g, LfPtrs p, int64_t n_rec, float2* __rest
 extern "C" lf_status lf_export_params(const lf_handle* h, float* d_residual, float* d_shift, void* stream)
 {
     if (!h || !d_residual || !d_shift) return lf_fail(LF_EINVAL, "null argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_export_params")) return cs;
     const LfGeom& g = h->L.g;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_export_residual, dim3(65536), dim3(256), 0, s, g, h->p, d_residual);
@@ -235,6 +236,7 @@ extern "C" lf_status lf_render_relaxed(const lf_handle* h, const float* d_residu
                                        void* stream)
 {
     if (!h || !d_residual || !d_shift || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_render_relaxed")) return cs;
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
     const int64_t total = (int64_t)n_views * width * height;
@@ -290,6 +292,7 @@ extern "C" lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, 
                                            int64_t* bytes)
 {
     if (!h || !bytes || n_views < 1 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_backward_workspace")) return cs;
     BwdLayout B;
     lf_status st = bwd_layout(h, n_views, width, height, &B);
     if (st != LF_OK) return st;
@@ -628,6 +631,7 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     if (!h || !d_residual || !d_shift || !d_cams || !d_grad_out || !d_grad_residual || !d_grad_shift || !d_workspace ||
         n_views < 1 || width < 1 || height < 1)
         return lf_fail(LF_EINVAL, "bad argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_render_backward")) return cs;
     const LfGeom& g = h->L.g;
     BwdLayout Bl;
     lf_status st = bwd_layout(h, n_views, width, height, &Bl);

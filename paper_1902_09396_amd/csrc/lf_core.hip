@@ -82,6 +82,12 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
         g.h > 16384)
         return lf_fail(LF_EFORMAT, "bad geometry");
     if (g.bs & (g.bs - 1)) return lf_fail(LF_EFORMAT, "block size %d is not a power of two", g.bs);
+    const uint32_t cf = rd32(s + LF_HDR_CHROMA);
+    if (cf > 1) return lf_fail(LF_EFORMAT, "unknown chroma format %u", cf);
+    if (cf == 1 && (g.w % (2 * g.bs) || g.h % (2 * g.bs)))
+        return lf_fail(LF_EFORMAT, "4:2:0 chroma planes are not whole blocks");
+    L->chroma420 = (int32_t)cf;
+    g.nch = cf ? 1 : 3;
     g.bsl = 0;
     while ((1 << g.bsl) < g.bs) g.bsl++;
     g.nbx = g.w / g.bs;
@@ -115,7 +121,26 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
         g.step[l] = st;
         g.bias[l] = 4 * wn;
     }
-    const int64_t plane = (int64_t)g.w * g.h;
+    // chroma geometry: the same tree at half width and height
+    LfGeom& gc = L->gc;
+    if (cf) {
+        gc = g;
+        gc.nch = 2;
+        gc.w = g.w / 2;
+        gc.h = g.h / 2;
+        gc.nbx = gc.w / g.bs;
+        gc.nblk = gc.nbx * (gc.h / g.bs);
+    }
+    // stream channel c: its geometry, its index there, first table entry and root sample
+    auto geo = [&](int c) -> LfGeom& { return (cf && c > 0) ? gc : g; };
+    auto local = [&](int c) { return (cf && c > 0) ? c - 1 : c; };
+    int64_t tfirst[3], rfirst[3], tb = 0, rb = 0;
+    for (int c = 0; c < 3; c++) {
+        tfirst[c] = tb;
+        rfirst[c] = rb;
+        tb += nodes * geo(c).nblk;
+        rb += (int64_t)g.root_na * g.root_nb * geo(c).w * geo(c).h;
+    }
     L->root_off = rd64(s + 112);
     L->root_bytes = rd64(s + 120);
     L->table_off = rd64(s + 128);
@@ -125,8 +150,7 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     L->mv_off = rd64(s + 160);
     L->mv_bytes = rd64(s + 168);
     const uint64_t N = n;
-    if (L->root_bytes != (uint64_t)(3 * (int64_t)g.root_na * g.root_nb * plane * 2) ||
-        L->table_bytes != (uint64_t)(3 * nodes * g.nblk * 8))
+    if (L->root_bytes != (uint64_t)(rb * 2) || L->table_bytes != (uint64_t)(tb * 8))
         return lf_fail(LF_EFORMAT, "section sizes do not match the geometry");
     struct {
         uint64_t o, b;
@@ -144,8 +168,9 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     const uint8_t* tab = s + L->table_off;
     for (int c = 0; c < 3; c++)
         for (int l = g.H - 1; l >= 0; l--) {
-            const int64_t first = ((int64_t)c * nodes + g.node_base[l]) * g.nblk;
-            const int64_t count = (int64_t)g.na_l[l] * g.nb_l[l] * g.nblk;
+            const int nblk = geo(c).nblk;
+            const int64_t first = tfirst[c] + (int64_t)g.node_base[l] * nblk;
+            const int64_t count = (int64_t)g.na_l[l] * g.nb_l[l] * nblk;
             for (int64_t e = first; e < first + count; e++) {
                 const uint8_t* t = tab + 8 * e;
                 const int mode = t[6];
@@ -166,22 +191,24 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     int64_t rec = 0;
     for (int c = 0; c < 3; c++)
         for (int l = g.H - 1; l >= 0; l--) {
+            LfGeom& gg = geo(c);
+            const int lc = local(c);
             const uint8_t* dd = s + 176 + (c * LF_MAX_LEVELS + l) * 16;
-            g.mv_word[c][l] = rd32(dd);
-            g.sig_word[c][l] = rd32(dd + 4);
+            gg.mv_word[lc][l] = rd32(dd);
+            gg.sig_word[lc][l] = rd32(dd + 4);
             uint32_t count = rd32(dd + 8);
-            g.mv_mode[c][l] = dd[12];
+            gg.mv_mode[lc][l] = dd[12];
             int64_t npn = (int64_t)(g.nb_l[l] / 2) * g.na_l[l] + (int64_t)((g.nb_l[l] + 1) / 2) * (g.na_l[l] / 2);
-            int64_t expect = npn * g.nblk;
+            int64_t expect = npn * gg.nblk;
             if ((int64_t)count != expect) return lf_fail(LF_EFORMAT, "motion record count mismatch");
             if (expect > 0) {
-                int m = g.mv_mode[c][l];
+                int m = gg.mv_mode[lc][l];
                 if ((m >> 5) > 2 || (m & 31) > 20) return lf_fail(LF_EFORMAT, "bad motion-vector mode");
-                if ((int64_t)g.mv_word[c][l] + (bise_bits_host(m, 2 * expect) + 31) / 32 + 1 > mwords ||
-                    (int64_t)g.sig_word[c][l] + (2 * expect + 31) / 32 + 1 > mwords)
+                if ((int64_t)gg.mv_word[lc][l] + (bise_bits_host(m, 2 * expect) + 31) / 32 + 1 > mwords ||
+                    (int64_t)gg.sig_word[lc][l] + (2 * expect + 31) / 32 + 1 > mwords)
                     return lf_fail(LF_EFORMAT, "motion-vector section out of range");
             }
-            g.rec_base[c][l] = rec;
+            gg.rec_base[lc][l] = rec;
             rec += expect;
         }
     L->n_rec = rec;
@@ -189,16 +216,31 @@ lf_status lf_parse(const uint8_t* s, size_t n, LfLayout* L)
     // aligned; desc holds one 16-byte block descriptor per (channel, node,
     // block), expanded from the table and motion vectors at load; the status
     // tail keeps the multi-word loads at the end of the last section inside
-    // the arena
+    // the arena.  4:2:0: [refs] holds the luma reference planes, then the
+    // chroma ones at a_refs_c, and there are no descriptors.
+    const int64_t plane = (int64_t)g.w * g.h;
     L->a_root = 0;
     L->a_table = align256(L->a_root + (int64_t)L->root_bytes);
     L->a_payload = align256(L->a_table + (int64_t)L->table_bytes);
     L->a_mv = align256(L->a_payload + (int64_t)L->payload_bytes);
     L->a_refs = align256(L->a_mv + (int64_t)L->mv_bytes);
-    L->a_desc = align256(L->a_refs + 3 * refs * plane * 2);
-    L->a_status = align256(L->a_desc + 3 * nodes * (int64_t)g.nblk * 16);
+    if (cf) {
+        L->a_refs_c = align256(L->a_refs + refs * plane * 2);
+        L->a_desc = align256(L->a_refs_c + 2 * refs * (int64_t)gc.w * gc.h * 2);
+        L->a_status = L->a_desc;
+    } else {
+        L->a_desc = align256(L->a_refs + 3 * refs * plane * 2);
+        L->a_status = align256(L->a_desc + 3 * nodes * (int64_t)g.nblk * 16);
+    }
     L->arena = L->a_status + 256;
     L->stream_bytes = (int64_t)n;
+    (void)rfirst;
+    return LF_OK;
+}
+
+lf_status lf_require_full_chroma(const lf_handle* h, const char* what)
+{
+    if (h && h->L.chroma420) return lf_fail(LF_EINVAL, "%s needs full-size chroma planes (a 4:4:4 stream)", what);
     return LF_OK;
 }
 
@@ -234,19 +276,41 @@ static lf_status lf_layout_sparse(const uint8_t* s, LfLayout* L)
     const LfGeom& g = L->g;
     L->n_tiles = lf_ref_slots(s, *L, nullptr);
     if (L->n_tiles > 0x7FFFFFFF) return lf_fail(LF_EFORMAT, "too many reference blocks");
-    L->sparse = 1;
+    L->sparse = LF_RES_TILES;
     L->a_slots = align256(L->a_refs + L->n_tiles * (int64_t)g.bs * g.bs * 2);
     L->a_desc = L->a_status = align256(L->a_slots + 3 * (int64_t)g.n_refs * g.nblk * 4);
     L->arena = L->a_status + 256;
     return LF_OK;
 }
 
+// Re-lay a parsed layout for CSR residency: [root][table][payload][mv]
+// [values][columns][row starts][status].  The
+// nonzero count is known only after decoding, so values and columns are
+// sized for every pixel of the significant reference blocks.
+static lf_status lf_layout_csr(const uint8_t* s, LfLayout* L)
+{
+    const LfGeom& g = L->g;
+    if (g.w > 65535) return lf_fail(LF_EINVAL, "CSR residency stores 16-bit columns");
+    L->nnz_bound = lf_ref_slots(s, *L, nullptr) * (int64_t)g.bs * g.bs;
+    if (L->nnz_bound > 0xFFFFFFF0ll) return lf_fail(LF_EFORMAT, "too many reference pixels for 32-bit row starts");
+    const int64_t rows = 3 * (int64_t)g.n_refs * g.h;
+    L->sparse = LF_RES_CSR;
+    L->a_cols = align256(L->a_refs + L->nnz_bound * 2);
+    L->a_rowptr = align256(L->a_cols + L->nnz_bound * 2);
+    L->a_desc = L->a_status = align256(L->a_rowptr + (rows + 1) * 4);
+    L->arena = L->a_status + 256;
+    return LF_OK;
+}
+
 static lf_status lf_parse_ex(const uint8_t* s, size_t n, int32_t flags, LfLayout* L)
 {
-    if (flags & ~LF_LOAD_SPARSE_REFS) return lf_fail(LF_EINVAL, "unknown load flags 0x%x", flags);
+    if ((flags & ~(LF_LOAD_SPARSE_REFS | LF_LOAD_CSR_REFS)) ||
+        (flags & (LF_LOAD_SPARSE_REFS | LF_LOAD_CSR_REFS)) == (LF_LOAD_SPARSE_REFS | LF_LOAD_CSR_REFS))
+        return lf_fail(LF_EINVAL, "unknown or conflicting load flags 0x%x", flags);
     lf_status st = lf_parse(s, n, L);
-    if (st != LF_OK || !(flags & LF_LOAD_SPARSE_REFS)) return st;
-    return lf_layout_sparse(s, L);
+    if (st != LF_OK || !flags) return st;
+    if (L->chroma420) return lf_fail(LF_EINVAL, "sparse reference residency needs full-size chroma planes");
+    return (flags & LF_LOAD_CSR_REFS) ? lf_layout_csr(s, L) : lf_layout_sparse(s, L);
 }
 
 extern "C" lf_status lf_query_arena_ex(const void* host_stream, size_t nbytes, int32_t flags, int64_t* arena_bytes)
@@ -282,7 +346,7 @@ __global__ void k_load_refs(LfGeom g, LfPtrs p, int16_t* __restrict__ refs, int*
 {
     bool bad = false;
     const int64_t plane = (int64_t)g.w * g.h;
-    const int64_t total = 3 * (int64_t)g.n_refs * plane;
+    const int64_t total = g.nch * (int64_t)g.n_refs * plane;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         int64_t px = t % plane;
         int64_t r = (t / plane) % g.n_refs;
@@ -328,6 +392,68 @@ __global__ void k_load_tiles(LfGeom g, LfPtrs p, int16_t* __restrict__ tiles, in
     if (bad) atomicOr(status, LF_ST_REF);
 }
 
+// Dequantised value of pixel (y, x) of reference plane rp (index into
+// [3][n_refs]) straight from the stream.
+__device__ __forceinline__ int lf_ref_value(const LfGeom& g, const LfPtrs& p, int64_t rp, int y, int x)
+{
+    const int c = (int)(rp / g.n_refs), r = (int)(rp % g.n_refs);
+    int l = 0;
+    while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
+    const int local = r - g.ref_base[l];
+    const int Bp = local / g.na_l[l + 1], Ap = local % g.na_l[l + 1];
+    const int node = g.node_base[l] + (2 * Bp) * g.na_l[l] + 2 * Ap;
+    return lf_residual(g, p, c, l, node, (y >> g.bsl) * g.nbx + (x >> g.bsl),
+                       ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1)));
+}
+
+// CSR residency, pass 1: nonzero pixels of every reference row (one wave per
+// row), range-checked like the dense planes.
+__global__ void __launch_bounds__(256) k_csr_count(LfGeom g, LfPtrs p, uint32_t* __restrict__ counts, int64_t rows,
+                                                   int* __restrict__ status)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row == 0 && threadIdx.x == 0) counts[rows] = 0;
+    if (row >= rows) return;
+    const int64_t rp = row / g.h;
+    const int y = (int)(row - rp * g.h);
+    uint32_t cnt = 0;
+    bool bad = false;
+    for (int x = lane; x < g.w; x += 64) {
+        const int v = lf_ref_value(g, p, rp, y, x);
+        cnt += v != 0;
+        bad |= v < -LF_REF_LIMIT || v > LF_REF_LIMIT;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0) counts[row] = cnt;
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(status, LF_ST_REF);
+}
+
+// CSR residency, pass 2: columns and values of every row's nonzero pixels in
+// increasing column order, from the row's start (one wave per row).
+__global__ void __launch_bounds__(256) k_csr_fill(LfGeom g, LfPtrs p, const uint32_t* __restrict__ rowptr,
+                                                  uint16_t* __restrict__ cols, int16_t* __restrict__ vals, int64_t rows)
+{
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= rows) return;
+    const int64_t rp = row / g.h;
+    const int y = (int)(row - rp * g.h);
+    uint32_t at = rowptr[row];
+    for (int x0 = 0; x0 < g.w; x0 += 64) {
+        const int x = x0 + lane;
+        const int v = x < g.w ? lf_ref_value(g, p, rp, y, x) : 0;
+        const uint64_t m = __ballot(v != 0);
+        if (v != 0) {
+            const uint32_t k = at + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            cols[k] = (uint16_t)x;
+            vals[k] = (int16_t)v;
+        }
+        at += (uint32_t)__popcll(m);
+    }
+}
+
 // Block descriptors of every (channel, node, block), BFS node order.  A
 // descriptor holds each vector component in 12 signed bits: a motion vector
 // beyond +-2047 quarter pixels (a stream can code one when 4W + 2047 is
@@ -370,7 +496,7 @@ __global__ void k_load_check(LfGeom g, LfPtrs p, int* __restrict__ status)
         const int b = (int)(view / g.na), a = (int)(view - (int64_t)b * g.na);
         const int y = (int)(px / g.w), x = (int)(px - (int64_t)y * g.w);
         for (int c = 0; c < 3; c++) {
-            const int v = lf_decode_channel<false>(g, p, c, b, a, y, x);
+            const int v = lf_decode_channel<LF_RES_DENSE>(g, p, c, b, a, y, x);
             bad |= v < -LF_SAMPLE_LIMIT || v > LF_SAMPLE_LIMIT;
         }
     }
@@ -410,9 +536,21 @@ extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbyte
     h->p.payload = (const uint32_t*)(A + L.a_payload);
     h->p.mv = (const uint32_t*)(A + L.a_mv);
     h->p.refs = (const int16_t*)(A + L.a_refs);
-    h->p.desc = L.sparse ? nullptr : (const uint4*)(A + L.a_desc);
-    h->p.slots = L.sparse ? (const int32_t*)(A + L.a_slots) : nullptr;
-    const int64_t total = 3 * (int64_t)L.g.n_refs * L.g.w * L.g.h;
+    h->p.desc = (L.sparse || L.chroma420) ? nullptr : (const uint4*)(A + L.a_desc);
+    h->p.slots = L.sparse == LF_RES_TILES ? (const int32_t*)(A + L.a_slots) : nullptr;
+    h->p.rowptr = L.sparse == LF_RES_CSR ? (const uint32_t*)(A + L.a_rowptr) : nullptr;
+    h->p.cols = L.sparse == LF_RES_CSR ? (const uint16_t*)(A + L.a_cols) : nullptr;
+    h->pc = LfPtrs{};
+    if (L.chroma420) {
+        // chroma sections follow the luma ones inside the root and table
+        const int64_t luma_root = (int64_t)L.g.root_na * L.g.root_nb * L.g.w * L.g.h;
+        h->pc.root = h->p.root + luma_root;
+        h->pc.table = h->p.table + (int64_t)L.g.n_nodes * L.g.nblk;
+        h->pc.payload = h->p.payload;
+        h->pc.mv = h->p.mv;
+        h->pc.refs = (const int16_t*)(A + L.a_refs_c);
+    }
+    const int64_t total = L.g.nch * (int64_t)L.g.n_refs * L.g.w * L.g.h;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     int* status = (int*)(A + L.a_status);
@@ -421,7 +559,38 @@ extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbyte
         return lf_fail(LF_EDEVICE, "status clear failed");
     }
     std::vector<int32_t> slots;
-    if (L.sparse && total > 0) {
+    if (L.sparse == LF_RES_CSR && total > 0) {
+        // row counts on the device, row starts by a prefix sum on the host
+        // (load time only), then the columns and values
+        const int64_t rows = 3 * (int64_t)L.g.n_refs * L.g.h;
+        uint32_t* rowptr = (uint32_t*)(A + L.a_rowptr);
+        const unsigned rblocks = (unsigned)((rows + 3) / 4);
+        hipLaunchKernelGGL(k_csr_count, dim3(rblocks), dim3(256), 0, s, L.g, h->p, rowptr, rows, status);
+        std::vector<uint32_t> rp((size_t)rows + 1);
+        st = lf_check_launch("load_csr");
+        if (st == LF_OK && (hipMemcpyAsync(rp.data(), rowptr, rp.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                            hipStreamSynchronize(s) != hipSuccess))
+            st = lf_fail(LF_EDEVICE, "CSR row counts failed");
+        uint64_t run = 0;
+        for (size_t r = 0; r < rp.size() && st == LF_OK; r++) {
+            const uint32_t cnt = rp[r];
+            rp[r] = (uint32_t)run;
+            run += cnt;
+        }
+        if (st == LF_OK && (int64_t)run > L.nnz_bound) st = lf_fail(LF_EFORMAT, "more nonzero reference pixels than blocks hold");
+        if (st == LF_OK && hipMemcpyAsync(rowptr, rp.data(), rp.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            st = lf_fail(LF_EDEVICE, "CSR row starts upload failed");
+        if (st == LF_OK) {
+            hipLaunchKernelGGL(k_csr_fill, dim3(rblocks), dim3(256), 0, s, L.g, h->p, (const uint32_t*)rowptr,
+                               (uint16_t*)(A + L.a_cols), (int16_t*)h->p.refs, rows);
+            st = lf_check_launch("load_csr");
+        }
+        if (st != LF_OK) {
+            delete h;
+            return st;
+        }
+        h->L.nnz = (int64_t)run;
+    } else if (L.sparse && total > 0) {
         slots.resize((size_t)(3 * (int64_t)L.g.n_refs * L.g.nblk));
         lf_ref_slots(S, L, slots.data());
         if (hipMemcpyAsync(A + L.a_slots, slots.data(), slots.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess) {
@@ -438,13 +607,16 @@ extern "C" lf_status lf_load_compressed_ex(const void* host_stream, size_t nbyte
     } else if (total > 0) {
         hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.g, h->p, (int16_t*)h->p.refs,
                            status);
+        if (L.chroma420)
+            hipLaunchKernelGGL(k_load_refs, dim3((unsigned)blocks), dim3(256), 0, s, L.gc, h->pc,
+                               (int16_t*)h->pc.refs, status);
         st = lf_check_launch("load_refs");
         if (st != LF_OK) {
             delete h;
             return st;
         }
     }
-    if (!L.sparse) {
+    if (!L.sparse && !L.chroma420) {
         const int64_t nd = 3 * (int64_t)L.g.n_nodes * L.g.nblk;
         const int64_t dblocks = std::min<int64_t>((nd + 255) / 256, 65536);
         hipLaunchKernelGGL(k_load_desc, dim3((unsigned)dblocks), dim3(256), 0, s, L.g, h->p, (uint4*)(A + L.a_desc),
@@ -514,7 +686,11 @@ extern "C" lf_status lf_get_info(const lf_handle* h, lf_info* o)
     o->stream_bytes = h->L.stream_bytes;
     o->payload_bytes = (int64_t)h->L.payload_bytes;
     o->sparse_refs = h->L.sparse;
-    o->ref_bytes = h->L.sparse ? h->L.a_status - h->L.a_refs : h->L.a_desc - h->L.a_refs;
+    o->chroma420 = h->L.chroma420;
+    if (h->L.sparse == LF_RES_CSR)
+        o->ref_bytes = h->L.nnz * 4 + (3 * (int64_t)g.n_refs * g.h + 1) * 4;  // values, columns, row starts
+    else
+        o->ref_bytes = h->L.sparse ? h->L.a_status - h->L.a_refs : h->L.a_desc - h->L.a_refs;
     unsigned long long clamps = 0;
     if (hipMemcpy(&clamps, lf_clamp_counter(h), sizeof clamps, hipMemcpyDeviceToHost) != hipSuccess)
         return lf_fail(LF_EDEVICE, "reading the clamp counter failed");
@@ -533,7 +709,7 @@ __device__ __forceinline__ void lf_count_clamps(unsigned long long* counter, boo
     if (m && __lane_id() == (unsigned)(__ffsll((long long)m) - 1)) atomicAdd(counter, (unsigned long long)__popcll(m));
 }
 
-template <bool SPARSE>
+template <int RES>
 __global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ coords, int64_t n,
                                 uint8_t* __restrict__ rgb, unsigned long long* __restrict__ clamps)
 {
@@ -543,14 +719,47 @@ __global__ void k_decode_pixels(LfGeom g, LfPtrs p, const int32_t* __restrict__ 
     int b = lf_clampi(q.x, 0, g.nb - 1), a = lf_clampi(q.y, 0, g.na - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
     lf_count_clamps(clamps, b != q.x || a != q.y || y != q.z || x != q.w);
-    int Y = lf_decode_channel<SPARSE>(g, p, 0, b, a, y, x);
-    int Co = lf_decode_channel<SPARSE>(g, p, 1, b, a, y, x);
-    int Cg = lf_decode_channel<SPARSE>(g, p, 2, b, a, y, x);
+    int Y = lf_decode_channel<RES>(g, p, 0, b, a, y, x);
+    int Co = lf_decode_channel<RES>(g, p, 1, b, a, y, x);
+    int Cg = lf_decode_channel<RES>(g, p, 2, b, a, y, x);
     int r, gg, bl;
     lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
     rgb[3 * k] = (uint8_t)r;
     rgb[3 * k + 1] = (uint8_t)gg;
     rgb[3 * k + 2] = (uint8_t)bl;
+}
+
+// 4:2:0 streams: luma from the luma geometry, Co and Cg up-sampled from the
+// half-size chroma geometry; lod > 0 reads level-lod node images (B, A).
+__global__ void k_decode_pixels420(LfGeom g, LfPtrs p, LfGeom gc, LfPtrs pc, int lod,
+                                   const int32_t* __restrict__ coords, int64_t n, uint8_t* __restrict__ rgb,
+                                   unsigned long long* __restrict__ clamps)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int4 q = reinterpret_cast<const int4*>(coords)[k];
+    int B = lf_clampi(q.x, 0, g.nb_l[lod] - 1), A = lf_clampi(q.y, 0, g.na_l[lod] - 1);
+    int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
+    lf_count_clamps(clamps, B != q.x || A != q.y || y != q.z || x != q.w);
+    const int b = B << lod, a = A << lod;
+    int Y = lf_decode_channel(g, p, 0, b, a, y, x, lod);
+    int Co = lf_chroma_up(gc, pc, 0, b, a, y, x, lod);
+    int Cg = lf_chroma_up(gc, pc, 1, b, a, y, x, lod);
+    int r, gg, bl;
+    lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
+    rgb[3 * k] = (uint8_t)r;
+    rgb[3 * k + 1] = (uint8_t)gg;
+    rgb[3 * k + 2] = (uint8_t)bl;
+}
+
+static lf_status lf_launch_decode420(const lf_handle* h, int lod, const int32_t* d_coords, int64_t n, uint8_t* d_rgb,
+                                     void* stream)
+{
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
+    hipLaunchKernelGGL(k_decode_pixels420, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, h->L.g, h->p,
+                       h->L.gc, h->pc, lod, d_coords, n, d_rgb, lf_clamp_counter(h));
+    return lf_check_launch("decode_pixels");
 }
 
 extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coords, int64_t n, uint8_t* d_rgb,
@@ -560,15 +769,19 @@ extern "C" lf_status lf_decode_pixels(const lf_handle* h, const int32_t* d_coord
     if (n == 0) return LF_OK;
     if (!d_coords || !d_rgb) return lf_fail(LF_EINVAL, "null buffer");
     if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
+    if (h->L.chroma420) return lf_launch_decode420(h, 0, d_coords, n, d_rgb, stream);
     int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
-    hipLaunchKernelGGL(h->p.slots ? k_decode_pixels<true> : k_decode_pixels<false>, dim3((unsigned)blocks), dim3(256),
+    hipLaunchKernelGGL(h->L.sparse == LF_RES_CSR     ? k_decode_pixels<LF_RES_CSR>
+                       : h->L.sparse == LF_RES_TILES ? k_decode_pixels<LF_RES_TILES>
+                                                     : k_decode_pixels<LF_RES_DENSE>,
+                       dim3((unsigned)blocks), dim3(256),
                        0, (hipStream_t)stream, h->L.g, h->p, d_coords, n, d_rgb, lf_clamp_counter(h));
     return lf_check_launch("decode_pixels");
 }
 
 // Progressive decode: samples of the level-`lod` node images.
-template <bool SPARSE>
+template <int RES>
 __global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __restrict__ coords, int64_t n,
                                uint8_t* __restrict__ rgb, unsigned long long* __restrict__ clamps)
 {
@@ -578,9 +791,9 @@ __global__ void k_decode_nodes(LfGeom g, LfPtrs p, int lod, const int32_t* __res
     int B = lf_clampi(q.x, 0, g.nb_l[lod] - 1), A = lf_clampi(q.y, 0, g.na_l[lod] - 1);
     int y = lf_clampi(q.z, 0, g.h - 1), x = lf_clampi(q.w, 0, g.w - 1);
     lf_count_clamps(clamps, B != q.x || A != q.y || y != q.z || x != q.w);
-    int Y = lf_decode_channel<SPARSE>(g, p, 0, B << lod, A << lod, y, x, lod);
-    int Co = lf_decode_channel<SPARSE>(g, p, 1, B << lod, A << lod, y, x, lod);
-    int Cg = lf_decode_channel<SPARSE>(g, p, 2, B << lod, A << lod, y, x, lod);
+    int Y = lf_decode_channel<RES>(g, p, 0, B << lod, A << lod, y, x, lod);
+    int Co = lf_decode_channel<RES>(g, p, 1, B << lod, A << lod, y, x, lod);
+    int Cg = lf_decode_channel<RES>(g, p, 2, B << lod, A << lod, y, x, lod);
     int r, gg, bl;
     lf_ycocg_to_rgb(Y, Co, Cg, r, gg, bl);
     rgb[3 * k] = (uint8_t)r;
@@ -595,9 +808,13 @@ extern "C" lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, con
     if (n == 0) return LF_OK;
     if (!d_coords || !d_rgb) return lf_fail(LF_EINVAL, "null buffer");
     if (((uintptr_t)d_coords) & 15) return lf_fail(LF_EINVAL, "coords must be 16-byte aligned");
+    if (h->L.chroma420) return lf_launch_decode420(h, level, d_coords, n, d_rgb, stream);
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many samples");
-    hipLaunchKernelGGL(h->p.slots ? k_decode_nodes<true> : k_decode_nodes<false>, dim3((unsigned)blocks), dim3(256), 0,
+    hipLaunchKernelGGL(h->L.sparse == LF_RES_CSR     ? k_decode_nodes<LF_RES_CSR>
+                       : h->L.sparse == LF_RES_TILES ? k_decode_nodes<LF_RES_TILES>
+                                                     : k_decode_nodes<LF_RES_DENSE>,
+                       dim3((unsigned)blocks), dim3(256), 0,
                        (hipStream_t)stream, h->L.g, h->p, (int)level, d_coords, n, d_rgb, lf_clamp_counter(h));
     return lf_check_launch("decode_pixels_lod");
 }

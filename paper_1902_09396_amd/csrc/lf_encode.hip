@@ -32,6 +32,8 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <algorithm>
+
 #include "lf_internal.h"
 
 namespace {
@@ -121,21 +123,33 @@ __device__ uint32_t seq_word(const Val& val, int64_t n, int fam, int b, int64_t 
 // plan: level grids, entry counts and the workspace layout
 // ---------------------------------------------------------------------------
 
+// Channels coded at one plane size: all three, or for 4:2:0 chroma the luma
+// (group 0) and Co, Cg at half width and height (group 1).
+struct Group {
+    int nch, c0;  // channels, first stream channel
+    int w, h, nbx, nblk;
+    int64_t plane;
+    int64_t npred[kMaxLevels];     // predictive blocks per channel and level
+    int64_t rec_base[kMaxLevels];  // first motion record of each level, [channel][record] inside
+    int64_t ebase;                 // first table entry of the group
+    int64_t o_I[kMaxLevels + 1], o_shat;  // workspace: YCoCg planes per level, coded SRVs
+};
+
 struct Plan {
-    int H, bs, bsl, n, w, h, nbx, nblk, na, nb;
+    int H, bs, bsl, n, w, h, na, nb, c420, ngroups;
+    Group grp[2];
     int na_l[kMaxLevels + 1], nb_l[kMaxLevels + 1];
-    int64_t plane, views[kMaxLevels + 1], node_base[kMaxLevels], n_nodes, nent;
-    int64_t npred[kMaxLevels];  // predictive blocks per channel and level
-    int64_t rec_base[kMaxLevels], n_rec;  // motion records, [level][channel][record]
-    int64_t payload_bound;      // payload words without slack, upper bound
-    // motion-vector section (word offsets, modes), [channel][level]
+    int64_t views[kMaxLevels + 1], node_base[kMaxLevels], n_nodes, nent, n_rec;
+    int64_t payload_bound;  // payload words without slack, upper bound
+    // motion-vector section (word offsets, modes), [stream channel][level]
     uint32_t mv_word[3][kMaxLevels], sig_word[3][kMaxLevels];
     int mv_mode[3][kMaxLevels];
     int64_t mv_words;  // without slack
     int64_t n_tiles;   // prefix-sum tiles
     // workspace sections (byte offsets)
-    int64_t o_status, o_rgb, o_I[kMaxLevels + 1], o_shat, o_q, o_ext, o_wm, o_woff, o_table, o_tile, o_rec, o_items,
-        o_payload, o_mv, total;
+    int64_t o_status, o_rgb, o_q, o_ext, o_wm, o_woff, o_table, o_tile, o_rec, o_items, o_payload, o_mv, o_full,
+        total;
+    const Group& of(int c) const { return grp[(c420 && c > 0) ? 1 : 0]; }
 };
 
 constexpr int SCAN_PER_THREAD = 16, SCAN_THREADS = 256, SCAN_TILE = SCAN_PER_THREAD * SCAN_THREADS;
@@ -143,10 +157,13 @@ constexpr int SCAN_PER_THREAD = 16, SCAN_THREADS = 256, SCAN_TILE = SCAN_PER_THR
 lf_status make_plan(int32_t nb, int32_t na, int32_t h, int32_t w, const lf_encode_params* prm, Plan* P)
 {
     if (!prm) return lf_fail(LF_EINVAL, "null argument");
-    const int H = prm->levels, bs = prm->block;
+    const int H = prm->levels, bs = prm->block, c420 = prm->chroma420 != 0;
     if (H < 1 || H > kMaxLevels || bs < 1 || bs > 64 || (bs & (bs - 1)) || w < 1 || h < 1 || w % bs || h % bs ||
         na < 1 || nb < 1 || na > 4096 || nb > 4096 || w > 16384 || h > 16384)
         return lf_fail(LF_EINVAL, "bad geometry (block a power of two up to 64 dividing the image sides)");
+    if (c420 && (w % (2 * bs) || h % (2 * bs)))
+        return lf_fail(LF_EINVAL, "4:2:0 chroma needs image sides that are multiples of twice the block size");
+    if (prm->chroma420 < 0 || prm->chroma420 > 1) return lf_fail(LF_EINVAL, "chroma420 must be 0 or 1");
     for (int l = 0; l < H; l++)
         if (prm->step[l] < 1 || prm->step[l] > 4096 || prm->win[l] < 0 || prm->win[l] > 255)
             return lf_fail(LF_EINVAL, "bad step or window at level %d", l);
@@ -166,9 +183,8 @@ lf_status make_plan(int32_t nb, int32_t na, int32_t h, int32_t w, const lf_encod
     p.h = h;
     p.na = na;
     p.nb = nb;
-    p.nbx = w / bs;
-    p.nblk = p.nbx * (h / bs);
-    p.plane = (int64_t)w * h;
+    p.c420 = c420;
+    p.ngroups = c420 ? 2 : 1;
     p.na_l[0] = na;
     p.nb_l[0] = nb;
     for (int l = 1; l <= H; l++) {
@@ -180,29 +196,42 @@ lf_status make_plan(int32_t nb, int32_t na, int32_t h, int32_t w, const lf_encod
         p.node_base[l] = p.n_nodes;
         p.n_nodes += p.views[l];
     }
-    p.nent = 3 * p.n_nodes * p.nblk;
-    for (int l = 0; l < H; l++) {
-        // predictive nodes: every node of an odd row, odd columns of an even row
-        const int64_t pn = (int64_t)(p.nb_l[l] >> 1) * p.na_l[l] + (int64_t)((p.nb_l[l] + 1) >> 1) * (p.na_l[l] >> 1);
-        p.npred[l] = pn * p.nblk;
-        p.rec_base[l] = p.n_rec;
-        p.n_rec += 3 * p.npred[l];
+    int64_t items_max = 0;
+    for (int gi = 0; gi < p.ngroups; gi++) {
+        Group& G = p.grp[gi];
+        G.nch = c420 ? (gi == 0 ? 1 : 2) : 3;
+        G.c0 = gi == 0 ? 0 : 1;
+        G.w = gi == 0 ? w : w / 2;
+        G.h = gi == 0 ? h : h / 2;
+        G.nbx = G.w / bs;
+        G.nblk = G.nbx * (G.h / bs);
+        G.plane = (int64_t)G.w * G.h;
+        G.ebase = p.nent;
+        p.nent += G.nch * p.n_nodes * G.nblk;
+        for (int l = 0; l < H; l++) {
+            // predictive nodes: every node of an odd row, odd columns of an even row
+            const int64_t pn =
+                (int64_t)(p.nb_l[l] >> 1) * p.na_l[l] + (int64_t)((p.nb_l[l] + 1) >> 1) * (p.na_l[l] >> 1);
+            G.npred[l] = pn * G.nblk;
+            G.rec_base[l] = p.n_rec;
+            p.n_rec += G.nch * G.npred[l];
+        }
+        items_max = std::max(items_max, G.nch * G.npred[0]);
     }
-    if (3 * p.npred[0] > 0x7FFFFFF0ll) return lf_fail(LF_EINVAL, "too many blocks per level");
+    if (items_max > 0x7FFFFFF0ll) return lf_fail(LF_EINVAL, "too many blocks per level");
     // every quantised value fits int16 (checked), so a block never needs
     // more than 16 bits per value: the 16-bit plain family already fits
     p.payload_bound = p.nent * (((int64_t)16 * p.n + 31) / 32);
     int64_t mw = 0;
     for (int c = 0; c < 3; c++)
         for (int l = H - 1; l >= 0; l--) {
-            const int64_t nv = 2 * p.npred[l];
-            int64_t bits = 0;
+            const int64_t nv = 2 * p.of(c).npred[l];
             p.mv_mode[c][l] = pick_mode((uint32_t)(8 * prm->win[l]), nv > 0 ? nv : 2, nullptr);
-            bits = seq_bits(p.mv_mode[c][l] >> 5, p.mv_mode[c][l] & 31, nv);
+            const int64_t bits = seq_bits(p.mv_mode[c][l] >> 5, p.mv_mode[c][l] & 31, nv);
             p.mv_word[c][l] = (uint32_t)mw;
             mw += (bits + 31) / 32;
             p.sig_word[c][l] = (uint32_t)mw;
-            mw += (2 * p.npred[l] + 31) / 32;
+            mw += (nv + 31) / 32;
         }
     p.mv_words = mw;
     if (mw + 2 > 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "motion-vector section too large");
@@ -213,10 +242,11 @@ lf_status make_plan(int32_t nb, int32_t na, int32_t h, int32_t w, const lf_encod
         o = align256(o + bytes);
         return at;
     };
+    Group& G0 = p.grp[0];
     p.o_status = take(256);
-    p.o_rgb = take(p.views[0] * p.plane * 3);
-    for (int l = 0; l <= H; l++) p.o_I[l] = take(3 * p.views[l] * p.plane * 2);
-    p.o_shat = take(3 * p.views[0] * p.plane * 2);
+    p.o_rgb = take(p.views[0] * (int64_t)w * h * 3);
+    for (int l = 0; l <= H; l++) G0.o_I[l] = take(G0.nch * p.views[l] * G0.plane * 2);
+    G0.o_shat = take(G0.nch * p.views[0] * G0.plane * 2);
     p.o_q = take(p.nent * p.n * 2);
     p.o_ext = take(p.nent * 8);
     p.o_wm = take(p.nent * 4);
@@ -224,9 +254,15 @@ lf_status make_plan(int32_t nb, int32_t na, int32_t h, int32_t w, const lf_encod
     p.o_table = take(p.nent * 8);
     p.o_tile = take((p.n_tiles + 1) * 8);
     p.o_rec = take(p.n_rec * 16);
-    p.o_items = take(3 * p.npred[0] * 12);
+    p.o_items = take(items_max * 12);
     p.o_payload = take(p.payload_bound * 4);
     p.o_mv = take(p.mv_words * 4);
+    if (c420) {
+        Group& G1 = p.grp[1];
+        for (int l = 0; l <= H; l++) G1.o_I[l] = take(G1.nch * p.views[l] * G1.plane * 2);
+        G1.o_shat = take(G1.nch * p.views[0] * G1.plane * 2);
+        p.o_full = take(2 * p.views[0] * (int64_t)w * h * 2);  // full-size Co, Cg before sub-sampling
+    }
     p.total = o;
     return LF_OK;
 }
@@ -246,27 +282,49 @@ __global__ void k_enc_clear(int32_t* p, int n)
     if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
-// RGB uint8 [views][plane][3] -> YCoCg-R int16 [3][views][plane]:
+// RGB uint8 [views][plane][3] -> YCoCg-R int16 planes [views][plane] of Y,
+// Co and Cg (three destinations):
 // Co = R - B, t = B + (Co >> 1), Cg = G - t, Y = t + (Cg >> 1)
-__global__ void k_enc_colour(const uint8_t* __restrict__ rgb, int16_t* __restrict__ I0, int64_t npx)
+__global__ void k_enc_colour(const uint8_t* __restrict__ rgb, int16_t* __restrict__ Y, int16_t* __restrict__ Co,
+                             int16_t* __restrict__ Cg, int64_t npx)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npx; i += (int64_t)gridDim.x * blockDim.x) {
         const int r = rgb[3 * i], g = rgb[3 * i + 1], b = rgb[3 * i + 2];
         const int co = r - b;
         const int t = b + (co >> 1);
         const int cg = g - t;
-        I0[i] = (int16_t)(t + (cg >> 1));
-        I0[npx + i] = (int16_t)co;
-        I0[2 * npx + i] = (int16_t)cg;
+        Y[i] = (int16_t)(t + (cg >> 1));
+        Co[i] = (int16_t)co;
+        Cg[i] = (int16_t)cg;
+    }
+}
+
+// 4:2:0 chroma: each half-size sample is the rounded mean of its 2x2
+// full-size samples, floor((sum + 2) / 4); planes [n_planes][h][w] ->
+// [n_planes][h / 2][w / 2].
+__global__ void k_enc_chroma_down(const int16_t* __restrict__ full, int16_t* __restrict__ half, int64_t n_planes,
+                                  int w, int h)
+{
+    const int hw = w / 2, hh = h / 2;
+    const int64_t total = n_planes * hw * hh;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pl = i / ((int64_t)hw * hh), px = i - pl * hw * hh;
+        const int Y = (int)(px / hw), X = (int)(px - (int64_t)Y * hw);
+        const int16_t* f = full + pl * w * (int64_t)h + (int64_t)(2 * Y) * w + 2 * X;
+        const int num = f[0] + f[1] + f[w] + f[w + 1] + 2;
+        int q = num / 4;
+        if (q * 4 > num) q--;  // floor for negative sums
+        half[i] = (int16_t)q;
     }
 }
 
 // Level l+1 RKV: mean of the cluster's present members, rounded half up
 // (floor((sum + floor(m / 2)) / m) for m members).
-__global__ void k_enc_rkv(const int16_t* __restrict__ lo, int16_t* __restrict__ hi, int nal, int nbl, int nau, int nbu,
-                          int64_t plane)
+__global__ void k_enc_rkv(const int16_t* __restrict__ lo, int16_t* __restrict__ hi, int nch, int nal, int nbl, int nau,
+                          int nbu, int64_t plane)
 {
-    const int64_t total = 3 * (int64_t)nau * nbu * plane;
+    const int64_t total = nch * (int64_t)nau * nbu * plane;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t px = i % plane, node = i / plane;
@@ -289,10 +347,10 @@ __global__ void k_enc_rkv(const int16_t* __restrict__ lo, int16_t* __restrict__ 
 // sign -1 forms the SRVs (view - parent RKV), sign +1 the reconstruction
 // (parent RKV + coded SRV).
 // (dst may be a: each element is read before it is written, by one thread)
-__global__ void k_enc_parent(int16_t* dst, const int16_t* a, const int16_t* __restrict__ up,
-                             int sign, int nal, int nbl, int nau, int nbu, int64_t plane, int32_t* __restrict__ status)
+__global__ void k_enc_parent(int16_t* dst, const int16_t* a, const int16_t* __restrict__ up, int sign, int nch,
+                             int nal, int nbl, int nau, int nbu, int64_t plane, int32_t* __restrict__ status)
 {
-    const int64_t total = 3 * (int64_t)nal * nbl * plane;
+    const int64_t total = nch * (int64_t)nal * nbl * plane;
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -323,10 +381,10 @@ __device__ __forceinline__ void pred_node(int64_t ord, int nal, int* B, int* A)
     }
 }
 
-__global__ void k_enc_items(int32_t* __restrict__ items, int64_t npred, int nal, int nbl, int nblk)
+__global__ void k_enc_items(int32_t* __restrict__ items, int nch, int64_t npred, int nal, int nbl, int nblk)
 {
     const int64_t nv = (int64_t)nal * nbl;
-    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < 3 * npred;
+    for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < nch * npred;
          it += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(it / npred);
         const int64_t j = it - c * npred;
@@ -387,8 +445,8 @@ struct LevelArgs {
     int2* ext;          // per entry (min, max) of the quantised values
     int4* rec;          // motion records of the level [3][npred] (mx, my, sigma, cost)
     int32_t* status;
-    int64_t plane, npred, node_base, n_nodes;
-    int nal, nbl, nau, nbx, nblk, bs, bsl, n, w, h, step, thr, no_mc, bias;
+    int64_t plane, npred, node_base, n_nodes, ebase;
+    int nch, nal, nbl, nau, nbx, nblk, bs, bsl, n, w, h, step, thr, no_mc, bias;
 };
 
 // One wave64 per block: quantise (PRED: the residual after the phase-signed
@@ -401,7 +459,7 @@ __global__ void __launch_bounds__(256) k_enc_code(LevelArgs a)
     const int lane = threadIdx.x & 63;
     const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t nv = (int64_t)a.nal * a.nbl;
-    const int64_t items = PRED ? 3 * a.npred : 3 * (int64_t)a.nau * ((a.nbl + 1) >> 1) * a.nblk;
+    const int64_t items = PRED ? a.nch * a.npred : a.nch * (int64_t)a.nau * ((a.nbl + 1) >> 1) * a.nblk;
     if (it >= items) return;
     int c, B, A, k;
     int mx = 0, my = 0, sg = 0;
@@ -450,7 +508,7 @@ __global__ void __launch_bounds__(256) k_enc_code(LevelArgs a)
         energy += (int64_t)abs(value(i, &pr)) * a.step;
     }
     const bool keep = wave_sum64(energy) >= a.thr;
-    const int64_t entry = ((int64_t)c * a.n_nodes + a.node_base + v) * a.nblk + k;
+    const int64_t entry = a.ebase + ((int64_t)c * a.n_nodes + a.node_base + v) * a.nblk + k;
     int16_t* Q = a.q + entry * a.n;
     int qmin = 0x7FFFFFFF, qmax = -0x7FFFFFFF - 1;
     bool bad = false;
@@ -641,12 +699,14 @@ struct StreamHeader {
     uint32_t step[kMaxLevels], win[kMaxLevels];
     uint64_t root_off, root_bytes, table_off, table_bytes, payload_off, payload_bytes, mv_off, mv_bytes;
     MvDir dir[3][kMaxLevels];
-    uint8_t reserved[LF_HDR_BYTES - 560];
+    uint32_t chroma_format;  // 0: full-size chroma, 1: 4:2:0
+    uint8_t reserved[LF_HDR_BYTES - 564];
 };
 #pragma pack(pop)
 static_assert(sizeof(StreamHeader) == LF_HDR_BYTES, "header size");
 static_assert(offsetof(StreamHeader, step) == 48 && offsetof(StreamHeader, win) == 80, "header layout");
 static_assert(offsetof(StreamHeader, root_off) == 112 && offsetof(StreamHeader, dir) == 176, "header layout");
+static_assert(offsetof(StreamHeader, chroma_format) == LF_HDR_CHROMA, "header layout");
 
 }  // namespace
 
@@ -675,8 +735,7 @@ extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_
     hipStream_t s = (hipStream_t)stream;
     uint8_t* W = (uint8_t*)d_work;
     int32_t* status = (int32_t*)(W + p.o_status);
-    auto I = [&](int l) { return (int16_t*)(W + p.o_I[l]); };
-    int16_t* shat = (int16_t*)(W + p.o_shat);
+    auto I = [&](const Group& G, int l) { return (int16_t*)(W + G.o_I[l]); };
     int16_t* q = (int16_t*)(W + p.o_q);
     int2* ext = (int2*)(W + p.o_ext);
     uint32_t* wm = (uint32_t*)(W + p.o_wm);
@@ -687,68 +746,87 @@ extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_
     uint32_t* payload = (uint32_t*)(W + p.o_payload);
     uint32_t* mvsec = (uint32_t*)(W + p.o_mv);
     const unsigned T = 256;
-    const unsigned G = 8192;  // grid-stride kernels: 32 workgroups per CU
+    const unsigned GRID = 8192;  // grid-stride kernels: 32 workgroups per CU
+    const int64_t fplane = (int64_t)p.w * p.h, nv0 = p.views[0];
 
     hipLaunchKernelGGL(k_enc_clear, dim3(1), dim3(64), 0, s, status, 64);
-    if (hipMemcpyAsync(W + p.o_rgb, host_lf, (size_t)(p.views[0] * p.plane * 3), hipMemcpyHostToDevice, s) !=
-        hipSuccess)
+    if (hipMemcpyAsync(W + p.o_rgb, host_lf, (size_t)(nv0 * fplane * 3), hipMemcpyHostToDevice, s) != hipSuccess)
         return lf_fail(LF_EDEVICE, "upload failed");
-    hipLaunchKernelGGL(k_enc_colour, dim3(G), dim3(T), 0, s, (const uint8_t*)(W + p.o_rgb), I(0),
-                       p.views[0] * p.plane);
-    for (int l = 0; l < p.H; l++)
-        hipLaunchKernelGGL(k_enc_rkv, dim3(G), dim3(T), 0, s, (const int16_t*)I(l), I(l + 1), p.na_l[l], p.nb_l[l],
-                           p.na_l[l + 1], p.nb_l[l + 1], p.plane);
+    // colour transform; 4:2:0 chroma goes through a full-size buffer and the 2x2 mean
+    {
+        int16_t* y = I(p.grp[0], 0);
+        int16_t* co = p.c420 ? (int16_t*)(W + p.o_full) : y + nv0 * fplane;
+        int16_t* cg = co + nv0 * fplane;
+        hipLaunchKernelGGL(k_enc_colour, dim3(GRID), dim3(T), 0, s, (const uint8_t*)(W + p.o_rgb), y, co, cg,
+                           nv0 * fplane);
+        if (p.c420)
+            hipLaunchKernelGGL(k_enc_chroma_down, dim3(GRID), dim3(T), 0, s, (const int16_t*)co, I(p.grp[1], 0),
+                               2 * nv0, p.w, p.h);
+    }
+    for (int gi = 0; gi < p.ngroups; gi++) {
+        const Group& Gp = p.grp[gi];
+        for (int l = 0; l < p.H; l++)
+            hipLaunchKernelGGL(k_enc_rkv, dim3(GRID), dim3(T), 0, s, (const int16_t*)I(Gp, l), I(Gp, l + 1), Gp.nch,
+                               p.na_l[l], p.nb_l[l], p.na_l[l + 1], p.nb_l[l + 1], Gp.plane);
+    }
     if ((st = lf_check_launch("encode: hierarchy")) != LF_OK) return st;
 
-    // closed loop: I(l + 1) holds the reconstruction of level l + 1 (the
-    // root is lossless); I(l) becomes the SRVs, then the reconstruction
-    for (int l = p.H - 1; l >= 0; l--) {
-        const int nal = p.na_l[l], nbl = p.nb_l[l], nau = p.na_l[l + 1], nbu = p.nb_l[l + 1];
-        hipLaunchKernelGGL(k_enc_parent, dim3(G), dim3(T), 0, s, I(l), (const int16_t*)I(l), (const int16_t*)I(l + 1),
-                           -1, nal, nbl, nau, nbu, p.plane, status);
-        LevelArgs a;
-        a.S = I(l);
-        a.shat = shat;
-        a.q = q;
-        a.ext = ext;
-        a.rec = rec + p.rec_base[l];
-        a.status = status;
-        a.plane = p.plane;
-        a.npred = p.npred[l];
-        a.node_base = p.node_base[l];
-        a.n_nodes = p.n_nodes;
-        a.nal = nal;
-        a.nbl = nbl;
-        a.nau = nau;
-        a.nbx = p.nbx;
-        a.nblk = p.nblk;
-        a.bs = p.bs;
-        a.bsl = p.bsl;
-        a.n = p.n;
-        a.w = p.w;
-        a.h = p.h;
-        a.step = prm->step[l];
-        a.thr = prm->t_ref[l];
-        a.no_mc = prm->no_mc != 0;
-        a.bias = 4 * prm->win[l];
-        const int64_t nref_items = 3 * (int64_t)nau * ((nbl + 1) >> 1) * p.nblk;
-        hipLaunchKernelGGL(k_enc_code<false>, dim3(grid_for(nref_items, 4)), dim3(256), 0, s, a);
-        const int64_t npi = 3 * p.npred[l];
-        if (npi > 0) {
-            if (!prm->no_mc) {
-                hipLaunchKernelGGL(k_enc_items, dim3(grid_for(npi, T)), dim3(T), 0, s, items, p.npred[l], nal, nbl,
-                                   p.nblk);
-                const int64_t nv = 3 * (int64_t)nal * nbl;
-                st = lf_search_launch(I(l), shat, nv, nv, p.w, p.h, p.bs, prm->win[l], prm->subpel, prm->zero_phase,
-                                      items, npi, (int32_t*)a.rec, stream);
-                if (st != LF_OK) return st;
+    // closed loop, per channel group: I(l + 1) holds the reconstruction of
+    // level l + 1 (the root is lossless); I(l) becomes the SRVs, then the
+    // reconstruction
+    for (int gi = 0; gi < p.ngroups; gi++) {
+        const Group& Gp = p.grp[gi];
+        int16_t* shat = (int16_t*)(W + Gp.o_shat);
+        for (int l = p.H - 1; l >= 0; l--) {
+            const int nal = p.na_l[l], nbl = p.nb_l[l], nau = p.na_l[l + 1], nbu = p.nb_l[l + 1];
+            hipLaunchKernelGGL(k_enc_parent, dim3(GRID), dim3(T), 0, s, I(Gp, l), (const int16_t*)I(Gp, l),
+                               (const int16_t*)I(Gp, l + 1), -1, Gp.nch, nal, nbl, nau, nbu, Gp.plane, status);
+            LevelArgs a;
+            a.S = I(Gp, l);
+            a.shat = shat;
+            a.q = q;
+            a.ext = ext;
+            a.rec = rec + Gp.rec_base[l];
+            a.status = status;
+            a.plane = Gp.plane;
+            a.npred = Gp.npred[l];
+            a.node_base = p.node_base[l];
+            a.n_nodes = p.n_nodes;
+            a.ebase = Gp.ebase;
+            a.nch = Gp.nch;
+            a.nal = nal;
+            a.nbl = nbl;
+            a.nau = nau;
+            a.nbx = Gp.nbx;
+            a.nblk = Gp.nblk;
+            a.bs = p.bs;
+            a.bsl = p.bsl;
+            a.n = p.n;
+            a.w = Gp.w;
+            a.h = Gp.h;
+            a.step = prm->step[l];
+            a.thr = prm->t_ref[l];
+            a.no_mc = prm->no_mc != 0;
+            a.bias = 4 * prm->win[l];
+            const int64_t nref_items = Gp.nch * (int64_t)nau * ((nbl + 1) >> 1) * Gp.nblk;
+            hipLaunchKernelGGL(k_enc_code<false>, dim3(grid_for(nref_items, 4)), dim3(256), 0, s, a);
+            const int64_t npi = Gp.nch * Gp.npred[l];
+            if (npi > 0) {
+                if (!prm->no_mc) {
+                    hipLaunchKernelGGL(k_enc_items, dim3(grid_for(npi, T)), dim3(T), 0, s, items, Gp.nch, Gp.npred[l],
+                                       nal, nbl, Gp.nblk);
+                    const int64_t nv = Gp.nch * (int64_t)nal * nbl;
+                    st = lf_search_launch(I(Gp, l), shat, nv, nv, Gp.w, Gp.h, p.bs, prm->win[l], prm->subpel,
+                                          prm->zero_phase, items, npi, (int32_t*)a.rec, stream);
+                    if (st != LF_OK) return st;
+                }
+                a.thr = prm->t_pred[l];
+                hipLaunchKernelGGL(k_enc_code<true>, dim3(grid_for(npi, 4)), dim3(256), 0, s, a);
             }
-            a.thr = prm->t_pred[l];
-            hipLaunchKernelGGL(k_enc_code<true>, dim3(grid_for(npi, 4)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_enc_parent, dim3(GRID), dim3(T), 0, s, I(Gp, l), (const int16_t*)shat,
+                               (const int16_t*)I(Gp, l + 1), 1, Gp.nch, nal, nbl, nau, nbu, Gp.plane, status);
+            if ((st = lf_check_launch("encode: level")) != LF_OK) return st;
         }
-        hipLaunchKernelGGL(k_enc_parent, dim3(G), dim3(T), 0, s, I(l), (const int16_t*)shat, (const int16_t*)I(l + 1),
-                           1, nal, nbl, nau, nbu, p.plane, status);
-        if ((st = lf_check_launch("encode: level")) != LF_OK) return st;
     }
 
     // block payloads: word counts, offsets, table, packing
@@ -763,12 +841,13 @@ extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_
                        (const int64_t*)woff, (const int2*)ext, (uint2*)(W + p.o_table), p.nent);
     hipLaunchKernelGGL(k_enc_pack, dim3((unsigned)p.nent), dim3(64), (size_t)p.n * 4, s, (const int16_t*)q,
                        (const uint32_t*)wm, (const int64_t*)woff, (const int2*)ext, payload, p.n);
-    // motion vectors, [channel][level H-1 .. 0]
+    // motion vectors, [stream channel][level H-1 .. 0]
     for (int c = 0; c < 3; c++)
         for (int l = p.H - 1; l >= 0; l--) {
-            const int64_t nrec = p.npred[l];
+            const Group& Gp = p.of(c);
+            const int64_t nrec = Gp.npred[l];
             if (nrec == 0) continue;
-            const int4* r = rec + p.rec_base[l] + c * nrec;
+            const int4* r = rec + Gp.rec_base[l] + (c - Gp.c0) * nrec;
             const int mode = p.mv_mode[c][l];
             const int64_t mvw = (seq_bits(mode >> 5, mode & 31, 2 * nrec) + 31) / 32;
             if (mvw > 0)
@@ -808,8 +887,11 @@ extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_
         hd.step[l] = (uint32_t)prm->step[l];
         hd.win[l] = (uint32_t)prm->win[l];
     }
+    hd.chroma_format = (uint32_t)p.c420;
     hd.root_off = LF_HDR_BYTES;
-    hd.root_bytes = (uint64_t)(3 * p.views[p.H] * p.plane * 2);
+    uint64_t group_root[2] = {0, 0};
+    for (int gi = 0; gi < p.ngroups; gi++) group_root[gi] = (uint64_t)(p.grp[gi].nch * p.views[p.H] * p.grp[gi].plane * 2);
+    hd.root_bytes = group_root[0] + group_root[1];
     hd.table_off = hd.root_off + hd.root_bytes;
     hd.table_bytes = (uint64_t)p.nent * 8;
     hd.payload_off = hd.table_off + hd.table_bytes;
@@ -820,14 +902,17 @@ extern "C" lf_status lf_encode_device(const uint8_t* host_lf, int32_t nb, int32_
         for (int l = 0; l < p.H; l++) {
             hd.dir[c][l].mv_word = p.mv_word[c][l];
             hd.dir[c][l].sig_word = p.sig_word[c][l];
-            hd.dir[c][l].count = (uint32_t)p.npred[l];
+            hd.dir[c][l].count = (uint32_t)p.of(c).npred[l];
             hd.dir[c][l].mode = (uint8_t)p.mv_mode[c][l];
         }
     const size_t total = (size_t)(hd.mv_off + hd.mv_bytes);
     uint8_t* out = (uint8_t*)calloc(total, 1);
     if (!out) return lf_fail(LF_ENOMEM, "out of host memory");
     memcpy(out, &hd, sizeof hd);
-    const bool ok = hipMemcpyAsync(out + hd.root_off, I(p.H), hd.root_bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+    const bool ok = hipMemcpyAsync(out + hd.root_off, I(p.grp[0], p.H), group_root[0], hipMemcpyDeviceToHost, s) ==
+                        hipSuccess &&
+                    (!p.c420 || hipMemcpyAsync(out + hd.root_off + group_root[0], I(p.grp[1], p.H), group_root[1],
+                                               hipMemcpyDeviceToHost, s) == hipSuccess) &&
                     hipMemcpyAsync(out + hd.table_off, W + p.o_table, hd.table_bytes, hipMemcpyDeviceToHost, s) ==
                         hipSuccess &&
                     (pwords == 0 || hipMemcpyAsync(out + hd.payload_off, payload, (size_t)pwords * 4,

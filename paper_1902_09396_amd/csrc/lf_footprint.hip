@@ -110,6 +110,7 @@ extern "C" lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams,
                                         int32_t height, double* host_out, void* stream)
 {
     if (!h || !d_cams || !host_out || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_footprint_bytes")) return cs;
     const LfGeom& g = h->L.g;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n_ent = 3 * (int64_t)g.n_nodes * g.nblk;

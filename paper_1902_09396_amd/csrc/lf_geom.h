@@ -12,10 +12,12 @@
 
 #define LF_MAX_LEVELS 8
 #define LF_HDR_BYTES 1024
+#define LF_HDR_CHROMA 560  // u32 chroma format: 0 full-size chroma, 1 4:2:0
 #define LF_MODE_ZERO 0xFF
 
 struct LfGeom {
     int na, nb, w, h, H, bs, nbx, nblk;
+    int nch;  // channels this geometry holds: 3, or 1 (luma) and 2 (Co, Cg at half size) for 4:2:0
     int bsl;  // log2 of the block size (a power of two)
     int na_l[LF_MAX_LEVELS + 1], nb_l[LF_MAX_LEVELS + 1];
     int node_base[LF_MAX_LEVELS];  // first BFS node index of each level
@@ -40,7 +42,15 @@ struct LfPtrs {
     const uint4* desc;        // [3][n_nodes][nblk] block descriptors (lf_make_desc), built at load (dense only)
     const int32_t* slots;     // sparse: [3][n_refs][nblk] tile of each reference block, -1 = zero block;
                               // null for dense planes
+    const uint32_t* rowptr;   // CSR: first nonzero of every reference row [3][n_refs][h], then the count
+    const uint16_t* cols;     // CSR: column of every nonzero, increasing within a row (values in refs)
 };
+
+// Reference residency: dense int16 planes, block-sparse tiles, or
+// per-pixel compressed sparse rows.
+#define LF_RES_DENSE 0
+#define LF_RES_TILES 1
+#define LF_RES_CSR 2
 
 // Ordinal of predictive node (B, A) among the predictive nodes of its level,
 // raster order: rows with odd B are entirely predictive, rows with even B
@@ -111,30 +121,44 @@ __device__ __forceinline__ void lf_motion(const LfGeom& g, const LfPtrs& p, int 
 __device__ __forceinline__ int lf_clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // Pixel (y, x) of reference plane rp (index into [3][n_refs]).  Dense
-// residency reads the plane; sparse residency (the paper's reduced-memory
-// reference storage, Decompression Analysis) reads the tile of the pixel's
-// block, a zero block having no tile.
-template <bool SPARSE>
+// residency reads the plane; block-sparse residency (the paper's
+// reduced-memory reference storage, Decompression Analysis) reads the tile of
+// the pixel's block, a zero block having no tile; CSR residency (the paper's
+// sparse matrix, per pixel) binary-searches the row's nonzero columns.
+template <int RES>
 __device__ __forceinline__ int lf_ref_tap(const LfGeom& g, const LfPtrs& p, uint32_t rp, int y, int x)
 {
-    if (!SPARSE) return p.refs[(size_t)rp * (size_t)(g.w * g.h) + y * g.w + x];
-    const int t = p.slots[(size_t)rp * g.nblk + (y >> g.bsl) * g.nbx + (x >> g.bsl)];
-    return t < 0 ? 0 : p.refs[((size_t)t << (2 * g.bsl)) + (((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1)))];
+    if (RES == LF_RES_DENSE) return p.refs[(size_t)rp * (size_t)(g.w * g.h) + y * g.w + x];
+    if (RES == LF_RES_TILES) {
+        const int t = p.slots[(size_t)rp * g.nblk + (y >> g.bsl) * g.nbx + (x >> g.bsl)];
+        return t < 0 ? 0 : p.refs[((size_t)t << (2 * g.bsl)) + (((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1)))];
+    }
+    const size_t row = (size_t)rp * g.h + y;
+    const uint32_t end = p.rowptr[row + 1];
+    uint32_t lo = p.rowptr[row], hi = end;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((int)p.cols[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return (lo < end && (int)p.cols[lo] == x) ? p.refs[lo] : 0;
 }
 
 // Quarter-pel bilinear prediction from reference plane rp, taps clamped to
 // the plane, rounded as (sum w * tap + 8) >> 4 with weights (4 - fx)(4 - fy),
 // fx(4 - fy), (4 - fx)fy, fx fy.
-template <bool SPARSE>
+template <int RES>
 __device__ __forceinline__ int lf_qpel(const LfGeom& g, const LfPtrs& p, uint32_t rp, int y, int x, int mx, int my)
 {
     int X = 4 * x + mx, Y = 4 * y + my;
     int x0 = X >> 2, y0 = Y >> 2, fx = X & 3, fy = Y & 3;
     int xa = lf_clampi(x0, 0, g.w - 1), xb = lf_clampi(x0 + 1, 0, g.w - 1);
     int ya = lf_clampi(y0, 0, g.h - 1), yb = lf_clampi(y0 + 1, 0, g.h - 1);
-    int acc = (4 - fx) * (4 - fy) * lf_ref_tap<SPARSE>(g, p, rp, ya, xa) +
-              fx * (4 - fy) * lf_ref_tap<SPARSE>(g, p, rp, ya, xb) +
-              (4 - fx) * fy * lf_ref_tap<SPARSE>(g, p, rp, yb, xa) + fx * fy * lf_ref_tap<SPARSE>(g, p, rp, yb, xb);
+    int acc = (4 - fx) * (4 - fy) * lf_ref_tap<RES>(g, p, rp, ya, xa) +
+              fx * (4 - fy) * lf_ref_tap<RES>(g, p, rp, ya, xb) +
+              (4 - fx) * fy * lf_ref_tap<RES>(g, p, rp, yb, xa) + fx * fy * lf_ref_tap<RES>(g, p, rp, yb, xb);
     return (acc + 8) >> 4;
 }
 
@@ -149,7 +173,7 @@ __device__ __forceinline__ uint32_t lf_ref_index(const LfGeom& g, int c, int l, 
 // level-l ancestor, the progressive decode).  Reference SRVs come from the
 // resident reference storage; predictive SRVs are residual + phase *
 // prediction.
-template <bool SPARSE = false>
+template <int RES = LF_RES_DENSE>
 __device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c, int b, int a, int y, int x,
                                         int lod = 0)
 {
@@ -161,17 +185,40 @@ __device__ inline int lf_decode_channel(const LfGeom& g, const LfPtrs& p, int c,
         int B = b >> l, A = a >> l;
         const uint32_t rp = lf_ref_index(g, c, l, B >> 1, A >> 1);
         if (!((A | B) & 1)) {
-            v += lf_ref_tap<SPARSE>(g, p, rp, y, x);
+            v += lf_ref_tap<RES>(g, p, rp, y, x);
             continue;
         }
         int node = g.node_base[l] + B * g.na_l[l] + A;
         int r = lf_residual(g, p, c, l, node, blk, i);
         int mx, my, sg;
         lf_motion(g, p, c, l, (uint32_t)(pred_ordinal(g.na_l[l], B, A) * g.nblk + blk), mx, my, sg);
-        if (sg) r += sg * lf_qpel<SPARSE>(g, p, rp, y, x, mx, my);
+        if (sg) r += sg * lf_qpel<RES>(g, p, rp, y, x, mx, my);
         v += r;
     }
     return v;
+}
+
+// 4:2:0 chroma (Compressing HMLFC tree: the chroma channels are
+// sub-sampled): channel c of the chroma geometry (0: Co, 1: Cg, coded at
+// half width and height) at full-resolution sample (y, x), by centred
+// bilinear up-sampling.  Half-resolution sample (Y, X) sits at full
+// resolution (2Y + 1/2, 2X + 1/2), so an even row y blends half rows
+// y/2 - 1 and y/2 with weights 1 and 3, an odd row y/2 and y/2 + 1 with 3
+// and 1 (clamped to the plane), columns likewise; (sum + 8) >> 4.
+template <int RES = LF_RES_DENSE>
+__device__ inline int lf_chroma_up(const LfGeom& gc, const LfPtrs& pc, int c, int b, int a, int y, int x, int lod = 0)
+{
+    const int y0 = (y & 1) ? (y >> 1) : (y >> 1) - 1, x0 = (x & 1) ? (x >> 1) : (x >> 1) - 1;
+    const int wy0 = (y & 1) ? 3 : 1, wx0 = (x & 1) ? 3 : 1;
+    int acc = 0;
+    for (int j = 0; j < 2; j++) {
+        const int yy = lf_clampi(y0 + j, 0, gc.h - 1), wy = j ? 4 - wy0 : wy0;
+        for (int i = 0; i < 2; i++) {
+            const int xx = lf_clampi(x0 + i, 0, gc.w - 1), wx = i ? 4 - wx0 : wx0;
+            acc += wy * wx * lf_decode_channel<RES>(gc, pc, c, b, a, yy, xx, lod);
+        }
+    }
+    return (acc + 8) >> 4;
 }
 
 // Inverse reversible YCoCg lifting, then clamp to 8 bits.

@@ -19,7 +19,7 @@
 
 #include "lf_render_tile.h"
 
-template <bool SPARSE>
+template <int RES>
 __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, float* __restrict__ out, int lod)
 {
@@ -30,9 +30,42 @@ __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const f
     const int64_t px = r - (int64_t)v * npix;
     const int j = (int)(px / wo), i = (int)(px % wo);
     float o[3];
-    lf_render_one<SPARSE>(g, p, cams + 18 * v, i, j, o, lod);
+    lf_render_one<RES>(g, p, cams + 18 * v, i, j, o, lod);
 #pragma unroll
     for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
+}
+
+// 4:2:0 streams, one thread per ray: each of the 16 samples is luma plus
+// up-sampled Co and Cg (lf_chroma_up), blended as in lf_render_one.
+__global__ void __launch_bounds__(256) k_render_rays420(LfGeom g, LfPtrs p, LfGeom gc, LfPtrs pc,
+                                                        const float* __restrict__ cams, int nv, int wo, int ho,
+                                                        float* __restrict__ out, int lod)
+{
+    const int64_t npix = (int64_t)wo * ho;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= npix * nv) return;
+    const int v = (int)(r / npix);
+    const int64_t px = r - (int64_t)v * npix;
+    const int j = (int)(px / wo), i = (int)(px % wo);
+    const Ray ray = lf_ray_setup(g, cams + 18 * v, i, j);
+    uint32_t rgb[16];
+#pragma unroll 1
+    for (int k = 0; k < 16; k++) {
+        const int b = (k & 8) ? ray.b1 : ray.b0, a = (k & 4) ? ray.a1 : ray.a0;
+        const int y = (k & 2) ? ray.y1 : ray.y0, x = (k & 1) ? ray.x1 : ray.x0;
+        int R, G, B;
+        lf_ycocg_to_rgb(lf_decode_channel(g, p, 0, b, a, y, x, lod), lf_chroma_up(gc, pc, 0, b, a, y, x, lod),
+                        lf_chroma_up(gc, pc, 1, b, a, y, x, lod), R, G, B);
+        rgb[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+    }
+    const BlendW w = lf_blend_weights(ray);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float sm[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) sm[k] = (float)((rgb[k] >> (8 * c)) & 255u);
+        out[((int64_t)v * 3 + c) * npix + px] = lf_blend16(sm, w);
+    }
 }
 
 lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,
@@ -41,8 +74,14 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
     int64_t total = (int64_t)nv * wo * ho;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many rays");
-    hipLaunchKernelGGL(h->p.slots ? k_render_rays<true> : k_render_rays<false>, dim3((unsigned)blocks), dim3(256), 0,
-                       s, h->L.g, h->p, d_cams, nv, wo, ho, d_out, lod);
+    if (h->L.chroma420)
+        hipLaunchKernelGGL(k_render_rays420, dim3((unsigned)blocks), dim3(256), 0, s, h->L.g, h->p, h->L.gc, h->pc,
+                           d_cams, nv, wo, ho, d_out, lod);
+    else
+        hipLaunchKernelGGL(h->L.sparse == LF_RES_CSR     ? k_render_rays<LF_RES_CSR>
+                           : h->L.sparse == LF_RES_TILES ? k_render_rays<LF_RES_TILES>
+                                                         : k_render_rays<LF_RES_DENSE>,
+                           dim3((unsigned)blocks), dim3(256), 0, s, h->L.g, h->p, d_cams, nv, wo, ho, d_out, lod);
     return lf_check_launch("render_rays");
 }
 
@@ -199,9 +238,9 @@ extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, in
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
-    // the tile kernel decodes quads of 4 pixels inside one block and reads
-    // dense reference planes
-    if (h->L.g.bs < 4 || h->p.slots)
+    // the tile kernel decodes quads of 4 pixels inside one block, reads
+    // dense reference planes and assembles three full-size channels
+    if (h->L.g.bs < 4 || h->L.sparse || h->L.chroma420)
         return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
     return lf_launch_render_batch(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
 }

@@ -71,14 +71,14 @@ __device__ __forceinline__ float lf_blend16(const float (&sm)[16], const BlendW&
 // node adds its dequantised residual and its phase-signed prediction.  The
 // block descriptor (table entry and motion record) is read once when the four
 // pixels share a block.
-template <bool SPARSE>
+template <int RES>
 __device__ inline void lf_srv_quad(const LfGeom& g, const LfPtrs& p, int c, int l, int B, int A, const int ys[2],
                                    const int xs[2], int v[4])
 {
     const uint32_t rp = lf_ref_index(g, c, l, B >> 1, A >> 1);
     if (!((A | B) & 1)) {
 #pragma unroll
-        for (int k = 0; k < 4; k++) v[k] = lf_ref_tap<SPARSE>(g, p, rp, ys[k >> 1], xs[k & 1]);
+        for (int k = 0; k < 4; k++) v[k] = lf_ref_tap<RES>(g, p, rp, ys[k >> 1], xs[k & 1]);
         return;
     }
     const int node = g.node_base[l] + B * g.na_l[l] + A;
@@ -100,7 +100,7 @@ __device__ inline void lf_srv_quad(const LfGeom& g, const LfPtrs& p, int c, int 
         }
         const int i = ((y & (g.bs - 1)) << g.bsl) | (x & (g.bs - 1));
         int r = mode == LF_MODE_ZERO ? 0 : (mn + (int)lf_bise_get(p.payload + word, mode, (uint32_t)i)) * g.step[l];
-        if (sg) r += sg * lf_qpel<SPARSE>(g, p, rp, y, x, mx, my);
+        if (sg) r += sg * lf_qpel<RES>(g, p, rp, y, x, mx, my);
         v[k] = r;
     }
 }
@@ -111,7 +111,7 @@ __device__ inline void lf_srv_quad(const LfGeom& g, const LfPtrs& p, int c, int 
 // SRV evaluation (views (b, a) and (b', a') share the level-l node when
 // b >> l == b' >> l and a >> l == a' >> l): the same sums as 16 independent
 // tree walks.
-template <bool SPARSE>
+template <int RES>
 __device__ __forceinline__ void lf_ray_channel(const LfGeom& g, const LfPtrs& p, const Ray& r, int c, int lod,
                                                int acc[16])
 {
@@ -144,10 +144,10 @@ __device__ __forceinline__ void lf_ray_channel(const LfGeom& g, const LfPtrs& p,
     for (int l = lod; l < H; l++) {
         const bool eqA = (r.a0 >> l) == (r.a1 >> l), eqB = (r.b0 >> l) == (r.b1 >> l);
         int v[4][4];
-        lf_srv_quad<SPARSE>(g, p, c, l, r.b0 >> l, r.a0 >> l, ys, xs, v[0]);
-        if (!eqA) lf_srv_quad<SPARSE>(g, p, c, l, r.b0 >> l, r.a1 >> l, ys, xs, v[1]);
-        if (!eqB) lf_srv_quad<SPARSE>(g, p, c, l, r.b1 >> l, r.a0 >> l, ys, xs, v[2]);
-        if (!eqA && !eqB) lf_srv_quad<SPARSE>(g, p, c, l, r.b1 >> l, r.a1 >> l, ys, xs, v[3]);
+        lf_srv_quad<RES>(g, p, c, l, r.b0 >> l, r.a0 >> l, ys, xs, v[0]);
+        if (!eqA) lf_srv_quad<RES>(g, p, c, l, r.b0 >> l, r.a1 >> l, ys, xs, v[1]);
+        if (!eqB) lf_srv_quad<RES>(g, p, c, l, r.b1 >> l, r.a0 >> l, ys, xs, v[2]);
+        if (!eqA && !eqB) lf_srv_quad<RES>(g, p, c, l, r.b1 >> l, r.a1 >> l, ys, xs, v[3]);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             if (eqA) v[1][k] = v[0][k];
@@ -160,15 +160,15 @@ __device__ __forceinline__ void lf_ray_channel(const LfGeom& g, const LfPtrs& p,
     }
 }
 
-template <bool SPARSE = false>
+template <int RES = LF_RES_DENSE>
 __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cam, int i, int j,
                                      float out[3], int lod = 0)
 {
     const Ray r = lf_ray_setup(g, cam, i, j);
     int Y[16], Co[16], Cg[16];
-    lf_ray_channel<SPARSE>(g, p, r, 0, lod, Y);
-    lf_ray_channel<SPARSE>(g, p, r, 1, lod, Co);
-    lf_ray_channel<SPARSE>(g, p, r, 2, lod, Cg);
+    lf_ray_channel<RES>(g, p, r, 0, lod, Y);
+    lf_ray_channel<RES>(g, p, r, 1, lod, Co);
+    lf_ray_channel<RES>(g, p, r, 2, lod, Cg);
     uint32_t px[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) {

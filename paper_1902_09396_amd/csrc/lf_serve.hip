@@ -379,8 +379,9 @@ extern "C" lf_status lf_server_create(lf_handle* const* fields, int32_t n_fields
     if (cfg->max_slots < 1 || cfg->max_tiles < 1 || cfg->chunk_tiles < 1 || cfg->n_streams < 1 || cfg->n_streams > 4)
         return lf_fail(LF_EINVAL, "bad server configuration");
     for (int k = 0; k < n_fields; k++)
-        if (!fields[k] || fields[k]->L.g.bs < 4 || fields[k]->p.slots)
-            return lf_fail(LF_EINVAL, "field %d cannot be served (block size < 4 or sparse reference residency)", k);
+        if (!fields[k] || fields[k]->L.g.bs < 4 || fields[k]->L.sparse || fields[k]->L.chroma420)
+            return lf_fail(LF_EINVAL,
+                           "field %d cannot be served (block size < 4, sparse reference residency or 4:2:0 chroma)", k);
     lf_server* S = new lf_server();
     S->cfg = *cfg;
     S->pool = (uint8_t*)d_pool;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libhmlfc.so")
 
 LF_OK, LF_EINVAL, LF_ENOMEM, LF_EFORMAT, LF_EDEVICE = 0, -1, -2, -3, -4
 LF_LOAD_SPARSE_REFS = 1
+LF_LOAD_CSR_REFS = 2
 _NAMES = {LF_EINVAL: "LF_EINVAL", LF_ENOMEM: "LF_ENOMEM", LF_EFORMAT: "LF_EFORMAT", LF_EDEVICE: "LF_EDEVICE"}
 
 
@@ -32,7 +33,8 @@ class LfInfo(C.Structure):
                 ("levels", C.c_int32), ("block", C.c_int32), ("root_na", C.c_int32), ("root_nb", C.c_int32),
                 ("n_nodes", C.c_int64), ("n_pred_records", C.c_int64), ("n_refs", C.c_int64),
                 ("arena_bytes", C.c_int64), ("stream_bytes", C.c_int64), ("payload_bytes", C.c_int64),
-                ("ref_bytes", C.c_int64), ("sparse_refs", C.c_int32), ("clamped_coords", C.c_int64)]
+                ("ref_bytes", C.c_int64), ("sparse_refs", C.c_int32), ("clamped_coords", C.c_int64),
+                ("chroma420", C.c_int32)]
 
 
 _lib = None
@@ -111,15 +113,16 @@ def require_gpu():
 class LightField:
     """A compressed light field resident in device memory."""
 
-    def __init__(self, stream, device=None, sparse_refs: bool = False):
-        """sparse_refs=True keeps only the significant reference blocks resident
+    def __init__(self, stream, device=None, sparse_refs: bool = False, csr_refs: bool = False):
+        """sparse_refs=True keeps only the significant reference blocks resident,
+        csr_refs=True only the nonzero reference pixels as compressed sparse rows
         (same results; rendered one thread per ray)."""
         require_gpu()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         host = np.ascontiguousarray(np.frombuffer(bytes(stream), np.uint8) if isinstance(stream, (bytes, bytearray))
                                     else np.asarray(stream, dtype=np.uint8))
         self.stream_bytes = host.size
-        flags = LF_LOAD_SPARSE_REFS if sparse_refs else 0
+        flags = (LF_LOAD_SPARSE_REFS if sparse_refs else 0) | (LF_LOAD_CSR_REFS if csr_refs else 0)
         need = C.c_int64()
         check(lib().lf_query_arena_ex(host.ctypes.data_as(C.c_void_p), host.size, flags, C.byref(need)))
         with torch.cuda.device(self.device):
@@ -263,7 +266,7 @@ def ray_coords(cams: torch.Tensor, width: int, height: int) -> torch.Tensor:
 class EncodeParams(C.Structure):
     _fields_ = [("levels", C.c_int32), ("block", C.c_int32), ("step", C.c_int32 * 8), ("t_ref", C.c_int32 * 8),
                 ("t_pred", C.c_int32 * 8), ("win", C.c_int32 * 8), ("subpel", C.c_int32), ("zero_phase", C.c_int32),
-                ("no_mc", C.c_int32)]
+                ("no_mc", C.c_int32), ("chroma420", C.c_int32)]
 
 
 def encode(light_field: np.ndarray, enc: dict) -> np.ndarray:
@@ -308,12 +311,14 @@ def _encode_params(enc: dict):
         p.step[l], p.t_ref[l], p.t_pred[l], p.win[l] = enc["step"][l], enc["t_ref"][l], enc["t_pred"][l], enc["win"][l]
     p.subpel, p.zero_phase, p.no_mc = int(enc.get("subpel", True)), int(enc.get("zero_phase", False)), \
         int(enc.get("no_mc", False))
+    p.chroma420 = int(enc.get("chroma420", False))
     return p
 
 
-def query_arena(stream, sparse_refs: bool = False) -> int:
+def query_arena(stream, sparse_refs: bool = False, csr_refs: bool = False) -> int:
     host = np.ascontiguousarray(np.asarray(stream, dtype=np.uint8))
     need = C.c_int64()
     check(lib().lf_query_arena_ex(host.ctypes.data_as(C.c_void_p), host.size,
-                                  LF_LOAD_SPARSE_REFS if sparse_refs else 0, C.byref(need)))
+                                  (LF_LOAD_SPARSE_REFS if sparse_refs else 0) | (LF_LOAD_CSR_REFS if csr_refs else 0),
+                                  C.byref(need)))
     return int(need.value)

@@ -126,7 +126,7 @@ def test_decode_clamps_are_counted(tiny_stream, tiny_oracle):
         coords = np.stack([rng.integers(-3, 11, n), rng.integers(-3, 11, n), rng.integers(-9, 73, n),
                            rng.integers(-9, 73, n)], 1).astype(np.int32)
         hi = np.array([8, 8, 64, 64])
-        clamped = np.clip(coords, 0, hi - 1)
+        clamped = np.clip(coords, 0, hi - 1).astype(np.int32)
         n_out = int((clamped != coords).any(axis=1).sum())
         got = L.decode_pixels(torch.from_numpy(coords).cuda()).cpu().numpy()
         assert np.array_equal(got, tiny_oracle.decode_at(clamped))

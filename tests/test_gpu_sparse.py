@@ -1,6 +1,8 @@
-"""Sparse reference residency (only significant reference blocks resident,
-as tiles): every decode and render equals the dense handle's bit for bit,
-and the oracle's; the relaxed render is unaffected; serving rejects it."""
+"""Sparse reference residency, block tiles (only significant reference
+blocks resident) and per-pixel compressed sparse rows (only nonzero
+reference pixels): every decode and render equals the dense handle's bit for
+bit, and the oracle's; the relaxed render is unaffected; serving rejects
+them."""
 
 import numpy as np
 import pytest
@@ -26,15 +28,19 @@ def _coords(nb, na, h, w, n, seed):
     return c.astype(np.int32)
 
 
+RES = {"tiles": dict(sparse_refs=True), "csr": dict(csr_refs=True)}
+
+
+@pytest.mark.parametrize("res", ["tiles", "csr"])
 @pytest.mark.parametrize("over", [{}, {"step": 8, "t_ref": 200, "t_pred": 400}, {"subpel": False, "t_ref": 300},
-                                  {"no_mc": True, "t_ref": 300}])
-def test_sparse_equals_dense_tiny(torch_mod, tiny_lf, tiny_cams, tiny_cams_ez, over):
+                                  {"no_mc": True, "t_ref": 300}, {"block": 4, "t_ref": 75, "t_pred": 75}])
+def test_sparse_equals_dense_tiny(torch_mod, tiny_lf, tiny_cams, tiny_cams_ez, over, res):
     from paper_1902_09396_amd import lf
 
     torch = torch_mod
     s = stream_for("tiny", tiny_lf, **over)
-    dense, sparse = lf.LightField(s), lf.LightField(s, sparse_refs=True)
-    assert sparse.info["sparse_refs"] == 1 and dense.info["sparse_refs"] == 0
+    dense, sparse = lf.LightField(s), lf.LightField(s, **RES[res])
+    assert sparse.info["sparse_refs"] == (1 if res == "tiles" else 2) and dense.info["sparse_refs"] == 0
     # no descriptors in a sparse arena; with thresholds, zero reference blocks take no tiles
     assert sparse.info["arena_bytes"] < dense.info["arena_bytes"]
     if over.get("t_ref", 0) > 0:
@@ -61,7 +67,8 @@ def test_sparse_equals_dense_tiny(torch_mod, tiny_lf, tiny_cams, tiny_cams_ez, o
     assert torch.equal(sparse.render_relaxed(res, sh, cams, 32, 24), dense.render_relaxed(res_d, sh_d, cams, 32, 24))
 
 
-def test_sparse_mid_thresholded(torch_mod, mid_lf):
+@pytest.mark.parametrize("res", ["tiles", "csr"])
+def test_sparse_mid_thresholded(torch_mod, mid_lf, res):
     """17x17x128x128 with block thresholds: most reference blocks are zero."""
     from paper_1902_09396_amd import lf
 
@@ -70,7 +77,7 @@ def test_sparse_mid_thresholded(torch_mod, mid_lf):
     H = enc["levels"]
     enc.update(t_ref=[1200] * H, t_pred=[2400] * H)  # about half the reference blocks become zero
     s = lf.encode(mid_lf, enc)
-    dense, sparse = lf.LightField(s), lf.LightField(s, sparse_refs=True)
+    dense, sparse = lf.LightField(s), lf.LightField(s, **RES[res])
     assert sparse.info["ref_bytes"] < 0.8 * dense.info["ref_bytes"]
     coords = torch.from_numpy(_coords(17, 17, 128, 128, 500000, 3)).cuda()
     assert torch.equal(sparse.decode_pixels(coords), dense.decode_pixels(coords))
@@ -85,7 +92,34 @@ def test_serving_rejects_sparse(torch_mod, tiny_stream):
     from paper_1902_09396_amd import lf
     from paper_1902_09396_amd.serve import Server
 
-    sparse = lf.LightField(tiny_stream, sparse_refs=True)
-    with pytest.raises(lf.LFError) as e:
-        Server([sparse], pool_bytes=1 << 20)
+    for res in RES.values():
+        sparse = lf.LightField(tiny_stream, **res)
+        with pytest.raises(lf.LFError) as e:
+            Server([sparse], pool_bytes=1 << 20)
+        assert e.value.status == lf.LF_EINVAL
+    with pytest.raises(lf.LFError) as e:  # the two residencies do not combine
+        lf.LightField(tiny_stream, sparse_refs=True, csr_refs=True)
     assert e.value.status == lf.LF_EINVAL
+
+
+def test_csr_holds_only_nonzero_pixels(torch_mod, tiny_lf):
+    """The CSR store reports 4 bytes per nonzero reference pixel plus 4 per
+    row start: its nonzero count is the oracle's count of nonzero reference
+    SRV values."""
+    from paper_1902_09396_amd import lf
+
+    s = stream_for("tiny", tiny_lf, block=4, t_ref=75, t_pred=75)
+    o = oracle.OracleLF(s)
+    srv = o.decode_srv()  # [3][n_nodes][h][w]
+    # reference nodes: (even, even) of every level; BFS node numbering, level H-1 first
+    H, nbl = o.levels, [8]
+    for _ in range(H):
+        nbl.append((nbl[-1] + 1) // 2)
+    base, nodes = {}, 0
+    for l in range(H - 1, -1, -1):
+        base[l] = nodes
+        nodes += nbl[l] * nbl[l]
+    refs = [base[l] + B * nbl[l] + A for l in range(H) for B in range(0, nbl[l], 2) for A in range(0, nbl[l], 2)]
+    nnz = int((srv[:, refs] != 0).sum())
+    L = lf.LightField(s, csr_refs=True)
+    assert L.info["ref_bytes"] == 4 * nnz + 4 * (3 * len(refs) * 64 + 1)
