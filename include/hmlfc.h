@@ -235,6 +235,22 @@ lf_status lf_ray_coords(const float* d_cams, int32_t n_views, int32_t width, int
 lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                              int32_t height, double* host_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call hipMalloc): the per-view
+ * footprint bytes of lf_footprint_bytes, equal to its figures bit for bit,
+ * written to d_out (device double [n_views]) and only enqueued on `stream`
+ * (no synchronisation, no allocation).  Its scratch is a static device array
+ * of LF_FOOTPRINT_SCRATCH_MAX bytes in the library (one per GPU, held until
+ * the process ends), located with hipGetSymbolAddress on the first call on
+ * each device: the marks take 2 * 3 * n_nodes * n_blocks + 3 * root views *
+ * n_blocks bytes and the partial sums the last 8 KiB; a light field whose
+ * marks do not fit is rejected with LF_EINVAL.  Every call on a GPU shares
+ * that array, so calls that overlap on one GPU (other streams or threads)
+ * race: serialise them.  Errors: LF_EINVAL, LF_EDEVICE. */
+#define LF_FOOTPRINT_SCRATCH_MAX (64ll << 20)
+lf_status lf_footprint_bytes_noalloc(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
+                                     int32_t height, double* d_out, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Relaxed model and adjoint (encoder-side refinement).  Parameters: a     */
 /* real residual for every SRV value, float [3][n_nodes][height][width]    */

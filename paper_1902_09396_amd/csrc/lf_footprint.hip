@@ -3,6 +3,7 @@
 // on the render path.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <vector>
 
 #include "lf_internal.h"
@@ -156,4 +157,96 @@ extern "C" lf_status lf_footprint_bytes(const lf_handle* h, const float* d_cams,
     (void)hipFree(buf);
     (void)hipFree(part);
     return st;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the marks and partial sums live in a file-scope
+// device array, per-view totals are written to a caller's device buffer.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int64_t FP_PARTS = 1024;
+constexpr int64_t FP_SCRATCH_BYTES = LF_FOOTPRINT_SCRATCH_MAX;
+
+// Per GPU: the marks (2 * entries + root blocks bytes, from byte 0) and the
+// workgroup partial sums (FP_PARTS doubles, at the end).
+__device__ __align__(256) uint8_t scratch[FP_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each GPU, set once
+
+// view total = 12 bytes per ray + the partial sums in index order (fixed order: deterministic)
+__global__ void k_fp_total(const double* __restrict__ partial, int nparts, double rays_bytes, double* __restrict__ out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double tot = rays_bytes;
+        for (int k = 0; k < nparts; k++) tot += partial[k];
+        *out = tot;
+    }
+}
+
+lf_status scratch_address(uint8_t** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return lf_fail(LF_EDEVICE, "no current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return lf_fail(LF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (uint8_t*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LF_OK;
+}
+
+}  // namespace
+
+extern "C" lf_status lf_footprint_bytes_noalloc(const lf_handle* h, const float* d_cams, int32_t n_views,
+                                                int32_t width, int32_t height, double* d_out, void* stream)
+{
+    if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
+    if (lf_status cs = lf_require_full_chroma(h, "lf_footprint_bytes_noalloc")) return cs;
+    if (n_views == 0) return LF_OK;
+    if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
+    const LfGeom& g = h->L.g;
+    const int64_t n_ent = 3 * (int64_t)g.n_nodes * g.nblk;
+    const int64_t n_root = 3 * (int64_t)g.root_na * g.root_nb * g.nblk;
+    const int64_t marks = 2 * n_ent + n_root;
+    const int64_t parts_off = FP_SCRATCH_BYTES - FP_PARTS * (int64_t)sizeof(double);
+    if (marks > parts_off)
+        return lf_fail(LF_EINVAL, "light field needs %lld bytes of footprint marks; the allocation-free call holds %lld",
+                       (long long)marks, (long long)parts_off);
+    uint8_t* buf = nullptr;
+    lf_status st = scratch_address(&buf);
+    if (st != LF_OK) return st;
+    double* part = (double*)(buf + parts_off);
+    FpWeights w{};
+    for (int c = 0; c < 3; c++)
+        for (int l = 0; l < g.H; l++) {
+            int64_t cnt = (int64_t)((g.nb_l[l] / 2) * g.na_l[l] + ((g.nb_l[l] + 1) / 2) * (g.na_l[l] / 2)) * g.nblk;
+            if (cnt == 0) continue;
+            int m = g.mv_mode[c][l], fam = m >> 5, b = m & 31;
+            int64_t n = 2 * cnt;
+            int64_t bits = fam == 0 ? n * b : (fam == 1 ? (n + 4) / 5 * (8 + 5 * b) : (n + 2) / 3 * (7 + 3 * b));
+            w.mv_bytes[c][l] = ((double)bits + 2.0 * cnt) / (8.0 * cnt);
+        }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t rays = (int64_t)width * height;
+    for (int v = 0; v < n_views; v++) {
+        hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, s, buf, marks);
+        hipLaunchKernelGGL(k_fp_mark, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, h->p, d_cams + 18 * v,
+                           width, height, buf, buf + n_ent, buf + 2 * n_ent);
+        hipLaunchKernelGGL(k_fp_sum, dim3((unsigned)FP_PARTS), dim3(256), 0, s, g, h->p, w, buf, buf + n_ent,
+                           buf + 2 * n_ent, n_ent, n_root, part);
+        hipLaunchKernelGGL(k_fp_total, dim3(1), dim3(64), 0, s, (const double*)part, (int)FP_PARTS, 12.0 * (double)rays,
+                           d_out + v);
+        st = lf_check_launch("footprint_noalloc");
+        if (st != LF_OK) return st;
+    }
+    return LF_OK;
 }

@@ -56,6 +56,7 @@ SIGNATURES = {
     "lf_get_render_config": (C.c_int, [_I32, _I32, _I32, _P, _P]),
     "lf_ray_coords": (C.c_int, [_P, _I32, _I32, _I32, _P, _P]),
     "lf_footprint_bytes": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
+    "lf_footprint_bytes_noalloc": (C.c_int, [_P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_export_params": (C.c_int, [_P, _P, _P, _P]),
     "lf_render_relaxed": (C.c_int, [_P, _P, _P, _P, _I32, _I32, _I32, _P, _P]),
     "lf_backward_workspace": (C.c_int, [_P, _I32, _I32, _I32, _P]),
