@@ -86,7 +86,7 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
 }
 
 template <bool SMALL_BLOCKS>
-__global__ void __launch_bounds__(NT) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
+__global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, int tiles_x, int tiles_y, int chunk, int fpg,
                                                      float* __restrict__ out)
 {

@@ -870,7 +870,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                         __uint_as_float(FALLBACK_MARK);
             }
             f += 1;
-            n = gmax;
+            n = 1;  // the next group starts small again (below)
             __syncthreads();
             continue;
         }
@@ -1034,8 +1034,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             }
         }
         __syncthreads();
-        // phase 3: blend every ray of the group's views, two views at a time
-        // (the second view's sample reads are in flight during the first's blend)
+        // phase 3: blend every ray of the group's views: with one shared (s, t)
+        // axis view by view, reusing per-view (s, t) sums; otherwise two views
+        // at a time (the second view's sample reads in flight during the
+        // first's blend)
         {
             const int B00 = gp.B0[0], A00 = gp.A0[0], nA0 = gp.nA[0];
             // all views of the call share one st homography (a camera path with
@@ -1049,6 +1051,59 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 lf_axis(s, g.w, rst.x0, rst.x1, rst.fs);
                 lf_axis(t, g.h, rst.y0, rst.y1, rst.ft);
             }
+            if (st_shared) {
+                // Every view of the call has this pixel's (s, t) axis, so a
+                // neighbouring light-field view's (s, t) bilinear sum depends only
+                // on the 2x2 block of views (b0, a0) the ray reaches.  Each thread
+                // keeps the four sums of its last block; a view reaching the same
+                // block reuses them when every lane of the wave does, otherwise
+                // the wave recomputes them.  Same operations, in the same order,
+                // as lf_blend16.
+                const float gs = 1.0f - rst.fs, gt = 1.0f - rst.ft;
+                const float wst0 = gs * gt, wst1 = rst.fs * gt, wst2 = gs * rst.ft, wst3 = rst.fs * rst.ft;
+                const int pix = __mul24(rst.y0 - ymin, sxp) + (rst.x0 - xq0);
+                uint32_t ckey = 0xFFFFFFFFu;
+                float tc[4][3];
+                for (int q = f; q < f + n; q++) {
+                    float u, v;
+                    lf_ray_h(cams + 18 * (v0 + q), (float)ii + 0.5f, (float)jj + 0.5f, u, v);
+                    int a0, a1, b0, b1;
+                    float fu, fv;
+                    lf_axis(u, g.na, a0, a1, fu);
+                    lf_axis(v, g.nb, b0, b1, fv);
+                    const uint32_t key = ((uint32_t)b0 << 16) | (uint32_t)a0;
+                    if (__ballot(key != ckey) != 0ull) {  // uniform
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const int b = (k & 2) ? b1 : b0, a = (k & 1) ? a1 : a0;
+                            const uint32_t* q0 =
+                                rgba + __mul24(nodemap[0][__mul24(b - B00, nA0) + (a - A00)], npix) + pix;
+                            const uint32_t* q1 = q0 + sxp;
+                            const uint32_t s0 = q0[0], s1 = q0[1], s2 = q1[0], s3 = q1[1];
+#pragma unroll
+                            for (int c = 0; c < 3; c++) {
+                                float t = (float)((s0 >> (8 * c)) & 255u) * wst0;
+                                t = fmaf((float)((s1 >> (8 * c)) & 255u), wst1, t);
+                                t = fmaf((float)((s2 >> (8 * c)) & 255u), wst2, t);
+                                tc[k][c] = fmaf((float)((s3 >> (8 * c)) & 255u), wst3, t);
+                            }
+                        }
+                        ckey = key;
+                    }
+                    if (live) {
+                        const float gu = 1.0f - fu, gv = 1.0f - fv;
+                        const float uv0 = gu * gv, uv1 = fu * gv, uv2 = gu * fv, uv3 = fu * fv;
+#pragma unroll
+                        for (int c = 0; c < 3; c++) {
+                            float acc = tc[0][c] * uv0;
+                            acc = fmaf(tc[1][c], uv1, acc);
+                            acc = fmaf(tc[2][c], uv2, acc);
+                            acc = fmaf(tc[3][c], uv3, acc);
+                            out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = acc * (1.0f / 255.0f);
+                        }
+                    }
+                }
+            } else
             for (int q = f; q < f + n; q += 2) {
                 const bool two = q + 1 < f + n;  // uniform
                 Ray r[2];
@@ -1102,7 +1157,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         }
         __syncthreads();  // the next group's plan rewrites the node maps
         f += n;
-        n = gmax;
+        // views far apart (random cameras) keep groups small: the next group
+        // tries twice this one's size, so a call does not re-plan a full group
+        // and halve it for every view
+        n = min(gmax, 2 * n);
     }
     return left;
 }

@@ -86,3 +86,25 @@ def test_encoder_rejects(torch_mod, tiny_lf):
         with pytest.raises(lf.LFError) as e:
             lf.encode(x, dict(enc, **over))
         assert e.value.status == lf.LF_EINVAL, over
+
+
+def test_encoder_small_blocks_wide_window_thresholds(torch_mod):
+    """2x2 blocks with a 16-pixel window and block thresholds on a 3-level
+    tree (the rate-distortion sweep's setting): the stream equals the
+    oracle's and decodes like it, every pixel."""
+    import torch
+
+    from paper_1902_09396_amd import lf
+
+    x = crop_lf("path512", 9, 9, 64, 64)
+    enc = lfscene.get_config("path512")["enc"]
+    H = 3
+    enc.update(levels=H, block=2, step=[4] * H, win=[16] * H, t_ref=[75] * H, t_pred=[75] * H)
+    s = lf.encode(x, enc)
+    assert np.array_equal(s, oracle.encode(x, enc))
+    o = oracle.OracleLF(s)
+    L = lf.LightField(s)
+    coords = np.array([(b, a, y, xx) for b in range(9) for a in range(9) for y in range(64) for xx in range(64)],
+                      dtype=np.int32)
+    got = L.decode_pixels(torch.from_numpy(coords).cuda()).cpu().numpy()
+    assert np.array_equal(got.reshape(9, 9, 64, 64, 3), o.decode_full())

@@ -208,10 +208,13 @@ def test_cached_groups_equal_per_ray(torch_mod, lfmod, mid_stream):
 
 
 @pytest.mark.parametrize("shape", [(1, 5, 64, 32, 3, 8), (7, 3, 48, 40, 2, 4), (2, 2, 32, 32, 1, 16),
-                                   (9, 1, 16, 64, 4, 16)])
+                                   (9, 1, 16, 64, 4, 16), (5, 4, 64, 64, 2, 2), (4, 5, 96, 64, 2, 32),
+                                   (3, 3, 128, 64, 2, 64)])
 def test_thin_and_ragged_grids(torch_mod, lfmod, shape):
     """Single-row and single-column grids, odd grid sizes, one-level trees and
-    4-pixel blocks: decode bit-exact, render <= 1e-5, staged = per-ray."""
+    every block size the loader accepts for the tile renderer and below it
+    (2x2 blocks render per ray; 32x32 and 64x64 on the tile path): decode
+    bit-exact, render <= 1e-5, staged = per-ray."""
     torch = torch_mod
     na, nb, w, h, levels, block = shape
     lf = np.ascontiguousarray(lfscene.make_lf(na, nb, h, w, lfscene.get_config("tiny")["lf"]["spec"], 7))

@@ -41,10 +41,13 @@ def test_sparse_equals_dense_tiny(torch_mod, tiny_lf, tiny_cams, tiny_cams_ez, o
     s = stream_for("tiny", tiny_lf, **over)
     dense, sparse = lf.LightField(s), lf.LightField(s, **RES[res])
     assert sparse.info["sparse_refs"] == (1 if res == "tiles" else 2) and dense.info["sparse_refs"] == 0
-    # no descriptors in a sparse arena; with thresholds, zero reference blocks take no tiles
-    assert sparse.info["arena_bytes"] < dense.info["arena_bytes"]
-    if over.get("t_ref", 0) > 0:
-        assert sparse.info["ref_bytes"] < dense.info["ref_bytes"]
+    if res == "tiles":
+        # no descriptors in a sparse arena; with thresholds, zero reference blocks take no tiles
+        # (CSR memory is checked exactly in test_csr_holds_only_nonzero_pixels: 4 bytes per
+        # nonzero pixel, below the dense planes' 2 bytes per pixel only under 50% density)
+        assert sparse.info["arena_bytes"] < dense.info["arena_bytes"]
+        if over.get("t_ref", 0) > 0:
+            assert sparse.info["ref_bytes"] < dense.info["ref_bytes"]
     o = oracle.OracleLF(s)
     b, a, y, x = np.meshgrid(np.arange(8), np.arange(8), np.arange(64), np.arange(64), indexing="ij")
     coords = torch.from_numpy(np.stack([b.ravel(), a.ravel(), y.ravel(), x.ravel()], 1).astype(np.int32)).cuda()
@@ -78,7 +81,8 @@ def test_sparse_mid_thresholded(torch_mod, mid_lf, res):
     enc.update(t_ref=[1200] * H, t_pred=[2400] * H)  # about half the reference blocks become zero
     s = lf.encode(mid_lf, enc)
     dense, sparse = lf.LightField(s), lf.LightField(s, **RES[res])
-    assert sparse.info["ref_bytes"] < 0.8 * dense.info["ref_bytes"]
+    if res == "tiles":
+        assert sparse.info["ref_bytes"] < 0.8 * dense.info["ref_bytes"]
     coords = torch.from_numpy(_coords(17, 17, 128, 128, 500000, 3)).cuda()
     assert torch.equal(sparse.decode_pixels(coords), dense.decode_pixels(coords))
     cams = torch.from_numpy(lfscene.random_pinhole_cameras(3, 17, 17, 128, 128, 96, 64, seed=9,
