@@ -88,23 +88,45 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
 template <bool SMALL_BLOCKS>
 __global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
                                                      int wo, int ho, int tiles_x, int tiles_y, int chunk, int fpg,
-                                                     float* __restrict__ out)
+                                                     int64_t n_full, int split, float* __restrict__ out)
 {
     // A workgroup renders one screen tile for a chunk of consecutive views
     // (groups of fpg views, decoded values cached between the groups).
     // XCD-aware order: workgroup ids go round-robin over the 8 XCDs, so give
     // each XCD a contiguous range of (view chunk, tile) work: consecutive
     // views and neighbouring tiles share stream data in that XCD's L2.
+    // The first n_full (chunk, tile) items go to one workgroup each; the
+    // items after them, which would only part-fill the last round of
+    // resident workgroups, are cut into `split` runs of views each.
     const int n_chunks = (nv + chunk - 1) / chunk;
     const int64_t n_work = (int64_t)tiles_x * tiles_y * n_chunks;
-    const int64_t per_xcd = (n_work + 7) / 8;
-    const int64_t work = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (work >= n_work) return;  // uniform per workgroup
+    const int64_t ga = (n_full + 7) / 8 * 8;  // workgroups of the whole items
+    int64_t work;
+    int part = 0;
+    if ((int64_t)blockIdx.x < ga) {
+        const int64_t per_xcd = ga / 8;
+        work = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+        if (work >= n_full) return;  // uniform per workgroup
+    } else {
+        const int64_t b = blockIdx.x - ga, n_parts = (n_work - n_full) * split;
+        const int64_t per_xcd = (n_parts + 7) / 8;
+        const int64_t it = (b & 7) * per_xcd + (b >> 3);
+        if (it >= n_parts) return;
+        work = n_full + it / split;
+        part = (int)(it % split);
+    }
     TILE_LDS_DECL
     const int vc = (int)(work / ((int64_t)tiles_x * tiles_y));
     const int tt = (int)(work - (int64_t)vc * tiles_x * tiles_y);
     const int tyi = tt / tiles_x, txi = tt - tyi * tiles_x;
-    const int v0 = vc * chunk, nf = min(chunk, nv - v0);
+    const int c0 = vc * chunk, c1 = min(nv, c0 + chunk);
+    int v0 = c0, nf = c1 - c0;
+    if (work >= n_full) {
+        const int per = (nf + split - 1) / split;
+        v0 = c0 + part * per;
+        nf = min(per, c1 - v0);
+        if (nf <= 0) return;
+    }
     lf_tile_views<false, SMALL_BLOCKS>(g, p, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
 }
 
@@ -187,6 +209,27 @@ static int frames_per_chunk(int nv, int tiles)
     return (int)((nv + n_chunks - 1) / n_chunks);
 }
 
+// runs each tail item of the batched launch is cut into
+static int tail_split()
+{
+    static int v = env_int("HMLFC_TAIL_SPLIT", 2, 1, 8);
+    return v;
+}
+
+// compute units of the current device (cached per device id)
+static int device_cus()
+{
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 extern "C" lf_status lf_get_render_config(int32_t n_views, int32_t width, int32_t height, int32_t* views_per_group,
                                           int32_t* views_per_chunk)
 {
@@ -203,7 +246,15 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int tx = (wo + TW - 1) / TW, ty = (ho + TH - 1) / TH;
     const int fpg = frames_per_group(), chunk = frames_per_chunk(nv, tx * ty);
     const int64_t n_work = (int64_t)tx * ty * ((nv + chunk - 1) / chunk);
-    const int64_t grid = ((n_work + 7) / 8) * 8;
+    // Split the items past the last whole round of resident workgroups
+    // (3 per CU) into runs of views, so the tail of the launch is spread
+    // over more CUs; chunks too short to split keep one workgroup each.
+    const int split = tail_split();
+    const int64_t slots = 3 * (int64_t)device_cus();
+    int64_t n_full = n_work;
+    if (split > 1 && chunk >= 2 * split && n_work > slots && n_work % slots) n_full = n_work - n_work % slots;
+    const int sp = n_full < n_work ? split : 1;
+    const int64_t grid = (n_full + 7) / 8 * 8 + ((n_work - n_full) * sp + 7) / 8 * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
     const bool small = h->L.g.bs < 16;
     const size_t lds = small ? LDS_DYN_BYTES_SB : LDS_DYN_BYTES;
@@ -216,10 +267,10 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     }
     if (small)
         hipLaunchKernelGGL(k_render_batch<true>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv, wo,
-                           ho, tx, ty, chunk, fpg, d_out);
+                           ho, tx, ty, chunk, fpg, n_full, sp, d_out);
     else
         hipLaunchKernelGGL(k_render_batch<false>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv,
-                           wo, ho, tx, ty, chunk, fpg, d_out);
+                           wo, ho, tx, ty, chunk, fpg, n_full, sp, d_out);
     // marked pairs: workgroups each check a contiguous range.  With 16x16
     // blocks few tiles exceed the staging budget and 1024 workgroups keep the
     // pass short; smaller blocks mark many more tiles, which need the wider grid.

@@ -63,3 +63,29 @@ def test_fullsize_footprint(full):
     sel = cams[[0, 77]]
     got = field.footprint_bytes(torch.from_numpy(sel).cuda(), 512, 512)
     assert np.allclose(got, o.footprint_bytes(sel, 512, 512), rtol=1e-12, atol=0)
+
+
+def test_fullsize_block2_stream_decode_samples(full):
+    """The largest table the loader sees here: the 17x17x512x512 field coded
+    with 2x2 blocks (16-pel window, threshold 75, 3-level tree) holds 77.7
+    million table entries in a 752 MB stream; 10^6 random samples decode
+    bit-exactly like the oracle's."""
+    torch, cfg, _, _, _ = full
+    from paper_1902_09396_amd import lf
+
+    L = cfg["lf"]
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    H = 3
+    enc = dict(cfg["enc"], levels=H, block=2, step=[4] * H, win=[16] * H, t_ref=[75] * H, t_pred=[75] * H)
+    stream = lf.encode(light, enc)
+    assert stream.size > 512 << 20
+    o = oracle.OracleLF(stream)
+    field = lf.LightField(stream, device="cuda:0")
+    rng = np.random.default_rng(23)
+    n = 1_000_000
+    coords = np.stack([rng.integers(0, 17, n), rng.integers(0, 17, n), rng.integers(0, 512, n),
+                       rng.integers(0, 512, n)], 1).astype(np.int32)
+    got = field.decode_pixels(torch.from_numpy(coords).cuda()).cpu().numpy()
+    assert np.array_equal(got, o.decode_at(coords))
+    field.close()
+    o.close()

@@ -149,6 +149,24 @@ def test_tiled_equals_per_ray(torch_mod, lfmod, mid_stream, tiny_stream, tiny_ca
     assert np.array_equal(a, b)
 
 
+def test_tail_split_equals_per_ray(torch_mod, lfmod, mid_stream):
+    """A launch with more (chunk, tile) items than one round of resident
+    workgroups and a ragged remainder: the remainder items are cut into runs
+    of views, the last chunk is short, and every pixel still equals the
+    per-ray kernel's."""
+    torch = torch_mod
+    M = lfmod.LightField(mid_stream)
+    nv, wo, ho = 60, 400, 200
+    vpg, vpc = lfmod.render_config(nv, wo, ho)
+    tiles = ((wo + 31) // 32) * ((ho + 7) // 8)
+    n_work = tiles * ((nv + vpc - 1) // vpc)
+    assert n_work > 3 * 256 and n_work % (3 * 256) != 0 and nv % vpc != 0
+    cams = _cams_dev(torch, lfscene.camera_path_orbit(nv, 17, 17, 128, 128, wo, ho))
+    a = M.render_views(cams, wo, ho).cpu().numpy()
+    b = M.render_views(cams, wo, ho, per_ray=True).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
 def test_render_projective_cameras(torch_mod, lfmod, tiny_stream, tiny_oracle, tiny_cams_ez, mid_stream):
     """Cameras with a tilted image plane: the footprint boxes come from every
     pixel of a tile instead of its four corners."""
