@@ -272,8 +272,8 @@ lf_status lf_render_relaxed(const lf_handle* h, const float* d_residual, const f
                             int32_t n_views, int32_t width, int32_t height, float* d_out, void* stream);
 
 /* Device workspace bytes lf_render_backward needs for this view batch.
- * Host-only.  LF_EINVAL for batches above 2^27 - 1 rays (n_views * width *
- * height; each ray contributes 16 pairs to a sort whose count is an int). */
+ * Host-only.  LF_EINVAL for batches above 2^29 - 1 rays (n_views * width *
+ * height; each ray contributes 4 records to a sort whose count is an int). */
 lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, int32_t width, int32_t height, int64_t* bytes);
 
 /* Adjoint of lf_render_relaxed: given d_grad_out = dL/d(out) (same layout

@@ -13,12 +13,16 @@
 // fraction (floor(x + dx) = x + floor(dx)), which both directions use.
 //
 // Adjoint, deterministic and without atomics:
-//  1. every ray emits (sample index, ray * 16 + corner) pairs and its four
-//     blend fractions;
-//  2. a stable radix sort groups the pairs by sample;
-//  3. a segmented reduction walks each sample's run in ray order, forms each
-//     ray's blend weight from its fractions and applies the colour transpose,
-//     writing the sample gradients into the level-0 node planes;
+//  1. every ray emits one record per light-field view it blends, keyed by
+//     the sample at the top-left of its 2x2 pixel footprint in that view
+//     (ray * 4 + view corner), and its four blend fractions;
+//  2. a stable radix sort groups the records by key, and a table gives the
+//     first record of each key;
+//  3. every sample gathers the records keyed at itself and at its left, upper
+//     and upper-left neighbours (the footprints that cover it), in that order
+//     and in ray order within each, forms each ray's blend weight from its
+//     fractions and applies the colour transpose, writing the sample
+//     gradients into the level-0 node planes;
 //  4. node gradients are summed up the tree level by level in fixed order;
 //  5. each reference residual pulls the phase-signed bilinear transpose of
 //     its predictive siblings' gradients;
@@ -32,7 +36,8 @@
 
 #define AD_MAX_PARTS 1024  // partial maxima of the shift reduction
 #define AD_TILE 16         // reference tile side of the pull kernel
-#define AD_CAND_MAX 1536   // block records a tile stages in LDS
+#define AD_CAND_MAX 384    // candidate blocks a tile stages in LDS
+#define AD_WIN_MAX 4800    // sibling gradient values a tile stages in LDS (3 windows of up to 40 x 40)
 
 __device__ __forceinline__ float ad_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 
@@ -251,10 +256,10 @@ extern "C" lf_status lf_render_relaxed(const lf_handle* h, const float* d_residu
 // ---------------------------------------------------------------------------
 
 struct BwdLayout {
-    int64_t n_pairs, n_samples;
+    int64_t n_recs, n_samples;
     int end_bit;
     size_t sort_bytes;
-    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_max, o_parts, o_rayf, total;
+    int64_t o_kin, o_kout, o_vin, o_vout, o_sort, o_start, o_max, o_parts, o_rayf, o_brec, total;
 };
 
 static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
@@ -262,29 +267,31 @@ static int64_t al256(int64_t v) { return (v + 255) & ~(int64_t)255; }
 static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayout* B)
 {
     const LfGeom& g = h->L.g;
-    B->n_pairs = (int64_t)nv * wo * ho * 16;
+    B->n_recs = (int64_t)nv * wo * ho * 4;
     B->n_samples = (int64_t)g.na * g.nb * g.w * g.h;
-    // the pair sort takes an int count: at most 2^31 - 1 pairs (134,217,727 rays per call)
-    if (B->n_pairs > 0x7FFFFFFFll) return lf_fail(LF_EINVAL, "too many rays for one backward call (at most 2^27 - 1)");
-    if (B->n_samples > 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many light-field samples");
+    // the record sort takes an int count: at most 2^31 - 1 records (2^29 - 1 rays per call)
+    if (B->n_recs > 0x7FFFFFFFll) return lf_fail(LF_EINVAL, "too many rays for one backward call (at most 2^29 - 1)");
+    if (B->n_samples >= 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many light-field samples");
     int eb = 1;
     while (eb < 32 && ((int64_t)1 << eb) < B->n_samples) eb++;
     B->end_bit = eb;
     size_t sb = 0;
     if (hipcub::DeviceRadixSort::SortPairs(nullptr, sb, (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t*)nullptr,
-                                           (uint32_t*)nullptr, (int)B->n_pairs, 0, eb) != hipSuccess)
+                                           (uint32_t*)nullptr, (int)B->n_recs, 0, eb) != hipSuccess)
         return lf_fail(LF_EDEVICE, "sort workspace query failed");
     B->sort_bytes = sb;
-    const int64_t pb = al256(B->n_pairs * 4);
+    const int64_t pb = al256(B->n_recs * 4);
     B->o_kin = 0;
     B->o_kout = B->o_kin + pb;
     B->o_vin = B->o_kout + pb;
     B->o_vout = B->o_vin + pb;
     B->o_sort = B->o_vout + pb;
-    B->o_max = B->o_sort + al256((int64_t)sb);
+    B->o_start = B->o_sort + al256((int64_t)sb);
+    B->o_max = B->o_start + al256(B->n_samples * 4);
     B->o_parts = B->o_max + 256;
     B->o_rayf = B->o_parts + al256(AD_MAX_PARTS * 4);
-    B->total = B->o_rayf + al256(B->n_pairs / 16 * 16);  // one float4 per ray
+    B->o_brec = B->o_rayf + al256(B->n_recs / 4 * 16);  // one float4 per ray
+    B->total = B->o_brec + al256(h->L.n_rec * 16);         // one split shift per predictive block
     return LF_OK;
 }
 
@@ -300,8 +307,8 @@ extern "C" lf_status lf_backward_workspace(const lf_handle* h, int32_t n_views, 
     return LF_OK;
 }
 
-__global__ void k_ad_pairs(LfGeom g, const float* __restrict__ cams, int nv, int wo, int ho, uint32_t* __restrict__ keys,
-                           uint32_t* __restrict__ vals, float4* __restrict__ rayf)
+__global__ void k_ad_records(LfGeom g, const float* __restrict__ cams, int nv, int wo, int ho,
+                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, float4* __restrict__ rayf)
 {
     const int64_t npix = (int64_t)wo * ho;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,52 +316,73 @@ __global__ void k_ad_pairs(LfGeom g, const float* __restrict__ cams, int nv, int
     const int v = (int)(r / npix);
     const int64_t px = r - (int64_t)v * npix;
     const AdRay ry = ad_ray(g, cams + 18 * v, (int)(px % wo), (int)(px / wo));
-    rayf[r] = make_float4(ry.fu, ry.fv, ry.fs, ry.ft);  // the blend fractions, for the segment pass
+    rayf[r] = make_float4(ry.fu, ry.fv, ry.fs, ry.ft);  // the blend fractions, for the gather pass
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const int b = (k & 8) ? ry.b1 : ry.b0, a = (k & 4) ? ry.a1 : ry.a0;
-        const int y = (k & 2) ? ry.y1 : ry.y0, x = (k & 1) ? ry.x1 : ry.x0;
-        keys[r * 16 + k] = (uint32_t)((((int64_t)b * g.na + a) * g.h + y) * g.w + x);
-        vals[r * 16 + k] = (uint32_t)(r * 16 + k);
+    for (int q = 0; q < 4; q++) {
+        const int b = (q & 2) ? ry.b1 : ry.b0, a = (q & 1) ? ry.a1 : ry.a0;
+        keys[r * 4 + q] = (uint32_t)((((int64_t)b * g.na + a) * g.h + ry.y0) * g.w + ry.x0);
+        vals[r * 4 + q] = (uint32_t)(r * 4 + q);
     }
 }
 
-__global__ void k_ad_fill(float* __restrict__ p, int64_t n)
+__global__ void k_ad_nostart(uint32_t* __restrict__ start, int64_t n)
 {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
-        p[t] = 0.0f;
+        start[t] = 0xFFFFFFFFu;
 }
 
-// one thread per run of equal keys: sum the run in ray order
-// The sample index ((b * na + a) * h + y) * w + x is also the offset of pixel
-// (y, x) in the level-0 node planes of a channel, so the YCoCg sample
-// gradients go straight into the residual gradient (channel stride cstride).
-__global__ void k_ad_segments(const float4* __restrict__ rayf, int wo, int ho, const float* __restrict__ grad_out,
-                              const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n_pairs,
-                              int64_t cstride, float* __restrict__ g0 /* level-0 planes of channel 0 */)
+// first record of every key present
+__global__ void k_ad_heads(const uint32_t* __restrict__ keys, int64_t n, uint32_t* __restrict__ start)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
-    const uint32_t key = keys[i];
-    if (i > 0 && keys[i - 1] == key) return;
+    if (i >= n) return;
+    const uint32_t k = keys[i];
+    if (i == 0 || keys[i - 1] != k) start[k] = (uint32_t)i;
+}
+
+// One thread per light-field sample ((b * na + a) * h + y) * w + x, which is
+// also the offset of pixel (y, x) in the level-0 node planes of a channel, so
+// the YCoCg sample gradients go straight into the residual gradient (channel
+// stride cstride); samples no ray reaches get zero.  A record keyed at the
+// footprint corner (y0, x0) reaches pixel corner (cy, cx) at (y0 + cy, x0 +
+// cx), except along an axis of length 1, where both corners are pixel 0.
+__global__ void k_ad_samples(const float4* __restrict__ rayf, int wo, int ho, const float* __restrict__ grad_out,
+                             const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                             const uint32_t* __restrict__ start, int64_t n_recs, int64_t n_samples, int w, int h,
+                             int64_t cstride, float* __restrict__ g0 /* level-0 planes of channel 0 */)
+{
+    const int64_t S = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (S >= n_samples) return;
     const int64_t npix = (int64_t)wo * ho;
+    const int x = (int)(S % w), y = (int)((S / w) % h);
     float acc[3] = {0.0f, 0.0f, 0.0f};
-    for (int64_t jx = i; jx < n_pairs && keys[jx] == key; jx++) {
-        const uint32_t val = vals[jx];
-        const int64_t ray = val >> 4;
-        const int k = (int)(val & 15u);
-        const int v = (int)(ray / npix);
-        const int64_t px = ray - (int64_t)v * npix;
-        const float4 f = rayf[ray];  // (fu, fv, fs, ft)
-        const float w = ((k & 8) ? f.y : 1.0f - f.y) * ((k & 4) ? f.x : 1.0f - f.x) *
-                        ((k & 2) ? f.w : 1.0f - f.w) * ((k & 1) ? f.z : 1.0f - f.z) * (1.0f / 255.0f);
+    for (int cy = 0; cy < 2; cy++) {
+        const int dy = h >= 2 ? cy : 0;
+        if (y < dy) continue;
+        for (int cx = 0; cx < 2; cx++) {
+            const int dx = w >= 2 ? cx : 0;
+            if (x < dx) continue;
+            const uint32_t K = (uint32_t)(S - (int64_t)dy * w - dx);
+            uint32_t j = start[K];
+            if (j == 0xFFFFFFFFu) continue;
+            for (; (int64_t)j < n_recs && keys[j] == K; j++) {
+                const uint32_t val = vals[j];
+                const int64_t ray = val >> 2;
+                const int q = (int)(val & 3u);
+                const int v = (int)(ray / npix);
+                const int64_t px = ray - (int64_t)v * npix;
+                const float4 f = rayf[ray];  // (fu, fv, fs, ft)
+                const float wt = ((q & 2) ? f.y : 1.0f - f.y) * ((q & 1) ? f.x : 1.0f - f.x) *
+                                 (cy ? f.w : 1.0f - f.w) * (cx ? f.z : 1.0f - f.z) * (1.0f / 255.0f);
 #pragma unroll
-        for (int c = 0; c < 3; c++) acc[c] = fmaf(w, grad_out[((int64_t)v * 3 + c) * npix + px], acc[c]);
+                for (int c = 0; c < 3; c++) acc[c] = fmaf(wt, grad_out[((int64_t)v * 3 + c) * npix + px], acc[c]);
+            }
+        }
     }
     // colour transpose of R = Y + Co/2 - Cg/2, G = Y + Cg/2, B = Y - Co/2 - Cg/2
-    g0[key] = acc[0] + acc[1] + acc[2];
-    g0[cstride + key] = 0.5f * (acc[0] - acc[2]);
-    g0[2 * cstride + key] = 0.5f * (acc[1] - acc[0] - acc[2]);
+    g0[S] = acc[0] + acc[1] + acc[2];
+    g0[cstride + S] = 0.5f * (acc[0] - acc[2]);
+    g0[2 * cstride + S] = 0.5f * (acc[1] - acc[0] - acc[2]);
 }
 
 // node gradients of level l >= 1: the sum of its children's (level 0 holds
@@ -437,19 +465,84 @@ struct AdRec {
     float fx, fy;
 };
 
-__device__ __forceinline__ AdRec ad_fetch(const LfGeom& g, const LfPtrs& p, const float2* __restrict__ shift, int c,
-                                          int l, int B, int A, int blk)
+__device__ __forceinline__ int4 ad_pack(const AdRec& d)
 {
-    AdRec d{0, 0, 0, 0.0f, 0.0f};
-    d.sg = ad_phase(g, p, c, l, B, A, blk);
-    if (!d.sg) return d;
-    const float2 s = shift[ad_record(g, c, l, B, A, blk)];
-    const float fdx = floorf(s.x), fdy = floorf(s.y);
-    d.fx = s.x - fdx;
-    d.fy = s.y - fdy;
-    d.ix = (int)fminf(fmaxf(fdx, (float)(-g.w - 1)), (float)g.w);
-    d.iy = (int)fminf(fmaxf(fdy, (float)(-g.h - 1)), (float)g.h);
-    return d;
+    return make_int4(d.sg, (d.ix & 0xFFFF) | (d.iy << 16), __float_as_int(d.fx), __float_as_int(d.fy));
+}
+
+__device__ __forceinline__ AdRec ad_unpack(int4 v)
+{
+    return AdRec{v.x, (int)(int16_t)(v.y & 0xFFFF), v.y >> 16, __int_as_float(v.z), __int_as_float(v.w)};
+}
+
+// phase and split shift of every predictive block, in record order, decoded
+// once for the reference pull (each block is a candidate of several tiles)
+__global__ void k_ad_blockrec(LfGeom g, LfPtrs p, const float2* __restrict__ shift, int64_t n_rec,
+                              int4* __restrict__ brec)
+{
+    const int64_t rec = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rec >= n_rec) return;
+    int c = 0, l = g.H - 1;
+    while (c < 2 && rec >= g.rec_base[c + 1][g.H - 1]) c++;
+    while (l > 0 && rec >= g.rec_base[c][l - 1]) l--;
+    int mx, my, sg;
+    lf_motion(g, p, c, l, (uint32_t)(rec - g.rec_base[c][l]), mx, my, sg);
+    AdRec d{sg, 0, 0, 0.0f, 0.0f};
+    if (sg) {
+        const float2 s = shift[rec];
+        const float fdx = floorf(s.x), fdy = floorf(s.y);
+        d.fx = s.x - fdx;
+        d.fy = s.y - fdy;
+        d.ix = (int)fminf(fmaxf(fdx, (float)(-g.w - 1)), (float)g.w);
+        d.iy = (int)fminf(fmaxf(fdy, (float)(-g.h - 1)), (float)g.h);
+    }
+    brec[rec] = ad_pack(d);
+}
+
+// What reference pixel (X, Y) pulls from one predictive block (row ky,
+// column kx) with gradient plane gp: the bilinear weights of the block's taps
+// that land on the pixel times the gradients of their pixels, phase-signed,
+// added to acc.
+template <class Get>
+__device__ __forceinline__ float ad_block_pull(const LfGeom& g, Get get, int X, int Y, int ky, int kx, const AdRec& d,
+                                               float acc)
+{
+    float blk_acc = 0.0f;
+    const int bx0 = kx * g.bs, by0 = ky * g.bs;
+    if (X > 0 && X < g.w - 1 && Y > 0 && Y < g.h - 1) {
+        // away from the image border no tap is clamped: the tap (oy, ox)
+        // landing on the pixel comes from source pixel (Y - iy - oy, X - ix - ox)
+        // alone, when that pixel lies in the block
+#pragma unroll
+        for (int oy = 0; oy < 2; oy++) {
+            const int ys = Y - d.iy - oy;
+            const float wy = oy ? d.fy : 1.0f - d.fy;
+#pragma unroll
+            for (int ox = 0; ox < 2; ox++) {
+                const int xs = X - d.ix - ox;
+                if (ys >= by0 && ys < by0 + g.bs && xs >= bx0 && xs < bx0 + g.bs)
+                    blk_acc = fmaf(wy * (ox ? d.fx : 1.0f - d.fx), get(ys, xs), blk_acc);
+            }
+        }
+    } else {
+        for (int oy = 0; oy < 2; oy++) {
+            int ylo, yhi;
+            ad_tap_range(Y, g.h, d.iy, oy, by0, by0 + g.bs - 1, ylo, yhi);
+            if (ylo > yhi) continue;
+            const float wy = oy ? d.fy : 1.0f - d.fy;
+            for (int ox = 0; ox < 2; ox++) {
+                int xlo, xhi;
+                ad_tap_range(X, g.w, d.ix, ox, bx0, bx0 + g.bs - 1, xlo, xhi);
+                if (xlo > xhi) continue;
+                const float wxy = wy * (ox ? d.fx : 1.0f - d.fx);
+                float sum = 0.0f;
+                for (int y = ylo; y <= yhi; y++)
+                    for (int x = xlo; x <= xhi; x++) sum += get(y, x);
+                blk_acc = fmaf(wxy, sum, blk_acc);
+            }
+        }
+    }
+    return acc + (d.sg > 0 ? blk_acc : -blk_acc);
 }
 
 // Gradient that reference pixel (X, Y) of the cluster with reference node
@@ -476,24 +569,7 @@ __device__ inline float ad_pull(const LfGeom& g, const float* __restrict__ gres,
                 if (ky < ky0 || ky > ky1 || kx < kx0 || kx > kx1) continue;
                 const AdRec d = fetch(sib, B, A, ky, kx);
                 if (!d.sg) continue;
-                float blk_acc = 0.0f;
-                for (int oy = 0; oy < 2; oy++) {
-                    int ylo, yhi;
-                    ad_tap_range(Y, g.h, d.iy, oy, ky * g.bs, ky * g.bs + g.bs - 1, ylo, yhi);
-                    if (ylo > yhi) continue;
-                    const float wy = oy ? d.fy : 1.0f - d.fy;
-                    for (int ox = 0; ox < 2; ox++) {
-                        int xlo, xhi;
-                        ad_tap_range(X, g.w, d.ix, ox, kx * g.bs, kx * g.bs + g.bs - 1, xlo, xhi);
-                        if (xlo > xhi) continue;
-                        const float wxy = wy * (ox ? d.fx : 1.0f - d.fx);
-                        float sum = 0.0f;
-                        for (int y = ylo; y <= yhi; y++)
-                            for (int x = xlo; x <= xhi; x++) sum += gp[y * g.w + x];
-                        blk_acc = fmaf(wxy, sum, blk_acc);
-                    }
-                }
-                acc += d.sg > 0 ? blk_acc : -blk_acc;
+                acc = ad_block_pull(g, [&](int y, int x) { return gp[y * g.w + x]; }, X, Y, ky, kx, d, acc);
             }
     }
     return acc;
@@ -502,20 +578,33 @@ __device__ inline float ad_pull(const LfGeom& g, const float* __restrict__ gres,
 
 // reference residual gradient: own node gradient plus the phase-signed
 // bilinear transpose of every predictive sibling's gradient (pull form).  A
-// workgroup takes 16x16 tiles of one reference plane; the blocks any pixel
-// of the tile can pull from are decoded once per tile into LDS (phase and
-// split shift), unless there are more than the LDS budget holds, in which
-// case every pixel decodes them itself.
-__global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const float2* __restrict__ shift,
+// workgroup takes 16x16 tiles of one reference plane.  The candidate blocks
+// (those within the largest shift of the tile) are read from the decoded
+// block records; the ones whose shifted taps land inside the tile are kept, in
+// (sibling, block-row, block-column) order, in an LDS list that every pixel
+// of the tile walks (the blocks left out add exactly zero to every pixel of
+// the tile).  The three sibling gradient windows the taps can come from are
+// staged in LDS when they fit; their loads, the candidates' and the pixel's
+// own gradient are issued together.  With more candidates than the LDS
+// budget holds, every pixel reads its own candidates instead.
+__global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, const int4* __restrict__ brec,
                                                       const float* __restrict__ maxshift, float* __restrict__ gres)
 {
-    __shared__ int4 rec[AD_CAND_MAX];
+    // kept block i: windowed tiles: lst_a = (x origin kx bs + ix, y origin
+    // ky bs + iy, window offset of source pixel (Y - iy, X - ix) less
+    // Y ww + X, packed (sibling, ky, kx)), lst_b = the tap weights (1-fy)(1-fx),
+    // (1-fy) fx, fy (1-fx), fy fx times the phase (float bits); otherwise
+    // lst_a = the block record, lst_b.x = packed (sibling, ky, kx)
+    __shared__ int4 lst_a[AD_CAND_MAX], lst_b[AD_CAND_MAX];
+    __shared__ float win[AD_WIN_MAX];  // [sibling - 1][window row][window column]
+    __shared__ int wcount[4];
     const int64_t plane = (int64_t)g.w * g.h;
     const int tiles_x = (g.w + AD_TILE - 1) / AD_TILE, tiles_y = (g.h + AD_TILE - 1) / AD_TILE;
     const int64_t per_plane = (int64_t)tiles_x * tiles_y;
     const int64_t n_tiles = 3 * (int64_t)g.n_refs * per_plane;
     const int reach = (int)ceilf(fminf(maxshift[0], (float)(g.w + g.h))) + 2;
     const int nby = g.h / g.bs;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int64_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
         const int64_t rp = T / per_plane;
         const int tt = (int)(T - rp * per_plane);
@@ -530,43 +619,153 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, LfPtrs p, const 
         const int cky0 = max(0, (ty0 - reach) / g.bs), cky1 = min(nby - 1, (ty1 + reach) / g.bs);
         const int nkx = ckx1 - ckx0 + 1, nk = nkx * (cky1 - cky0 + 1);
         const bool staged = 3 * nk <= AD_CAND_MAX;  // uniform
-        if (staged) {
-            for (int e = threadIdx.x; e < 3 * nk; e += blockDim.x) {
+        // Every tap a pixel of the tile pulls comes from within `reach` of the tile.
+        const int wx0 = max(0, tx0 - reach), wx1 = min(g.w - 1, tx1 + reach);
+        const int wy0 = max(0, ty0 - reach), wy1 = min(g.h - 1, ty1 + reach);
+        const int ww = wx1 - wx0 + 1, nr = wy1 - wy0 + 1, wa = ww * nr;
+        const bool windowed = staged && ww <= 64 && 3 * wa <= AD_WIN_MAX;  // uniform
+
+        // loads in flight together: candidate records, the pixel's own
+        // gradient, the sibling windows
+        constexpr int CR = (AD_CAND_MAX + 255) / 256;
+        int4 cv[CR];
+        bool cok[CR];
+#pragma unroll
+        for (int k2 = 0; k2 < CR; k2++) {
+            const int e = k2 * 256 + (int)threadIdx.x;
+            cok[k2] = false;
+            cv[k2] = make_int4(0, 0, 0, 0);
+            if (staged && e < 3 * nk) {
                 const int sib = 1 + e / nk, k = e - (sib - 1) * nk;
                 const int B = Br + (sib >> 1), A = Ar + (sib & 1);
-                int4 v = make_int4(0, 0, 0, 0);
                 if (B < g.nb_l[l] && A < g.na_l[l]) {
-                    const AdRec d =
-                        ad_fetch(g, p, shift, c, l, B, A, (cky0 + k / nkx) * g.nbx + ckx0 + k % nkx);
-                    v = make_int4(d.sg, (d.ix & 0xFFFF) | (d.iy << 16), __float_as_int(d.fx), __float_as_int(d.fy));
+                    cok[k2] = true;
+                    cv[k2] = brec[ad_record(g, c, l, B, A, (cky0 + k / nkx) * g.nbx + ckx0 + k % nkx)];
                 }
-                rec[e] = v;
             }
         }
-        __syncthreads();
         const int X = tx0 + (int)threadIdx.x % AD_TILE, Y = ty0 + (int)threadIdx.x / AD_TILE;
-        if (X <= tx1 && Y <= ty1) {
-            const int64_t own = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + Y * g.w + X;
-            float acc = gres[own];
-            if (staged)
-                acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach, cky0, cky1, ckx0, ckx1,
-                              [&](int sib, int, int, int ky, int kx) {
-                                  const int4 v = rec[(sib - 1) * nk + (ky - cky0) * nkx + (kx - ckx0)];
-                                  return AdRec{v.x, (int)(int16_t)(v.y & 0xFFFF), v.y >> 16, __int_as_float(v.z),
-                                               __int_as_float(v.w)};
-                              },
-                              acc);
-            else
+        const bool mine = X <= tx1 && Y <= ty1;
+        const int64_t own = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + Y * g.w + X;
+        const float own_g = mine ? gres[own] : 0.0f;
+        if (windowed) {
+            // all of the three windows' loads in flight at once: value e of
+            // sibling window s (row e / ww, column e % ww; the row from a
+            // float reciprocal, exact for e < 2^13 and ww <= 64)
+            constexpr int WL = (AD_WIN_MAX + 255) / 256;
+            const float rw = 1.0f / (float)ww;
+            const int64_t nb0 = (int64_t)c * g.n_nodes + g.node_base[l];
+            const bool h1 = Ar + 1 < g.na_l[l], h2 = Br + 1 < g.nb_l[l], h3 = h1 && h2;
+            const float* s1 = gres + (nb0 + Br * g.na_l[l] + Ar + 1) * plane;
+            const float* s2 = gres + (nb0 + (Br + 1) * g.na_l[l] + Ar) * plane;
+            const float* s3 = gres + (nb0 + (Br + 1) * g.na_l[l] + Ar + 1) * plane;
+            float v[WL];
+#pragma unroll
+            for (int u = 0; u < WL; u++) {
+                const int e = u * 256 + (int)threadIdx.x;
+                const int sw = e >= 2 * wa ? 2 : (e >= wa ? 1 : 0);
+                const int rr = e - sw * wa;
+                const int yy = (int)(((float)rr + 0.5f) * rw), xx = rr - yy * ww;
+                const bool has = sw == 0 ? h1 : (sw == 1 ? h2 : h3);
+                const float* sp = sw == 0 ? s1 : (sw == 1 ? s2 : s3);
+                v[u] = (e < 3 * wa && has) ? sp[(int64_t)(wy0 + yy) * g.w + wx0 + xx] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < WL; u++) {
+                const int e = u * 256 + (int)threadIdx.x;
+                if (e < 3 * wa) win[e] = v[u];
+            }
+        }
+        // keep the candidates whose taps reach the tile, in order
+        int n_list = 0;
+        if (staged) {
+#pragma unroll
+            for (int k2 = 0; k2 < CR; k2++) {
+                if (k2 * 256 >= 3 * nk) break;  // uniform
+                const int e = k2 * 256 + (int)threadIdx.x;
+                const AdRec d = ad_unpack(cv[k2]);
+                const int sib = 1 + e / nk, k = e - (sib - 1) * nk;
+                const int ky = cky0 + k / nkx, kx = ckx0 + k % nkx;
+                // taps of the block's pixels: [k bs + i, k bs + bs + i] per axis, clamped
+                const int xlo = lf_clampi(kx * g.bs + d.ix, 0, g.w - 1);
+                const int xhi = lf_clampi(kx * g.bs + g.bs + d.ix, 0, g.w - 1);
+                const int ylo = lf_clampi(ky * g.bs + d.iy, 0, g.h - 1);
+                const int yhi = lf_clampi(ky * g.bs + g.bs + d.iy, 0, g.h - 1);
+                const bool keep = cok[k2] && d.sg != 0 && xlo <= tx1 && xhi >= tx0 && ylo <= ty1 && yhi >= ty0;
+                const uint64_t m = __ballot(keep);
+                if (lane == 0) wcount[wv] = __popcll(m);
+                __syncthreads();
+                int pos = n_list;
+                for (int q = 0; q < wv; q++) pos += wcount[q];
+                pos += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (keep) {
+                    const int at = (sib << 28) | (ky << 14) | kx;
+                    if (windowed) {
+                        const float sg = (float)d.sg, gx = 1.0f - d.fx, gy = 1.0f - d.fy;
+                        lst_a[pos] = make_int4(kx * g.bs + d.ix, ky * g.bs + d.iy,
+                                               (sib - 1) * wa - (d.iy + wy0) * ww - (d.ix + wx0), at);
+                        lst_b[pos] = make_int4(__float_as_int(sg * (gy * gx)), __float_as_int(sg * (gy * d.fx)),
+                                               __float_as_int(sg * (d.fy * gx)), __float_as_int(sg * (d.fy * d.fx)));
+                    } else {
+                        lst_a[pos] = cv[k2];
+                        lst_b[pos] = make_int4(at, 0, 0, 0);
+                    }
+                }
+                for (int q = 0; q < 4; q++) n_list += wcount[q];
+                __syncthreads();  // wcount is rewritten by the next round; lists and window complete
+            }
+        }
+        if (mine) {
+            float acc = own_g;
+            if (windowed && X > 0 && X < g.w - 1 && Y > 0 && Y < g.h - 1) {
+                // away from the image border each tap (oy, ox) landing on the
+                // pixel comes from source pixel (Y - iy - oy, X - ix - ox) alone,
+                // when it lies in the block: the same products, in the same
+                // order, as the general form
+                const int base = Y * ww + X;
+                for (int i = 0; i < n_list; i++) {
+                    const int4 e = lst_a[i];
+                    const int dx = X - e.x, dy = Y - e.y;
+                    const bool x0 = (unsigned)dx < (unsigned)g.bs, x1 = (unsigned)(dx - 1) < (unsigned)g.bs;
+                    const bool y0 = (unsigned)dy < (unsigned)g.bs, y1 = (unsigned)(dy - 1) < (unsigned)g.bs;
+                    if (!((x0 || x1) && (y0 || y1))) continue;
+                    const int4 wb = lst_b[i];
+                    const float* src = win + base + e.z;
+                    float blk = 0.0f;
+                    if (y0 && x0) blk = fmaf(__int_as_float(wb.x), src[0], blk);
+                    if (y0 && x1) blk = fmaf(__int_as_float(wb.y), src[-1], blk);
+                    if (y1 && x0) blk = fmaf(__int_as_float(wb.z), src[-ww], blk);
+                    if (y1 && x1) blk = fmaf(__int_as_float(wb.w), src[-ww - 1], blk);
+                    acc += blk;
+                }
+            } else if (staged) {
+                for (int i = 0; i < n_list; i++) {
+                    const int at = windowed ? lst_a[i].w : lst_b[i].x;
+                    const int sib = at >> 28, ky = (at >> 14) & 0x3FFF, kx = at & 0x3FFF;
+                    const int B = Br + (sib >> 1), A = Ar + (sib & 1);
+                    if (windowed) {  // a border pixel
+                        const AdRec d = ad_unpack(brec[ad_record(g, c, l, B, A, ky * g.nbx + kx)]);
+                        const float* ws = win + (sib - 1) * wa - wy0 * ww - wx0;
+                        acc = ad_block_pull(g, [&](int y, int x) { return ws[y * ww + x]; }, X, Y, ky, kx, d, acc);
+                    } else {
+                        const AdRec d = ad_unpack(lst_a[i]);
+                        const float* gp =
+                            gres + ((int64_t)c * g.n_nodes + g.node_base[l] + B * g.na_l[l] + A) * plane;
+                        acc = ad_block_pull(g, [&](int y, int x) { return gp[y * g.w + x]; }, X, Y, ky, kx, d, acc);
+                    }
+                }
+            } else {
                 acc = ad_pull(g, gres, c, l, Br, Ar, X, Y, reach, max(0, (Y - reach) / g.bs),
                               min(nby - 1, (Y + reach) / g.bs), max(0, (X - reach) / g.bs),
                               min(g.nbx - 1, (X + reach) / g.bs),
                               [&](int, int B, int A, int ky, int kx) {
-                                  return ad_fetch(g, p, shift, c, l, B, A, ky * g.nbx + kx);
+                                  return ad_unpack(brec[ad_record(g, c, l, B, A, ky * g.nbx + kx)]);
                               },
                               acc);
+            }
             gres[own] = acc;
         }
-        __syncthreads();  // rec is rewritten for the next tile
+        __syncthreads();  // lists and window are rewritten for the next tile
     }
 }
 
@@ -646,19 +845,20 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
     float* mxs = (float*)(W + Bl.o_max);
     float4* rayf = (float4*)(W + Bl.o_rayf);
     const int64_t rays = (int64_t)n_views * width * height;
-    hipLaunchKernelGGL(k_ad_pairs, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, d_cams, n_views, width,
-                       height, kin, vin, rayf);
+    hipLaunchKernelGGL(k_ad_records, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, s, g, d_cams, n_views,
+                       width, height, kin, vin, rayf);
     size_t sb = Bl.sort_bytes;
-    if (hipcub::DeviceRadixSort::SortPairs(W + Bl.o_sort, sb, kin, kout, vin, vout, (int)Bl.n_pairs, 0, Bl.end_bit, s) !=
+    if (hipcub::DeviceRadixSort::SortPairs(W + Bl.o_sort, sb, kin, kout, vin, vout, (int)Bl.n_recs, 0, Bl.end_bit, s) !=
         hipSuccess)
         return lf_fail(LF_EDEVICE, "radix sort failed");
-    // level-0 node planes of each channel: the samples not reached stay zero
+    uint32_t* start = (uint32_t*)(W + Bl.o_start);
+    hipLaunchKernelGGL(k_ad_nostart, dim3(4096), dim3(256), 0, s, start, Bl.n_samples);
+    hipLaunchKernelGGL(k_ad_heads, dim3((unsigned)((Bl.n_recs + 255) / 256)), dim3(256), 0, s, kout, Bl.n_recs, start);
+    // level-0 node planes of each channel, every sample written
     const int64_t plane = (int64_t)g.w * g.h, cstride = (int64_t)g.n_nodes * plane;
     float* g0 = d_grad_residual + (int64_t)g.node_base[0] * plane;
-    for (int c = 0; c < 3; c++)
-        hipLaunchKernelGGL(k_ad_fill, dim3(4096), dim3(256), 0, s, g0 + c * cstride, Bl.n_samples);
-    hipLaunchKernelGGL(k_ad_segments, dim3((unsigned)((Bl.n_pairs + 255) / 256)), dim3(256), 0, s, rayf, width, height,
-                       d_grad_out, kout, vout, Bl.n_pairs, cstride, g0);
+    hipLaunchKernelGGL(k_ad_samples, dim3((unsigned)((Bl.n_samples + 255) / 256)), dim3(256), 0, s, rayf, width, height,
+                       d_grad_out, kout, vout, start, Bl.n_recs, Bl.n_samples, g.w, g.h, cstride, g0);
     for (int l = 1; l < g.H; l++)
         hipLaunchKernelGGL(k_ad_tree, dim3(8192), dim3(256), 0, s, g, l, d_grad_residual);
     float* parts = (float*)(W + Bl.o_parts);
@@ -671,8 +871,12 @@ extern "C" lf_status lf_render_backward(const lf_handle* h, const float* d_resid
                            (const float2*)d_shift, d_grad_residual, (float2*)d_grad_shift, h->L.n_rec);
     {
         const int64_t n_tiles = 3 * (int64_t)g.n_refs * ((g.w + AD_TILE - 1) / AD_TILE) * ((g.h + AD_TILE - 1) / AD_TILE);
+        int4* brec = (int4*)(W + Bl.o_brec);
+        if (h->L.n_rec > 0)
+            hipLaunchKernelGGL(k_ad_blockrec, dim3((unsigned)((h->L.n_rec + 255) / 256)), dim3(256), 0, s, g, h->p,
+                               (const float2*)d_shift, h->L.n_rec, brec);
         hipLaunchKernelGGL(k_ad_reference, dim3((unsigned)std::min<int64_t>(std::max<int64_t>(n_tiles, 1), 65536)),
-                           dim3(256), 0, s, g, h->p, (const float2*)d_shift, mxs, d_grad_residual);
+                           dim3(256), 0, s, g, (const int4*)brec, mxs, d_grad_residual);
     }
     return lf_check_launch("render_backward");
 }

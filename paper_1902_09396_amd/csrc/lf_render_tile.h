@@ -1099,7 +1099,9 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                             acc = fmaf(tc[1][c], uv1, acc);
                             acc = fmaf(tc[2][c], uv2, acc);
                             acc = fmaf(tc[3][c], uv3, acc);
-                            out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i] = acc * (1.0f / 255.0f);
+                            // written once, never read here: streaming stores keep L2 for the stream
+                            __builtin_nontemporal_store(acc * (1.0f / 255.0f),
+                                                        &out[((int64_t)(v0 + q) * 3 + c) * npix_out + (int64_t)j * wo + i]);
                         }
                     }
                 }
@@ -1149,7 +1151,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                             float sm[16];
 #pragma unroll
                             for (int k = 0; k < 16; k++) sm[k] = (float)((s16[h][k] >> (8 * c)) & 255u);
-                            out[((int64_t)(v0 + q + h) * 3 + c) * npix_out + (int64_t)j * wo + i] = lf_blend16(sm, w);
+                            __builtin_nontemporal_store(
+                                lf_blend16(sm, w), &out[((int64_t)(v0 + q + h) * 3 + c) * npix_out + (int64_t)j * wo + i]);
                         }
                     }
                 }
