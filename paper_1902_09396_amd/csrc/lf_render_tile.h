@@ -190,6 +190,9 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
 // batched tile renderer
 // ---------------------------------------------------------------------------
 
+#ifndef GROUP_FIRST
+#define GROUP_FIRST(gmax) (gmax)
+#endif
 #define TW 32
 #define TH 8
 #define NT (TW * TH)
@@ -669,11 +672,17 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
 
     const int64_t npix_out = (int64_t)wo * ho;
     bool left = false;
-    int f = 0, n = gmax;
+    // group sizes: after a success the next group doubles, but stays below
+    // the smallest size that failed; that ceiling rises by one every four
+    // successes in a row
+    int f = 0, n = GROUP_FIRST(gmax), ceil_n = gmax + 1, streak = 0;
     while (f < nf) {
         n = min(n, nf - f);
-        // plan the group [f, f + n) (wave 0)
+        // plan the group [f, f + n) (wave 0); a plan that fails stops at the
+        // first check that fails
         if (wid == 0) {
+            int ok = 0;
+            do {
             uint32_t lo_ab = 0xFFFFFFFFu, hi_ab = 0u, lo_xy = 0xFFFFFFFFu, hi_xy = 0u;
             for (int q = f; q < f + n; q++) {
                 lo_ab = pk_min(lo_ab, fbox[q][0]);
@@ -693,7 +702,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const bool same = gp.cbox0 == bx0 && gp.cbox1 == bx1;  // cached entries hold this box
             const int cap0 = min(CMAX, BR / npix), cap1 = min(CMAX, BSV / (3 * npix));
             const int nA0 = amax - amin + 1, nB0 = bmax - bmin + 1;
-            int ok = nA0 * nB0 <= LMAX;
+            ok = nA0 * nB0 <= LMAX && npix <= BR;
+            if (!ok) break;
             // node maps start empty; cache entries that a node of this group
             // keeps write their index into the node's map (entry side), and
             // each node then reads its map (node side; same wave, LDS in order)
@@ -726,6 +736,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             const uint64_t newm0 = __ballot(new0);
             const int nnew0 = __popcll(newm0);
             ok = ok && nnew0 <= __popcll(free0);
+            if (!ok) break;
             if (new0 && ok) ent0 = lf_nth_bit(free0, __popcll(newm0 & ((1ull << lane) - 1ull)));
             // levels 1..H: ancestors of the new leaf views.  A node (B, A) of
             // level l covers leaf rows [B << l, (B + 1) << l) and columns
@@ -753,12 +764,16 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             int nnew1 = 0, nd = 3 * nbk * nnew0, ns = 0;
             int cnt[LF_MAX_LEVELS + 1];
             cnt[0] = nnew0;
+            const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
+            const int nfree1 = __popcll(free1);
+            ok = ok && nd <= BD;
+            if (!ok) break;
 #pragma unroll
             for (int l = 1; l <= LF_MAX_LEVELS; l++) {
                 entl[l] = -1;
                 newl[l] = false;
                 cnt[l] = 0;
-                if (l > g.H) continue;
+                if (l > g.H || !ok) continue;  // uniform; past a failed budget check nothing is counted
                 const int B0 = bmin >> l, A0 = amin >> l;
                 const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
                 if (nB * nA > LMAX) ok = 0;
@@ -776,10 +791,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                 nnew1 += cnt[l];
                 ns += 3 * cnt[l];
                 if (l < g.H) nd += 3 * nbk * cnt[l];
+                if (nnew1 > nfree1 || nd > BD || ns > SLOT_MAX) ok = 0;  // over a budget
             }
-            const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
-            ok = ok && nnew1 <= __popcll(free1) && nd <= BD && ns <= SLOT_MAX;
-            if (ok) {
+            if (!ok) break;
+            {
                 // commit: entries of the new nodes, node maps, new-node lists, keys
                 if (!same && lane < CMAX) {
                     ckey[0][lane] = CKEY_EMPTY;
@@ -847,10 +862,14 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     gp.cbox1 = bx1;
                 }
             }
+            } while (false);
+            if (!ok && lane == 0) gp.ok = 0;
         }
         __syncthreads();
         if (!gp.ok) {
             if (n > 1) {
+                if (n <= 4) ceil_n = n;  // views far apart: stop doubling into failures
+                streak = 0;
                 n = (n + 1) / 2;  // try half the group
                 __syncthreads();
                 continue;
@@ -1160,10 +1179,11 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         }
         __syncthreads();  // the next group's plan rewrites the node maps
         f += n;
-        // views far apart (random cameras) keep groups small: the next group
-        // tries twice this one's size, so a call does not re-plan a full group
-        // and halve it for every view
-        n = min(gmax, 2 * n);
+        if (++streak == 4) {
+            ceil_n = min(ceil_n + 1, gmax + 1);
+            streak = 0;
+        }
+        n = min(min(gmax, 2 * n), ceil_n - 1);
     }
     return left;
 }
