@@ -759,40 +759,81 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             }
             const uint64_t keep1 = __ballot(kneed);
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            int entl[LF_MAX_LEVELS + 1];
-            bool newl[LF_MAX_LEVELS + 1];
-            int nnew1 = 0, nd = 3 * nbk * nnew0, ns = 0;
+            int nd = 3 * nbk * nnew0;
             int cnt[LF_MAX_LEVELS + 1];
             cnt[0] = nnew0;
             const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
-            const int nfree1 = __popcll(free1);
             ok = ok && nd <= BD;
             if (!ok) break;
+            // Levels 1..H at once: the level rectangles laid end to end (level
+            // 1 first), node t of the concatenation in lane t % 64 of pass t / 64.
+            // Their total stays below 128: level l holds at most
+            // (nB0 / 2^l + 1)(nA0 / 2^l + 1) nodes and nA0 nB0 <= 64.
+            int off[LF_MAX_LEVELS + 2];
+            int total = 0;
 #pragma unroll
-            for (int l = 1; l <= LF_MAX_LEVELS; l++) {
-                entl[l] = -1;
-                newl[l] = false;
-                cnt[l] = 0;
-                if (l > g.H || !ok) continue;  // uniform; past a failed budget check nothing is counted
-                const int B0 = bmin >> l, A0 = amin >> l;
-                const int nB = (bmax >> l) - B0 + 1, nA = (amax >> l) - A0 + 1;
-                if (nB * nA > LMAX) ok = 0;
-                bool need = false;
-                if (lane < nB * nA && nB * nA <= LMAX) {
-                    const int qb = lf_div_small(lane, nA), B = B0 + qb, A = A0 + lane - qb * nA;
+            for (int l = 1; l <= LF_MAX_LEVELS + 1; l++) {
+                off[l] = total;
+                if (l <= g.H) {
+                    const int nBl = (bmax >> l) - (bmin >> l) + 1, nAl = (amax >> l) - (amin >> l) + 1;
+                    if (nBl * nAl > LMAX) ok = 0;
+                    total += nBl * nAl;
+                }
+            }
+            ok = ok && total <= 128;
+            if (!ok) break;
+            bool newp[2];
+            int lvp[2], idxp[2];
+            uint64_t nmp[2];
+#pragma unroll
+            for (int pp = 0; pp < 2; pp++) {
+                const int t = 64 * pp + lane;
+                newp[pp] = false;
+                lvp[pp] = 1;
+                idxp[pp] = 0;
+                if (t < total) {
+                    // level of node t and its place in that level's rectangle
+                    int l = 1, base = 0;
+#pragma unroll
+                    for (int k = 2; k <= LF_MAX_LEVELS; k++)
+                        if (k <= g.H && t >= off[k]) {
+                            l = k;
+                            base = off[k];
+                        }
+                    const int B0 = bmin >> l, A0 = amin >> l, nA = (amax >> l) - A0 + 1;
+                    const int e = t - base;
+                    const int qb = lf_div_small(e, nA), B = B0 + qb, A = A0 + e - qb * nA;
+                    // A node (B, A) of level l covers leaf rows [B << l, (B + 1) << l)
+                    // and columns [A << l, (A + 1) << l); it is needed when one of the
+                    // new leaf views lies there.
                     const int rb0 = max(B << l, bmin) - bmin, rb1 = min(((B + 1) << l) - 1, bmax) - bmin;
                     const int ra0 = max(A << l, amin) - amin, ra1 = min(((A + 1) << l) - 1, amax) - amin;
+                    bool need = false;
                     for (int r = rb0; r <= rb1 && !need; r++)
                         need = ((newm0 >> (r * nA0 + ra0)) & ((2ull << (ra1 - ra0)) - 1ull)) != 0ull;
-                    entl[l] = nodemap[l][lane];
+                    newp[pp] = need && nodemap[l][e] < 0;
+                    lvp[pp] = l;
+                    idxp[pp] = e;
                 }
-                newl[l] = need && entl[l] < 0;
-                cnt[l] = __popcll(__ballot(newl[l]));
-                nnew1 += cnt[l];
-                ns += 3 * cnt[l];
-                if (l < g.H) nd += 3 * nbk * cnt[l];
-                if (nnew1 > nfree1 || nd > BD || ns > SLOT_MAX) ok = 0;  // over a budget
+                nmp[pp] = __ballot(newp[pp]);
             }
+            // new nodes per level: the set bits of each level's segment
+            int nnew1 = 0;
+#pragma unroll
+            for (int l = 1; l <= LF_MAX_LEVELS; l++) {
+                cnt[l] = 0;
+                if (l > g.H) continue;
+#pragma unroll
+                for (int pp = 0; pp < 2; pp++) {
+                    const int lo = min(max(off[l] - 64 * pp, 0), 64), hi = min(max(off[l + 1] - 64 * pp, 0), 64);
+                    const uint64_t m = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~(lo >= 64 ? ~0ull : ((1ull << lo) - 1ull));
+                    cnt[l] += __popcll(nmp[pp] & m);
+                }
+                nnew1 += cnt[l];
+                if (l < g.H) nd += 3 * nbk * cnt[l];
+            }
+            const int ns = 3 * nnew1;
+            ok = ok && nnew1 <= __popcll(free1) && nd <= BD && ns <= SLOT_MAX;
             if (!ok) break;
             {
                 // commit: entries of the new nodes, node maps, new-node lists, keys
@@ -807,29 +848,36 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
                     const int qb = lf_div_small(lane, nA0);
                     ckey[0][ent0] = lf_node_key(0, bmin + qb, amin + lane - qb * nA0);
                 }
-                int q0 = 0, sb = 0, db = 3 * nbk * nnew0;
-                if (lane == 0) gp.dbase[0] = 0;
+                // a new node's entry is the r-th free one, r its rank among the
+                // new nodes of all levels (level order); its list index is r less
+                // the new nodes of the levels before
 #pragma unroll
-                for (int l = 1; l <= LF_MAX_LEVELS; l++) {
-                    if (l > g.H) continue;
-                    const int B0 = bmin >> l, A0 = amin >> l, nA = (amax >> l) - A0 + 1;
-                    const uint64_t nm = __ballot(newl[l]);
-                    int e = entl[l];
-                    if (newl[l]) {
-                        const int k = __popcll(nm & ((1ull << lane) - 1ull));
-                        e = lf_nth_bit(free1, q0 + k);
-                        nodelist[l][k] = (uint16_t)(lane | (e << 8));
-                        const int qb = lf_div_small(lane, nA);
-                        ckey[1][e] = lf_node_key(l, B0 + qb, A0 + lane - qb * nA);
-                        nodemap[l][lane] = (int8_t)e;
+                for (int pp = 0; pp < 2; pp++) {
+                    if (newp[pp]) {
+                        const int r = (pp ? __popcll(nmp[0]) : 0) + __popcll(nmp[pp] & ((1ull << lane) - 1ull));
+                        const int e = lf_nth_bit(free1, r);
+                        int before = 0;
+#pragma unroll
+                        for (int k = 1; k < LF_MAX_LEVELS; k++)
+                            if (k < lvp[pp]) before += cnt[k];
+                        const int l = lvp[pp], nA = (amax >> l) - (amin >> l) + 1;
+                        const int qb = lf_div_small(idxp[pp], nA);
+                        nodelist[l][r - before] = (uint16_t)(idxp[pp] | (e << 8));
+                        ckey[1][e] = lf_node_key(l, (bmin >> l) + qb, (amin >> l) + idxp[pp] - qb * nA);
+                        nodemap[lvp[pp]][idxp[pp]] = (int8_t)e;
                     }
-                    if (lane == 0) {
+                }
+                if (lane == 0) {
+                    int sb = 0, db = 3 * nbk * nnew0;
+                    gp.dbase[0] = 0;
+#pragma unroll
+                    for (int l = 1; l <= LF_MAX_LEVELS; l++) {
+                        if (l > g.H) continue;
                         gp.sbase[l] = sb;
                         if (l < g.H) gp.dbase[l] = db;
+                        sb += 3 * cnt[l];
+                        if (l < g.H) db += 3 * nbk * cnt[l];
                     }
-                    q0 += cnt[l];
-                    sb += 3 * cnt[l];
-                    if (l < g.H) db += 3 * nbk * cnt[l];
                 }
             }
             if (lane == 0) {
