@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-sweep", default="", help="more request rates (comma list) for a saturation sweep")
     ap.add_argument("--serve-sweep-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-streams", type=int, default=4, help="launches in flight at once (1..4)")
     return ap.parse_args()
 
 
@@ -264,7 +265,8 @@ def serve_bench(args):
         field, cams, wh, arrival = schedule(rate, seconds, seed)
         rays = float((wh[:, 0].astype(np.int64) * wh[:, 1]).sum())
         log("%.0f req/s: %d requests, %.2f Grays offered over %.1f s" % (rate, field.size, rays / 1e9, arrival[-1]))
-        srv = Server(fields, pool_bytes=4 << 30, max_slots=64, max_tiles=16384, chunk_tiles=1024, n_streams=2)
+        srv = Server(fields, pool_bytes=4 << 30, max_slots=64, max_tiles=16384, chunk_tiles=1024,
+                     n_streams=args.serve_streams)
         t0 = time.time()
         lat, mk = srv.replay(field, cams, wh, arrival)
         stats = srv.stats()

@@ -311,6 +311,9 @@ typedef struct {
 
 typedef struct {
     int64_t submitted, admitted, completed, launches, tiles;
+    int64_t graph_launches; /* launches that replayed the captured graph (the rest: direct, one workgroup per tile) */
+    double queue_ms;        /* summed over completed requests: submission to the first launch of their tiles */
+    double flight_ms;       /* summed over completed requests: that launch to the completion seen */
 } lf_server_stats;
 
 /* fields: n_fields loaded handles (block size >= 4), borrowed for the

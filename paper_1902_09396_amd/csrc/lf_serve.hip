@@ -8,9 +8,13 @@
 // does not hold back a 256x256 one) until `max_tiles` tiles are queued.  Up to
 // `n_streams` launches are in flight at once on separate streams; requests
 // that arrive meanwhile are admitted as soon as a slot and output memory are
-// free, and their tiles join the next launch.  Each launch replays a graph
-// captured once per stream (work-list upload + kernel); the kernel reads the
-// work count from the uploaded list, so the graph never changes.
+// free, and their tiles join the next launch.  A launch copies the part of
+// its work list it uses, then replays a graph of the two kernels captured once
+// per stream (the kernels read the tile count from the list, so the graph
+// never changes); a launch of fewer tiles than the graph's workgroups
+// launches one workgroup per tile instead.  The scheduler polls the streams'
+// events and issues the copies and launches without the lock, which it takes
+// only to update the request tables, so submissions do not wait on HIP calls.
 //
 // Tiles are rendered by the same routine as lf_render_views (one view per
 // tile), so a request's pixels do not depend on what else is in flight.
@@ -68,13 +72,12 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
     const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
     int32_t* fb = work + serve_fb_off(max_tiles);
     if (threadIdx.x == 0) cur_field = -1;
-    // tiles come from a queue (their costs differ widely): every workgroup
-    // takes the next one until the queue is past n
-    for (;;) {
-        if (threadIdx.x == 0) next = atomicAdd(fb + 1, 1);
-        __syncthreads();
-        const int w = next;  // read before the barrier below; rewritten only after it
-        if (w >= n) break;
+    __syncthreads();
+    // workgroup b renders tile b first; the tiles past the grid come from a
+    // queue (their costs differ widely): every workgroup takes the next one
+    // until the queue is past n
+    for (int w = blockIdx.x;;) {
+        if (w >= n) break;  // uniform
         const ServeWork it = items[w];
         const ServeSlot* sl = slots + it.slot;
         const int field = sl->field;
@@ -94,6 +97,10 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
         const bool left = lf_tile_views<false, SMALL_BLOCKS>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
                                                reinterpret_cast<float*>(pool + sl->out_off), S);
         if (left && threadIdx.x == 0) work[serve_fbl_off(max_tiles) + atomicAdd(fb, 1)] = w;
+        if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(fb + 1, 1);
+        __syncthreads();
+        w = next;
+        __syncthreads();  // every thread has read `next` before thread 0 rewrites it
     }
 }
 
@@ -133,6 +140,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// how long the scheduler keeps polling after its last launch before it
+// blocks on the next submission
+#define SERVE_SPIN_US 5000
+
 struct Request {
     int64_t id;
     int field, wo, ho;
@@ -140,7 +151,7 @@ struct Request {
     int64_t out_bytes, out_off = -1;
     int slot = -1;
     int tiles_x = 0, tiles_total = 0, next_tile = 0, tiles_done = 0;
-    Clock::time_point t_submit, t_done;
+    Clock::time_point t_submit, t_launch, t_done;
     bool done = false;
     bool auto_release = false;
 };
@@ -220,22 +231,25 @@ struct lf_server {
     PoolAlloc alloc{0};
     int64_t next_id = 1;
     std::atomic<bool> stop{false};
+    // read by the scheduler without the lock, changed under it: requests
+    // waiting for admission, admitted tiles not yet in a launch
+    std::atomic<int64_t> n_pending{0}, tiles_left{0};
     std::thread worker;
     std::string error;
     lf_server_stats stats{};
 
     void run();
-    bool launch(StreamCtx& sc);
+    int build(StreamCtx& sc);
+    void issue(StreamCtx& sc, int n);
 };
 
+// The graph holds the two kernels; each launch first copies the part of the
+// work list it uses (and the zeroed counters) on the same stream, so a launch
+// of a few tiles does not move the whole list.
 static lf_status capture_graph(lf_server* S, StreamCtx& sc)
 {
-    // upload the whole list and the zero fallback count (no memset node in the graph)
-    const size_t wbytes = sizeof(int32_t) * serve_fbl_off(S->cfg.max_tiles);
     if (hipStreamBeginCapture(sc.s, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return lf_fail(LF_EDEVICE, "stream capture failed");
-    hipMemcpyAsync(sc.d_work, sc.h_work, wbytes, hipMemcpyHostToDevice, sc.s);
-    hipMemcpyAsync(sc.d_slots, S->h_slots, sizeof(ServeSlot) * S->cfg.max_slots, hipMemcpyHostToDevice, sc.s);
     if (S->small)
         hipLaunchKernelGGL(k_serve_tiles<true>, dim3(S->grid), dim3(NT), LDS_DYN_BYTES_SB, sc.s, S->d_geoms, S->d_ptrs,
                            sc.d_slots, sc.d_work, S->cfg.max_tiles, S->pool);
@@ -250,9 +264,10 @@ static lf_status capture_graph(lf_server* S, StreamCtx& sc)
     return LF_OK;
 }
 
-bool lf_server::launch(StreamCtx& sc)
+// Work list of the next launch on stream sc (caller holds mu): up to
+// chunk_tiles tiles of each active request in turn; returns the tile count.
+int lf_server::build(StreamCtx& sc)
 {
-    // caller holds mu
     int n = 0;
     sc.credits.clear();
     ServeWork* items = reinterpret_cast<ServeWork*>(sc.h_work + 1);
@@ -267,6 +282,7 @@ bool lf_server::launch(StreamCtx& sc)
                 const int t = r.next_tile + k;
                 items[n + k] = ServeWork{r.slot, t % r.tiles_x, t / r.tiles_x};
             }
+            if (r.next_tile == 0) r.t_launch = Clock::now();
             r.next_tile += take;
             n += take;
             sc.credits.emplace_back(id, take);
@@ -274,99 +290,132 @@ bool lf_server::launch(StreamCtx& sc)
             if (n >= cfg.max_tiles) break;
         }
     }
-    if (n == 0) return false;
+    if (n == 0) return 0;
+    tiles_left -= n;
     sc.h_work[0] = n;
-    if (cfg.use_graphs) {
-        hipGraphLaunch(sc.exec, sc.s);
-    } else {
-        const size_t fo = serve_fb_off(cfg.max_tiles);
-        hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
-        hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, 3 * sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
-        hipMemcpyAsync(sc.d_slots, h_slots, sizeof(ServeSlot) * cfg.max_slots, hipMemcpyHostToDevice, sc.s);
-        if (small)
-            hipLaunchKernelGGL(k_serve_tiles<true>, dim3(grid), dim3(NT), LDS_DYN_BYTES_SB, sc.s, d_geoms, d_ptrs,
-                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
-        else
-            hipLaunchKernelGGL(k_serve_tiles<false>, dim3(grid), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs,
-                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
-        hipLaunchKernelGGL(k_serve_fallback, dim3(grid), dim3(NT), 0, sc.s, d_geoms, d_ptrs, sc.d_slots, sc.d_work,
-                           cfg.max_tiles, pool);
-    }
-    hipEventRecord(sc.ev, sc.s);
     sc.busy = true;
     stats.launches++;
     stats.tiles += n;
-    return true;
+    if (cfg.use_graphs && n >= grid) stats.graph_launches++;
+    return n;
+}
+
+// Upload and launch the list build() wrote (scheduler thread, without the
+// lock: the stream, its buffers and the slot table entries of its requests
+// are not touched by anyone else until the launch completes).
+void lf_server::issue(StreamCtx& sc, int n)
+{
+    const size_t fo = serve_fb_off(cfg.max_tiles);
+    hipMemcpyAsync(sc.d_work, sc.h_work, sizeof(int32_t) * (1 + 3 * (size_t)n), hipMemcpyHostToDevice, sc.s);
+    hipMemcpyAsync(sc.d_work + fo, sc.h_work + fo, 3 * sizeof(int32_t), hipMemcpyHostToDevice, sc.s);
+    hipMemcpyAsync(sc.d_slots, h_slots, sizeof(ServeSlot) * cfg.max_slots, hipMemcpyHostToDevice, sc.s);
+    if (cfg.use_graphs && n >= grid) {
+        hipGraphLaunch(sc.exec, sc.s);
+    } else {
+        // fewer tiles than the graph's workgroups: launch one workgroup per tile
+        const int gl = std::min(grid, n);
+        if (small)
+            hipLaunchKernelGGL(k_serve_tiles<true>, dim3(gl), dim3(NT), LDS_DYN_BYTES_SB, sc.s, d_geoms, d_ptrs,
+                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
+        else
+            hipLaunchKernelGGL(k_serve_tiles<false>, dim3(gl), dim3(NT), LDS_DYN_BYTES, sc.s, d_geoms, d_ptrs,
+                               sc.d_slots, sc.d_work, cfg.max_tiles, pool);
+        hipLaunchKernelGGL(k_serve_fallback, dim3(gl), dim3(NT), 0, sc.s, d_geoms, d_ptrs, sc.d_slots, sc.d_work,
+                           cfg.max_tiles, pool);
+    }
+    hipEventRecord(sc.ev, sc.s);
 }
 
 void lf_server::run()
 {
-    std::unique_lock<std::mutex> lk(mu);
+    auto last_busy = Clock::now();
+    std::vector<char> ready(streams.size());
+    std::vector<std::pair<int, int>> to_issue;  // (stream, tiles)
     while (!stop.load()) {
-        // completions
-        for (StreamCtx& sc : streams) {
-            if (!sc.busy || hipEventQuery(sc.ev) != hipSuccess) continue;
-            sc.busy = false;
+        // completions, polled without the lock (the streams are this thread's)
+        bool any_ready = false, any_free = false;
+        for (size_t k = 0; k < streams.size(); k++) {
+            ready[k] = streams[k].busy && hipEventQuery(streams[k].ev) == hipSuccess;
+            any_ready |= ready[k] != 0;
+            any_free |= !streams[k].busy;
+        }
+        to_issue.clear();
+        if (any_ready || ((any_free || any_ready) && (n_pending.load() > 0 || tiles_left.load() > 0))) {
+            std::lock_guard<std::mutex> lk(mu);
             const auto now = Clock::now();
-            for (auto& cr : sc.credits) {
-                Request& r = reqs[cr.first];
-                r.tiles_done += cr.second;
-                if (r.tiles_done == r.tiles_total) {
-                    r.done = true;
-                    r.t_done = now;
-                    slot_owner[r.slot] = -1;
-                    active.erase(std::find(active.begin(), active.end(), r.id));
-                    stats.completed++;
-                    if (r.auto_release) {
-                        alloc.release(r.out_off, r.out_bytes);
+            for (size_t k = 0; k < streams.size(); k++) {
+                if (!ready[k]) continue;
+                StreamCtx& sc = streams[k];
+                sc.busy = false;
+                for (auto& cr : sc.credits) {
+                    Request& r = reqs[cr.first];
+                    r.tiles_done += cr.second;
+                    if (r.tiles_done == r.tiles_total) {
+                        r.done = true;
+                        r.t_done = now;
+                        stats.queue_ms += std::chrono::duration<double, std::milli>(r.t_launch - r.t_submit).count();
+                        stats.flight_ms += std::chrono::duration<double, std::milli>(now - r.t_launch).count();
+                        slot_owner[r.slot] = -1;
+                        active.erase(std::find(active.begin(), active.end(), r.id));
+                        stats.completed++;
+                        if (r.auto_release) alloc.release(r.out_off, r.out_bytes);
                     }
                 }
+                sc.credits.clear();
             }
-            sc.credits.clear();
-            cv_done.notify_all();
-        }
-        // admission (FIFO: the head waits until it fits)
-        while (!pending.empty()) {
-            Request& r = reqs[pending.front()];
-            int slot = -1;
-            for (int k = 0; k < cfg.max_slots; k++)
-                if (slot_owner[k] < 0) {
-                    slot = k;
-                    break;
+            if (any_ready) cv_done.notify_all();
+            // admission (FIFO: the head waits until it fits)
+            while (!pending.empty()) {
+                Request& r = reqs[pending.front()];
+                int slot = -1;
+                for (int k = 0; k < cfg.max_slots; k++)
+                    if (slot_owner[k] < 0) {
+                        slot = k;
+                        break;
+                    }
+                if (slot < 0) break;
+                const int64_t off = alloc.alloc(r.out_bytes);
+                if (off < 0) break;
+                r.out_off = off;
+                r.slot = slot;
+                slot_owner[slot] = r.id;
+                ServeSlot& hs = h_slots[slot];
+                memcpy(hs.cam, r.cam, sizeof hs.cam);
+                hs.field = r.field;
+                hs.wo = r.wo;
+                hs.ho = r.ho;
+                hs.tiles_x = r.tiles_x;
+                hs.out_off = (uint64_t)off;  // reaches the device with the next launch's slot table
+                active.push_back(r.id);
+                pending.pop_front();
+                n_pending--;
+                tiles_left += r.tiles_total;
+                stats.admitted++;
+            }
+            // new launches on free streams
+            for (size_t k = 0; k < streams.size(); k++)
+                if (!streams[k].busy) {
+                    const int n = build(streams[k]);
+                    if (n > 0) to_issue.emplace_back((int)k, n);
                 }
-            if (slot < 0) break;
-            const int64_t off = alloc.alloc(r.out_bytes);
-            if (off < 0) break;
-            r.out_off = off;
-            r.slot = slot;
-            slot_owner[slot] = r.id;
-            ServeSlot& hs = h_slots[slot];
-            memcpy(hs.cam, r.cam, sizeof hs.cam);
-            hs.field = r.field;
-            hs.wo = r.wo;
-            hs.ho = r.ho;
-            hs.tiles_x = r.tiles_x;
-            hs.out_off = (uint64_t)off;  // reaches the device with the next launch's slot table
-            active.push_back(r.id);
-            pending.pop_front();
-            stats.admitted++;
         }
-        // new launches on free streams
-        bool launched = false;
-        for (StreamCtx& sc : streams)
-            if (!sc.busy && launch(sc)) launched = true;
+        for (auto& t : to_issue) issue(streams[t.first], t.second);
         bool inflight = false;
         for (StreamCtx& sc : streams) inflight |= sc.busy;
-        if (!launched) {
-            if (inflight) {
-                // poll the launches in flight without sleeping: a timed sleep
-                // lasts tens of microseconds (timer slack), which a finished
-                // request would wait on top of its render
-                lk.unlock();
+        const auto now = Clock::now();
+        if (!to_issue.empty() || inflight || n_pending.load() > 0) last_busy = now;
+        if (to_issue.empty()) {
+            if (inflight || now - last_busy < std::chrono::microseconds(SERVE_SPIN_US)) {
+                // poll without sleeping while launches are in flight, and for a
+                // while after the last one: a timed sleep or a condition-variable
+                // wake-up lasts tens of microseconds, which a finished request
+                // (or a new one arriving at an idle server) would wait on top of
+                // its render
                 std::this_thread::yield();
-                lk.lock();
             } else {
-                cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait_for(lk, std::chrono::milliseconds(2),
+                                 [this] { return stop.load() || n_pending.load() > 0; });
             }
         }
     }
@@ -457,6 +506,7 @@ extern "C" lf_status lf_server_submit(lf_server* S, int32_t field, const float* 
         *id = r.id;
         S->reqs.emplace(r.id, r);
         S->pending.push_back(r.id);
+        S->n_pending++;
         S->stats.submitted++;
     }
     S->cv_work.notify_one();

@@ -23,7 +23,8 @@ class ServerConfig(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
-                ("launches", C.c_int64), ("tiles", C.c_int64)]
+                ("launches", C.c_int64), ("tiles", C.c_int64), ("graph_launches", C.c_int64),
+                ("queue_ms", C.c_double), ("flight_ms", C.c_double)]
 
 
 _SIGS = {
