@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--serve-sweep", default="", help="more request rates (comma list) for a saturation sweep")
     ap.add_argument("--serve-sweep-seconds", type=float, default=2.0)
     ap.add_argument("--serve-streams", type=int, default=4, help="launches in flight at once (1..4)")
+    ap.add_argument("--quant-sweep", default="",
+                    help="comma list of quantisation steps: render the workload's path from a stream coded at each")
     return ap.parse_args()
 
 
@@ -109,6 +111,9 @@ def main():
         return
     if args.rd:
         rd_bench(args)
+        return
+    if args.quant_sweep:
+        quant_sweep(args)
         return
     cfg = lfscene.get_config(args.workload)
     L = cfg["lf"]
@@ -465,6 +470,52 @@ def decode_field(field, nb, na, h, w):
             coords[:, 1] = a
             out[b, a] = field.decode_pixels(coords)
     return out.reshape(nb, na, h, w, 3)
+
+
+def quant_sweep(args):
+    """The render path of a workload from streams coded at several uniform
+    quantisation steps (the 17x17x512^2 configuration names steps 2 to 8):
+    stream size, PSNR of the decoded field, and the render kernel's time and
+    roofline fraction on each."""
+    import torch
+
+    import lfscene
+    from paper_1902_09396_amd import lf
+
+    cfg = lfscene.get_config(args.workload)
+    L = cfg["lf"]
+    light = lfscene.make_lf(L["na"], L["nb"], L["h"], L["w"], L["spec"], L["seed"])
+    light_dev = torch.from_numpy(light).cuda()
+    cams = torch.from_numpy(lfscene.make_views(cfg)).cuda()
+    V, wo, ho = cams.shape[0], cfg["views"]["wo"], cfg["views"]["ho"]
+    out = torch.empty((V, 3, ho, wo), dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    points = {}
+    for step in (int(x) for x in args.quant_sweep.split(",") if x):
+        e = dict(cfg["enc"])
+        e["step"] = [step] * e["levels"]
+        bpp, psnr, nbytes, _ = rd_point(light, e, light_dev)
+        field = lf.LightField(lf.encode(light, e), device="cuda:0")
+        fp = float(field.footprint_bytes(cams, wo, ho).sum())
+        for _ in range(args.warmup):
+            field.render_views(cams, wo, ho, out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(s)
+        for _ in range(args.steps):
+            field.render_views(cams, wo, ho, out)
+        b.record(s)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        field.close()
+        points[str(step)] = {"stream_bytes": nbytes, "bpp": round(bpp, 4), "psnr_db": round(psnr, 3),
+                             "kernel_ms": round(ms, 4), "grays_per_s": round(V * wo * ho / (ms * 1e-3) / 1e9, 3),
+                             "algorithmic_bytes_per_launch": int(fp),
+                             "roofline_frac": round(fp / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("step %d: %d bytes, %.2f dB, %.4f ms, frac %.4f" % (step, nbytes, psnr, ms, points[str(step)]["roofline_frac"]))
+    print(json.dumps({"metric": "render path over quantisation steps", "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": args.workload, "views": V, "width": wo, "height": ho}, "steps": points}),
+          flush=True)
 
 
 def rd_point(light, enc, light_dev=None):
