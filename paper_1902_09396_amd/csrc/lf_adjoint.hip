@@ -36,6 +36,7 @@
 
 #define AD_MAX_PARTS 1024  // partial maxima of the shift reduction
 #define AD_TILE 16         // reference tile side of the pull kernel
+#define AD_PPT 1           // pixels per thread (rows AD_TILE * k / AD_PPT apart)
 #define AD_CAND_MAX 384    // candidate blocks a tile stages in LDS
 #define AD_WIN_MAX 4800    // sibling gradient values a tile stages in LDS (3 windows of up to 40 x 40)
 
@@ -272,6 +273,9 @@ static lf_status bwd_layout(const lf_handle* h, int nv, int wo, int ho, BwdLayou
     // the record sort takes an int count: at most 2^31 - 1 records (2^29 - 1 rays per call)
     if (B->n_recs > 0x7FFFFFFFll) return lf_fail(LF_EINVAL, "too many rays for one backward call (at most 2^29 - 1)");
     if (B->n_samples >= 0xFFFFFFFFll) return lf_fail(LF_EINVAL, "too many light-field samples");
+    // the reference pull indexes its 16x16 tiles with 32-bit integers
+    if (3 * (int64_t)g.n_refs * ((g.w + AD_TILE - 1) / AD_TILE) * ((g.h + AD_TILE - 1) / AD_TILE) > 0x7FFFFFFFll)
+        return lf_fail(LF_EINVAL, "too many reference tiles for the adjoint");
     int eb = 1;
     while (eb < 32 && ((int64_t)1 << eb) < B->n_samples) eb++;
     B->end_bit = eb;
@@ -600,15 +604,16 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, const int4* __re
     __shared__ int wcount[4];
     const int64_t plane = (int64_t)g.w * g.h;
     const int tiles_x = (g.w + AD_TILE - 1) / AD_TILE, tiles_y = (g.h + AD_TILE - 1) / AD_TILE;
-    const int64_t per_plane = (int64_t)tiles_x * tiles_y;
-    const int64_t n_tiles = 3 * (int64_t)g.n_refs * per_plane;
+    // 32-bit tile indices (the host bounds the tile count by 2^31 - 1)
+    const int per_plane = tiles_x * tiles_y;
+    const int n_tiles = 3 * g.n_refs * per_plane;
     const int reach = (int)ceilf(fminf(maxshift[0], (float)(g.w + g.h))) + 2;
     const int nby = g.h / g.bs;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int64_t T = blockIdx.x; T < n_tiles; T += gridDim.x) {
-        const int64_t rp = T / per_plane;
-        const int tt = (int)(T - rp * per_plane);
-        const int c = (int)(rp / g.n_refs), r = (int)(rp % g.n_refs);
+    for (int T = blockIdx.x; T < n_tiles; T += gridDim.x) {
+        const int rp = T / per_plane;
+        const int tt = T - rp * per_plane;
+        const int c = rp / g.n_refs, r = rp - c * g.n_refs;
         int l = 0;
         while (l + 1 < g.H && r >= g.ref_base[l + 1]) l++;
         const int loc = r - g.ref_base[l];
@@ -644,14 +649,21 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, const int4* __re
                 }
             }
         }
-        const int X = tx0 + (int)threadIdx.x % AD_TILE, Y = ty0 + (int)threadIdx.x / AD_TILE;
-        const bool mine = X <= tx1 && Y <= ty1;
-        const int64_t own = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + Y * g.w + X;
-        const float own_g = mine ? gres[own] : 0.0f;
+        // pixel k of this thread: column tid % AD_TILE, row tid / AD_TILE + k AD_TILE / AD_PPT
+        constexpr int RSTEP = AD_TILE / AD_PPT;
+        const int X = tx0 + (int)threadIdx.x % AD_TILE, Y0 = ty0 + (int)threadIdx.x / AD_TILE;
+        const int64_t own0 = ((int64_t)c * g.n_nodes + g.node_base[l] + Br * g.na_l[l] + Ar) * plane + X;
+        float own_g[AD_PPT];
+#pragma unroll
+        for (int k = 0; k < AD_PPT; k++) {
+            const int Y = Y0 + k * RSTEP;
+            own_g[k] = (X <= tx1 && Y <= ty1) ? gres[own0 + (int64_t)Y * g.w] : 0.0f;
+        }
         if (windowed) {
             // all of the three windows' loads in flight at once: value e of
-            // sibling window s (row e / ww, column e % ww; the row from a
-            // float reciprocal, exact for e < 2^13 and ww <= 64)
+            // the concatenation is value rr of sibling window sw (row rr / ww,
+            // column rr % ww; the row from a float reciprocal, exact for
+            // rr < 2^13 and ww <= 64)
             constexpr int WL = (AD_WIN_MAX + 255) / 256;
             const float rw = 1.0f / (float)ww;
             const int64_t nb0 = (int64_t)c * g.n_nodes + g.node_base[l];
@@ -715,8 +727,11 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, const int4* __re
                 __syncthreads();  // wcount is rewritten by the next round; lists and window complete
             }
         }
-        if (mine) {
-            float acc = own_g;
+#pragma unroll
+        for (int kp = 0; kp < AD_PPT; kp++) {
+        const int Y = Y0 + kp * RSTEP;
+        if (X <= tx1 && Y <= ty1) {
+            float acc = own_g[kp];
             if (windowed && X > 0 && X < g.w - 1 && Y > 0 && Y < g.h - 1) {
                 // away from the image border each tap (oy, ox) landing on the
                 // pixel comes from source pixel (Y - iy - oy, X - ix - ox) alone,
@@ -763,7 +778,8 @@ __global__ void __launch_bounds__(256) k_ad_reference(LfGeom g, const int4* __re
                               },
                               acc);
             }
-            gres[own] = acc;
+            gres[own0 + (int64_t)Y * g.w] = acc;
+        }
         }
         __syncthreads();  // lists and window are rewritten for the next tile
     }
