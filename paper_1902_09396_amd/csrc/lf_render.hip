@@ -35,8 +35,7 @@ __global__ void __launch_bounds__(256) k_render_rays(LfGeom g, LfPtrs p, const f
     for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
 }
 
-// 4:2:0 streams, one thread per ray: each of the 16 samples is luma plus
-// up-sampled Co and Cg (lf_chroma_up), blended as in lf_render_one.
+// 4:2:0 streams, one thread per ray (lf_render_one420).
 __global__ void __launch_bounds__(256) k_render_rays420(LfGeom g, LfPtrs p, LfGeom gc, LfPtrs pc,
                                                         const float* __restrict__ cams, int nv, int wo, int ho,
                                                         float* __restrict__ out, int lod)
@@ -47,25 +46,10 @@ __global__ void __launch_bounds__(256) k_render_rays420(LfGeom g, LfPtrs p, LfGe
     const int v = (int)(r / npix);
     const int64_t px = r - (int64_t)v * npix;
     const int j = (int)(px / wo), i = (int)(px % wo);
-    const Ray ray = lf_ray_setup(g, cams + 18 * v, i, j);
-    uint32_t rgb[16];
-#pragma unroll 1
-    for (int k = 0; k < 16; k++) {
-        const int b = (k & 8) ? ray.b1 : ray.b0, a = (k & 4) ? ray.a1 : ray.a0;
-        const int y = (k & 2) ? ray.y1 : ray.y0, x = (k & 1) ? ray.x1 : ray.x0;
-        int R, G, B;
-        lf_ycocg_to_rgb(lf_decode_channel(g, p, 0, b, a, y, x, lod), lf_chroma_up(gc, pc, 0, b, a, y, x, lod),
-                        lf_chroma_up(gc, pc, 1, b, a, y, x, lod), R, G, B);
-        rgb[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
-    }
-    const BlendW w = lf_blend_weights(ray);
+    float o[3];
+    lf_render_one420(g, p, gc, pc, cams + 18 * v, i, j, o, lod);
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        float sm[16];
-#pragma unroll
-        for (int k = 0; k < 16; k++) sm[k] = (float)((rgb[k] >> (8 * c)) & 255u);
-        out[((int64_t)v * 3 + c) * npix + px] = lf_blend16(sm, w);
-    }
+    for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + px] = o[c];
 }
 
 lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv, int wo, int ho, float* d_out,
@@ -85,10 +69,12 @@ lf_status lf_launch_render_rays(const lf_handle* h, const float* d_cams, int nv,
     return lf_check_launch("render_rays");
 }
 
-template <bool SMALL_BLOCKS>
-__global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
-                                                     int wo, int ho, int tiles_x, int tiles_y, int chunk, int fpg,
-                                                     int64_t n_full, int split, float* __restrict__ out)
+// C420: a 4:2:0 stream, chroma geometry gc, pc (unused otherwise).
+template <bool SMALL_BLOCKS, bool C420>
+__global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, LfGeom gc, LfPtrs pc,
+                                                     const float* __restrict__ cams, int nv, int wo, int ho,
+                                                     int tiles_x, int tiles_y, int chunk, int fpg, int64_t n_full,
+                                                     int split, float* __restrict__ out)
 {
     // A workgroup renders one screen tile for a chunk of consecutive views
     // (groups of fpg views, decoded values cached between the groups).
@@ -127,7 +113,7 @@ __global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, cons
         nf = min(per, c1 - v0);
         if (nf <= 0) return;
     }
-    lf_tile_views<false, SMALL_BLOCKS>(g, p, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
+    lf_tile_views<false, SMALL_BLOCKS, C420>(g, p, gc, pc, cams, v0, nf, fpg, wo, ho, txi, tyi, out, S);
 }
 
 // Per-ray rendering of the (view, tile) pairs the batched kernel marked.
@@ -135,9 +121,10 @@ __global__ void __launch_bounds__(NT, 3) k_render_batch(LfGeom g, LfPtrs p, cons
 // of them at once (one per thread), compacts the marked ones, and renders
 // them one tile at a time, so a launch whose views are mostly marked (tiles
 // far minified) still spreads them over the whole grid.
-__global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, const float* __restrict__ cams, int nv,
-                                                        int wo, int ho, int tiles_x, int tiles_y, int per_wg,
-                                                        float* __restrict__ out)
+template <bool C420>
+__global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, LfGeom gc, LfPtrs pc,
+                                                        const float* __restrict__ cams, int nv, int wo, int ho,
+                                                        int tiles_x, int tiles_y, int per_wg, float* __restrict__ out)
 {
     __shared__ int marked[NT];
     __shared__ int wcount[NT / 64];
@@ -174,7 +161,10 @@ __global__ void __launch_bounds__(NT) k_render_fallback(LfGeom g, LfPtrs p, cons
             const int i = txi * TW + (int)threadIdx.x % TW, j = tyi * TH + (int)threadIdx.x / TW;
             if (i < wo && j < ho) {
                 float o[3];
-                lf_render_one(g, p, cams + 18 * v, i, j, o);
+                if (C420)
+                    lf_render_one420(g, p, gc, pc, cams + 18 * v, i, j, o);
+                else
+                    lf_render_one(g, p, cams + 18 * v, i, j, o);
 #pragma unroll
                 for (int c = 0; c < 3; c++) out[((int64_t)v * 3 + c) * npix + (int64_t)j * wo + i] = o[c];
             }
@@ -256,21 +246,24 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int sp = n_full < n_work ? split : 1;
     const int64_t grid = (n_full + 7) / 8 * 8 + ((n_work - n_full) * sp + 7) / 8 * 8;
     if (grid > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
-    const bool small = h->L.g.bs < 16;
+    const bool small = h->L.g.bs < 16, c420 = h->L.chroma420 != 0;
     const size_t lds = small ? LDS_DYN_BYTES_SB : LDS_DYN_BYTES;
-    const void* kern = small ? (const void*)k_render_batch<true> : (const void*)k_render_batch<false>;
-    static bool attr_set[2] = {false, false};
-    if (lds > 65536 && !attr_set[small]) {
-        if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    using BatchKernel = void (*)(LfGeom, LfPtrs, LfGeom, LfPtrs, const float*, int, int, int, int, int, int, int,
+                                 int64_t, int, float*);
+    static const BatchKernel kernels[2][2] = {{k_render_batch<false, false>, k_render_batch<false, true>},
+                                              {k_render_batch<true, false>, k_render_batch<true, true>}};
+    const BatchKernel kern = kernels[small][c420];
+    static bool attr_set[2][2] = {};
+    if (lds > 65536 && !attr_set[small][c420]) {
+        if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return lf_fail(LF_EDEVICE, "cannot reserve %zu bytes of LDS", lds);
-        attr_set[small] = true;
+        attr_set[small][c420] = true;
     }
-    if (small)
-        hipLaunchKernelGGL(k_render_batch<true>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv, wo,
-                           ho, tx, ty, chunk, fpg, n_full, sp, d_out);
-    else
-        hipLaunchKernelGGL(k_render_batch<false>, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, d_cams, nv,
-                           wo, ho, tx, ty, chunk, fpg, n_full, sp, d_out);
+    // a 4:4:4 stream passes its own geometry as the (unused) chroma geometry
+    const LfGeom& gc = c420 ? h->L.gc : h->L.g;
+    const LfPtrs& pc = c420 ? h->pc : h->p;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, h->L.g, h->p, gc, pc, d_cams, nv, wo, ho, tx, ty,
+                       chunk, fpg, n_full, sp, d_out);
     // marked pairs: workgroups each check a contiguous range.  With 16x16
     // blocks few tiles exceed the staging budget and 1024 workgroups keep the
     // pass short; smaller blocks mark many more tiles, which need the wider grid.
@@ -278,8 +271,8 @@ lf_status lf_launch_render_batch(const lf_handle* h, const float* d_cams, int nv
     const int64_t fb_grid = std::min<int64_t>(pairs, h->L.g.bs >= 16 ? 1024 : 8192);
     const int64_t per_wg = (pairs + fb_grid - 1) / fb_grid;
     if (per_wg > 0x7FFFFFFF) return lf_fail(LF_EINVAL, "too many tiles");
-    hipLaunchKernelGGL(k_render_fallback, dim3((unsigned)fb_grid), dim3(NT), 0, s, h->L.g, h->p, d_cams, nv, wo, ho, tx,
-                       ty, (int)per_wg, d_out);
+    hipLaunchKernelGGL(c420 ? k_render_fallback<true> : k_render_fallback<false>, dim3((unsigned)fb_grid), dim3(NT), 0,
+                       s, h->L.g, h->p, gc, pc, d_cams, nv, wo, ho, tx, ty, (int)per_wg, d_out);
     return lf_check_launch("render_batch");
 }
 
@@ -289,9 +282,9 @@ extern "C" lf_status lf_render_views(const lf_handle* h, const float* d_cams, in
     if (!h || n_views < 0 || width < 1 || height < 1) return lf_fail(LF_EINVAL, "bad argument");
     if (n_views == 0) return LF_OK;
     if (!d_cams || !d_out) return lf_fail(LF_EINVAL, "null buffer");
-    // the tile kernel decodes quads of 4 pixels inside one block, reads
-    // dense reference planes and assembles three full-size channels
-    if (h->L.g.bs < 4 || h->L.sparse || h->L.chroma420)
+    // the tile kernel decodes quads of 4 pixels inside one block and reads
+    // dense reference planes
+    if (h->L.g.bs < 4 || h->L.sparse)
         return lf_launch_render_rays(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
     return lf_launch_render_batch(h, d_cams, n_views, width, height, d_out, (hipStream_t)stream);
 }

@@ -186,6 +186,33 @@ __device__ inline void lf_render_one(const LfGeom& g, const LfPtrs& p, const flo
     }
 }
 
+// One ray of a 4:2:0 stream (luma geometry g, p; chroma geometry gc, pc):
+// each of the 16 samples is luma plus up-sampled Co and Cg, blended as in
+// lf_render_one.
+__device__ inline void lf_render_one420(const LfGeom& g, const LfPtrs& p, const LfGeom& gc, const LfPtrs& pc,
+                                        const float* __restrict__ cam, int i, int j, float out[3], int lod = 0)
+{
+    const Ray ray = lf_ray_setup(g, cam, i, j);
+    uint32_t rgb[16];
+#pragma unroll 1
+    for (int k = 0; k < 16; k++) {
+        const int b = (k & 8) ? ray.b1 : ray.b0, a = (k & 4) ? ray.a1 : ray.a0;
+        const int y = (k & 2) ? ray.y1 : ray.y0, x = (k & 1) ? ray.x1 : ray.x0;
+        int R, G, B;
+        lf_ycocg_to_rgb(lf_decode_channel(g, p, 0, b, a, y, x, lod), lf_chroma_up(gc, pc, 0, b, a, y, x, lod),
+                        lf_chroma_up(gc, pc, 1, b, a, y, x, lod), R, G, B);
+        rgb[k] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+    }
+    const BlendW w = lf_blend_weights(ray);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        float sm[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) sm[k] = (float)((rgb[k] >> (8 * c)) & 255u);
+        out[c] = lf_blend16(sm, w);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // batched tile renderer
 // ---------------------------------------------------------------------------
@@ -568,9 +595,14 @@ struct TileLds {
 // FALLBACK_MARK at the tile origin for a per-ray pass; the return value says
 // whether any view was left so (the same in every thread).  Every thread of
 // the workgroup calls it; LDS contents do not carry over between calls.
-template <bool INLINE_FALLBACK, bool SMALL_BLOCKS = false>
-__device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __restrict__ cams, int v0, int nf,
-                              int gmax, int wo, int ho, int txi, int tyi, float* __restrict__ out, const TileLds& S)
+// C420: a 4:2:0 stream (luma geometry g, p; chroma geometry gc, pc): the
+// leaf samples are reconstructed one by one (luma walk, up-sampled chroma
+// walks) into the same LDS sample cache, without descriptors or staged
+// ancestors; the plan, the cache across groups and the blend are shared.
+template <bool INLINE_FALLBACK, bool SMALL_BLOCKS = false, bool C420 = false>
+__device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc, const LfPtrs& pc,
+                              const float* __restrict__ cams, int v0, int nf, int gmax, int wo, int ho, int txi,
+                              int tyi, float* __restrict__ out, const TileLds& S)
 {
     // budgets of this instance (the dynamic LDS the launch reserved)
     constexpr int BD = SMALL_BLOCKS ? B_DESC_SB : B_DESC;
@@ -759,7 +791,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             }
             const uint64_t keep1 = __ballot(kneed);
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            int nd = 3 * nbk * nnew0;
+            int nd = C420 ? 0 : 3 * nbk * nnew0;
             int cnt[LF_MAX_LEVELS + 1];
             cnt[0] = nnew0;
             const uint64_t free1 = ~keep1 & (cap1 >= 64 ? ~0ull : ((1ull << cap1) - 1ull));
@@ -774,7 +806,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
 #pragma unroll
             for (int l = 1; l <= LF_MAX_LEVELS + 1; l++) {
                 off[l] = total;
-                if (l <= g.H) {
+                if (!C420 && l <= g.H) {  // a 4:2:0 group stages no ancestors
                     const int nBl = (bmax >> l) - (bmin >> l) + 1, nAl = (amax >> l) - (amin >> l) + 1;
                     if (nBl * nAl > LMAX) ok = 0;
                     total += nBl * nAl;
@@ -977,7 +1009,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
             slotinfo[sl] = info;
             slotdst[sl] = (uint8_t)(3 * (nl >> 8) + c);
         }
-        for (int k = threadIdx.x; k < gp.nnew[0]; k += NT) {
+        for (int k = threadIdx.x; k < (C420 ? 0 : gp.nnew[0]); k += NT) {
             const int e = nodelist[0][k] & 0xFF;
             const int qb = lf_div_small(e, gp.nA[0]), b = gp.B0[0] + qb, a = gp.A0[0] + e - qb * gp.nA[0];
             for (int l = 1; l <= g.H; l++) {
@@ -1030,7 +1062,28 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const float* __r
         // phase 2: every new (view, pixel quad) sample: level-0 SRV + staged
         // ancestors and root; two quads (six channel decodes) per thread at a time
         const int n2 = gp.nnew[0] * rowq;
-        for (int it0 = threadIdx.x; it0 < n2; it0 += 2 * NT) {
+        if (C420) {
+            // 4:2:0: each sample of the quad from the luma walk and the
+            // up-sampled chroma walks, inverse YCoCg-R, RGBA8
+            for (int it = threadIdx.x; it < n2; it += NT) {
+                const int k = lf_qdiv(it, m_rowq), rq = it - k * rowq;
+                const int yl = lf_qdiv(rq, m_nq), qi = rq - yl * nq;
+                const int y = ymin + yl, x0 = xq0 + 4 * qi;
+                const uint32_t nl = nodelist[0][k];
+                const int e = nl & 0xFF;
+                const int qb = lf_div_small(e, gp.nA[0]), b = gp.B0[0] + qb, a = gp.A0[0] + e - qb * gp.nA[0];
+                uint32_t px[4];
+#pragma unroll 1
+                for (int t = 0; t < 4; t++) {
+                    int R, G, B;
+                    lf_ycocg_to_rgb(lf_decode_channel(g, p, 0, b, a, y, x0 + t), lf_chroma_up(gc, pc, 0, b, a, y, x0 + t),
+                                    lf_chroma_up(gc, pc, 1, b, a, y, x0 + t), R, G, B);
+                    px[t] = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+                }
+                reinterpret_cast<uint4*>(rgba)[__mul24((int)(nl >> 8), rowq) + rq] = make_uint4(px[0], px[1], px[2], px[3]);
+            }
+        }
+        for (int it0 = threadIdx.x; it0 < (C420 ? 0 : n2); it0 += 2 * NT) {
             QuadIn in[2][3];
             int kk2[2], rq2[2], yy[2], xx[2];
 #pragma unroll

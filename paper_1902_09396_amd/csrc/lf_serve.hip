@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
             }
             __syncthreads();
         }
-        const bool left = lf_tile_views<false, SMALL_BLOCKS>(sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
+        const bool left = lf_tile_views<false, SMALL_BLOCKS>(sg, sp, sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
                                                reinterpret_cast<float*>(pool + sl->out_off), S);
         if (left && threadIdx.x == 0) work[serve_fbl_off(max_tiles) + atomicAdd(fb, 1)] = w;
         if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(fb + 1, 1);

@@ -1,9 +1,10 @@
 """The 4:2:0 chroma variant (Compressing HMLFC tree: the chroma channels are
 sub-sampled) on the GPU against the oracle: the GPU encoder's streams equal
 the oracle encoder's byte for byte; random-access decoding (leaf views and
-every level of the progressive decode) is bit-exact, and rendering (one
-thread per ray, the path such streams take) is within 1e-5.  Calls built on
-one plane geometry for all channels reject 4:2:0 handles."""
+every level of the progressive decode) is bit-exact, and rendering is within
+1e-5, the tile renderer (leaf samples reconstructed from the luma walk and
+the up-sampled chroma walks) equal to the per-ray kernel pixel for pixel.
+Calls built on one plane geometry for all channels reject 4:2:0 handles."""
 
 import ctypes as C
 
@@ -28,6 +29,11 @@ def _enc(name="tiny", **over):
 @pytest.fixture(scope="module")
 def tiny420(tiny_lf):
     return oracle.encode(tiny_lf, _enc())
+
+
+@pytest.fixture(scope="module")
+def mid420(mid_lf):
+    return oracle.encode(mid_lf, _enc("path512"))
 
 
 @pytest.mark.parametrize("over", [{}, {"step": 1}, {"zero_phase": True}, {"no_mc": True},
@@ -91,16 +97,61 @@ def test_render_420(tiny420, tiny_cams, tiny_cams_ez):
         assert np.abs(lod - o.render_lod(1, cams, 40, 24)).max() <= 1e-5
 
 
-def test_render_420_mid(mid_lf):
+@pytest.mark.parametrize("block", [4, 16])
+def test_render_420_tile_blocks(tiny_lf, block):
+    """Tile renderer on 4:2:0 streams with 4x4 blocks (the small-block
+    instance) and 16x16 blocks: equal to the per-ray kernel, within 1e-5 of
+    the oracle."""
     import torch
 
     from paper_1902_09396_amd import lf
 
-    s = lf.encode(mid_lf, _enc("path512"))
+    s = oracle.encode(tiny_lf, _enc(block=block))
+    o = oracle.OracleLF(s)
+    L = lf.LightField(s)
+    cams = lfscene.make_views(lfscene.get_config("tiny"))
+    cd = torch.from_numpy(np.ascontiguousarray(cams)).cuda()
+    img = L.render_views(cd, 72, 40)
+    assert torch.equal(img, L.render_views(cd, 72, 40, per_ray=True))
+    assert np.abs(img.cpu().numpy() - o.render(cams, 72, 40)).max() <= 1e-5
+
+
+def test_render_420_tiled_orbit(mid420):
+    """A 60-view orbit over the 17x17 grid in 4:2:0 through the tile
+    renderer: more (chunk, tile) items than one round of resident
+    workgroups with a ragged remainder (tail runs, a short last chunk),
+    groups of views sharing the cached leaf samples.  Every pixel equals the
+    per-ray kernel's; sampled rays are within 1e-5 of the oracle."""
+    import torch
+
+    from paper_1902_09396_amd import lf
+
+    L = lf.LightField(mid420)
+    nv, wo, ho = 60, 400, 200
+    cams = lfscene.camera_path_orbit(nv, 17, 17, 128, 128, wo, ho)
+    cd = torch.from_numpy(np.ascontiguousarray(cams)).cuda()
+    img = L.render_views(cd, wo, ho)
+    assert torch.equal(img, L.render_views(cd, wo, ho, per_ray=True))
+    rng = np.random.default_rng(21)
+    rays = np.stack([rng.integers(0, nv, 4000), rng.integers(0, wo, 4000), rng.integers(0, ho, 4000)], 1)
+    expect = oracle.OracleLF(mid420).render_rays(cams, wo, ho, rays)
+    got = img.cpu().numpy()[rays[:, 0], :, rays[:, 2], rays[:, 1]]
+    assert np.abs(got - expect).max() <= 1e-5
+
+
+def test_render_420_mid(mid_lf, mid420):
+    import torch
+
+    from paper_1902_09396_amd import lf
+
+    s = mid420
     o = oracle.OracleLF(s)
     L = lf.LightField(s)
     cams = lfscene.random_pinhole_cameras(3, 17, 17, 128, 128, 96, 64, seed=9, rho=1.0 / 16.0)
-    img = L.render_views(torch.from_numpy(cams).cuda(), 96, 64).cpu().numpy()
+    cd = torch.from_numpy(cams).cuda()
+    img = L.render_views(cd, 96, 64)
+    assert torch.equal(img, L.render_views(cd, 96, 64, per_ray=True))
+    img = img.cpu().numpy()
     assert np.abs(img - o.render(cams, 96, 64)).max() <= 1e-5
     rng = np.random.default_rng(4)
     coords = np.stack([rng.integers(0, 17, 200000), rng.integers(0, 17, 200000), rng.integers(0, 128, 200000),
