@@ -533,25 +533,6 @@ __device__ __forceinline__ uint32_t lf_node_key(int l, int B, int A)
     return ((uint32_t)l << 28) | ((uint32_t)B << 14) | (uint32_t)A;
 }
 
-// Position of the q-th (from 0) set bit of m (q < popcount(m))
-__device__ __forceinline__ int lf_nth_bit(uint64_t m, int q)
-{
-    int pos = 0;
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const uint64_t low = (1ull << w) - 1ull;
-        const int c = __popcll(m & low);
-        if (q >= c) {
-            q -= c;
-            m >>= w;
-            pos += w;
-        } else {
-            m &= low;
-        }
-    }
-    return pos;
-}
-
 #define FALLBACK_MARK 0x7FC0DEADu  // NaN payload: "this tile of this view needs per-ray decoding"
 
 // LDS of one tile renderer instance.
@@ -621,6 +602,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
     uint8_t* slotdst = S.slotdst;
     uint32_t (*ckey)[CMAX] = S.ckey;
     const uint32_t* digits = S.digits;
+    // plan only: [0] leaf, [1] ancestor entries in order of their rank among
+    // the free ones (the slot table's destinations are written after the plan)
+    static_assert(SLOT_MAX >= 128, "the plan's rank tables alias the slot destinations");
+    uint8_t (*inv)[64] = reinterpret_cast<uint8_t (*)[64]>(S.slotdst);
     const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
     const int i = txi * TW + lx, j = tyi * TH + ly;
     const bool live = i < wo && j < ho;
@@ -714,6 +699,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
         // first check that fails
         if (wid == 0) {
             int ok = 0;
+            __builtin_amdgcn_s_setprio(3);  // the plan holds up the workgroup: issue it first
             do {
             uint32_t lo_ab = 0xFFFFFFFFu, hi_ab = 0u, lo_xy = 0xFFFFFFFFu, hi_xy = 0u;
             for (int q = f; q < f + n; q++) {
@@ -722,6 +708,11 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
                 lo_xy = pk_min(lo_xy, fbox[q][2]);
                 hi_xy = pk_max(hi_xy, fbox[q][3]);
             }
+            // the box is the same in every lane: scalar from here on
+            lo_ab = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo_ab);
+            hi_ab = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi_ab);
+            lo_xy = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo_xy);
+            hi_xy = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi_xy);
             const int amin = (int)(lo_ab & 0xFFFFu), bmin = (int)(lo_ab >> 16);
             const int amax = (int)(hi_ab & 0xFFFFu), bmax = (int)(hi_ab >> 16);
             const int xmin = (int)(lo_xy & 0xFFFFu), ymin = (int)(lo_xy >> 16);
@@ -731,7 +722,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             const int bkx0 = xmin >> g.bsl, bky0 = ymin >> g.bsl;
             const int nbkx = (xmax >> g.bsl) - bkx0 + 1, nbk = nbkx * ((ymax >> g.bsl) - bky0 + 1);
             const uint32_t bx0 = (uint32_t)xq0 | ((uint32_t)ymin << 16), bx1 = (uint32_t)nq | ((uint32_t)sy << 16);
-            const bool same = gp.cbox0 == bx0 && gp.cbox1 == bx1;  // cached entries hold this box
+            const bool same = (uint32_t)__builtin_amdgcn_readfirstlane((int)gp.cbox0) == bx0 &&
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)gp.cbox1) == bx1;  // cached entries hold this box
             const int cap0 = min(CMAX, BR / npix), cap1 = min(CMAX, BSV / (3 * npix));
             const int nA0 = amax - amin + 1, nB0 = bmax - bmin + 1;
             ok = nA0 * nB0 <= LMAX && npix <= BR;
@@ -769,7 +761,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             const int nnew0 = __popcll(newm0);
             ok = ok && nnew0 <= __popcll(free0);
             if (!ok) break;
-            if (new0 && ok) ent0 = lf_nth_bit(free0, __popcll(newm0 & ((1ull << lane) - 1ull)));
+            // the k-th new leaf view takes the k-th free entry
+            if ((free0 >> lane) & 1ull) inv[0][__popcll(free0 & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (new0) ent0 = inv[0][__popcll(newm0 & ((1ull << lane) - 1ull))];
             // levels 1..H: ancestors of the new leaf views.  A node (B, A) of
             // level l covers leaf rows [B << l, (B + 1) << l) and columns
             // [A << l, (A + 1) << l); it is needed when one of the new leaf
@@ -867,6 +862,8 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             const int ns = 3 * nnew1;
             ok = ok && nnew1 <= __popcll(free1) && nd <= BD && ns <= SLOT_MAX;
             if (!ok) break;
+            if ((free1 >> lane) & 1ull) inv[1][__popcll(free1 & ((1ull << lane) - 1ull))] = (uint8_t)lane;
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
             {
                 // commit: entries of the new nodes, node maps, new-node lists, keys
                 if (!same && lane < CMAX) {
@@ -887,7 +884,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
                 for (int pp = 0; pp < 2; pp++) {
                     if (newp[pp]) {
                         const int r = (pp ? __popcll(nmp[0]) : 0) + __popcll(nmp[pp] & ((1ull << lane) - 1ull));
-                        const int e = lf_nth_bit(free1, r);
+                        const int e = inv[1][r];
                         int before = 0;
 #pragma unroll
                         for (int k = 1; k < LF_MAX_LEVELS; k++)
@@ -899,30 +896,29 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
                         nodemap[lvp[pp]][idxp[pp]] = (int8_t)e;
                     }
                 }
-                if (lane == 0) {
-                    int sb = 0, db = 3 * nbk * nnew0;
-                    gp.dbase[0] = 0;
+            }
+            if (lane <= g.H) {
+                // per-level fields, lane l for level l: the level's rectangle,
+                // its new nodes, and the first staged slot (levels 1..H) and
+                // descriptor (levels 0..H-1) of its new nodes
+                const int l = lane;
+                int cl = 0, s3 = 0, d3 = 0;
 #pragma unroll
-                    for (int l = 1; l <= LF_MAX_LEVELS; l++) {
-                        if (l > g.H) continue;
-                        gp.sbase[l] = sb;
-                        if (l < g.H) gp.dbase[l] = db;
-                        sb += 3 * cnt[l];
-                        if (l < g.H) db += 3 * nbk * cnt[l];
-                    }
+                for (int k = 0; k <= LF_MAX_LEVELS; k++) {
+                    if (k == l) cl = cnt[k];
+                    if (k >= 1 && k < l) s3 += 3 * cnt[k];
+                    if (k < l) d3 += 3 * nbk * cnt[k];
                 }
+                gp.B0[l] = bmin >> l;
+                gp.A0[l] = amin >> l;
+                gp.nA[l] = (amax >> l) - (amin >> l) + 1;
+                gp.nnew[l] = cl;
+                if (l >= 1) gp.sbase[l] = s3;
+                if (l < g.H) gp.dbase[l] = d3;
             }
             if (lane == 0) {
                 gp.ok = ok;
                 if (ok) {
-#pragma unroll
-                    for (int l = 0; l <= LF_MAX_LEVELS; l++) {
-                        if (l > g.H) continue;
-                        gp.B0[l] = bmin >> l;
-                        gp.A0[l] = amin >> l;
-                        gp.nA[l] = (amax >> l) - (amin >> l) + 1;
-                        gp.nnew[l] = cnt[l];
-                    }
                     gp.xq0 = xq0;
                     gp.ymin = ymin;
                     gp.sy = sy;
@@ -944,6 +940,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             }
             } while (false);
             if (!ok && lane == 0) gp.ok = 0;
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         if (!gp.ok) {
