@@ -55,7 +55,8 @@ def load_counters():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed launches (default 50 for the render line, whose launches take 0.5 ms, else 10)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="path512")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -77,7 +78,11 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=4, help="launches in flight at once (1..4)")
     ap.add_argument("--quant-sweep", default="",
                     help="comma list of quantisation steps: render the workload's path from a stream coded at each")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.steps is None:
+        render_line = not (args.serve or args.encode or args.rd or args.grad or args.quant_sweep)
+        args.steps = 50 if render_line else 10
+    return args
 
 
 def log(*a):

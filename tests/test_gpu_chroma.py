@@ -116,6 +116,24 @@ def test_render_420_tile_blocks(tiny_lf, block):
     assert np.abs(img.cpu().numpy() - o.render(cams, 72, 40)).max() <= 1e-5
 
 
+def test_render_420_beyond_budget(tiny420):
+    """Zoomed-out wide cameras whose tile footprints exceed the tile
+    renderer's LDS budget even for one view: those tiles are left to the
+    4:2:0 per-ray pass.  Equal to the per-ray kernel, within 1e-5 of the
+    oracle."""
+    import torch
+
+    from paper_1902_09396_amd import lf
+
+    L = lf.LightField(tiny420)
+    wide = lfscene.random_pinhole_cameras(3, 8, 8, 64, 64, 40, 40, seed=5, ez_range=(-8.0, -6.0),
+                                          zoom_range=(4.0, 6.0), rho=1.0)
+    cd = torch.from_numpy(np.ascontiguousarray(wide)).cuda()
+    img = L.render_views(cd, 40, 40)
+    assert torch.equal(img, L.render_views(cd, 40, 40, per_ray=True))
+    assert np.abs(img.cpu().numpy() - oracle.OracleLF(tiny420).render(wide, 40, 40)).max() <= 1e-5
+
+
 def test_render_420_tiled_orbit(mid420):
     """A 60-view orbit over the 17x17 grid in 4:2:0 through the tile
     renderer: more (chunk, tile) items than one round of resident
