@@ -186,9 +186,10 @@ lf_status lf_decode_pixels_lod(const lf_handle* h, int32_t level, const int32_t*
 
 /* d_cams: device float [n_views][18].  d_out: device float
  * [n_views][3][height][width] (planar RGB).  width, height >= 1.  Runs the
- * staged tile kernel; fields with blocks smaller than 4x4 and handles
- * loaded with LF_LOAD_SPARSE_REFS run the one-thread-per-ray kernel (same
- * results). */
+ * staged tile kernel (on a 4:2:0 handle each leaf sample from the luma and
+ * the up-sampled chroma decodes); fields with blocks smaller than 4x4 and
+ * handles loaded with LF_LOAD_SPARSE_REFS or LF_LOAD_CSR_REFS run the
+ * one-thread-per-ray kernel (same results). */
 lf_status lf_render_views(const lf_handle* h, const float* d_cams, int32_t n_views, int32_t width,
                           int32_t height, float* d_out, void* stream);
 
