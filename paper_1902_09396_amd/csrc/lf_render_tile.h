@@ -943,7 +943,10 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
-        if (!gp.ok) {
+        // the plan's fields are the same in every lane: read into scalar
+        // registers, so the group loop's control and the phases' uniform
+        // index arithmetic stay on the scalar unit
+        if (!__builtin_amdgcn_readfirstlane(gp.ok)) {
             if (n > 1) {
                 if (n <= 4) ceil_n = n;  // views far apart: stop doubling into failures
                 streak = 0;
@@ -970,14 +973,20 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             __syncthreads();
             continue;
         }
-        const int npix = gp.npix, sxp = gp.sxp, nq = gp.nq, nbk = gp.nbk, nbkx = gp.nbkx;
-        const int xq0 = gp.xq0, ymin = gp.ymin, bkx0 = gp.bkx0, bky0 = gp.bky0;
-        const int rowq = gp.sy * nq;  // quads per staged plane
-        const uint32_t m_rowq = gp.m_rowq, m_nq = gp.m_nq, m_nbk = gp.m_nbk;
+#define LF_UNI(x) __builtin_amdgcn_readfirstlane(x)
+        const int npix = LF_UNI(gp.npix), sxp = LF_UNI(gp.sxp), nq = LF_UNI(gp.nq), nbk = LF_UNI(gp.nbk),
+                  nbkx = LF_UNI(gp.nbkx);
+        const int xq0 = LF_UNI(gp.xq0), ymin = LF_UNI(gp.ymin), bkx0 = LF_UNI(gp.bkx0), bky0 = LF_UNI(gp.bky0);
+        const int rowq = LF_UNI(gp.sy) * nq;  // quads per staged plane
+        const uint32_t m_rowq = (uint32_t)LF_UNI((int)gp.m_rowq), m_nq = (uint32_t)LF_UNI((int)gp.m_nq),
+                       m_nbk = (uint32_t)LF_UNI((int)gp.m_nbk);
+        const int ndesc = LF_UNI(gp.ndesc), nslots = LF_UNI(gp.nslots), nnew0 = LF_UNI(gp.nnew[0]);
+        const int B00 = LF_UNI(gp.B0[0]), A00 = LF_UNI(gp.A0[0]), nA0 = LF_UNI(gp.nA[0]);
+#undef LF_UNI
         // phase 1a: block descriptors of the new nodes of levels 0..H-1, the
         // slot table of the new staged values (levels 1..H), and the
         // ancestor slots of the new leaf views
-        for (int d = threadIdx.x; d < gp.ndesc; d += NT) {
+        for (int d = threadIdx.x; d < ndesc; d += NT) {
             int l = 0;
             while (l + 1 < g.H && d >= gp.dbase[l + 1]) l++;
             const int row = lf_qdiv(d - gp.dbase[l], m_nbk);  // 3 k + c
@@ -989,7 +998,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             const int node = g.node_base[l] + B * g.na_l[l] + A;
             desc[d] = p.desc[((size_t)c * g.n_nodes + node) * g.nblk + blk];
         }
-        for (int sl = threadIdx.x; sl < gp.nslots; sl += NT) {
+        for (int sl = threadIdx.x; sl < nslots; sl += NT) {
             int l = 1;
             while (l < g.H && sl >= gp.sbase[l + 1]) l++;
             const int row = sl - gp.sbase[l];  // 3 k + c
@@ -1006,9 +1015,9 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
             slotinfo[sl] = info;
             slotdst[sl] = (uint8_t)(3 * (nl >> 8) + c);
         }
-        for (int k = threadIdx.x; k < (C420 ? 0 : gp.nnew[0]); k += NT) {
+        for (int k = threadIdx.x; k < (C420 ? 0 : nnew0); k += NT) {
             const int e = nodelist[0][k] & 0xFF;
-            const int qb = lf_div_small(e, gp.nA[0]), b = gp.B0[0] + qb, a = gp.A0[0] + e - qb * gp.nA[0];
+            const int qb = lf_div_small(e, nA0), b = B00 + qb, a = A00 + e - qb * nA0;
             for (int l = 1; l <= g.H; l++) {
                 const int el = __mul24((b >> l) - gp.B0[l], gp.nA[l]) + ((a >> l) - gp.A0[l]);
                 ancs[k][l - 1] = (uint8_t)(3 * nodemap[l][el]);
@@ -1019,7 +1028,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
         // quad: SRVs of levels 1..H-1 and the root RKV (level H).  Four quads
         // per thread at a time: all their loads are issued before any is used.
         {
-            const int n1b = gp.nslots * rowq;
+            const int n1b = nslots * rowq;
             const uint32_t plane = (uint32_t)(g.w * g.h);
             for (int it0 = threadIdx.x; it0 < n1b; it0 += 4 * NT) {
                 QuadIn in[4];
@@ -1058,7 +1067,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
         __syncthreads();
         // phase 2: every new (view, pixel quad) sample: level-0 SRV + staged
         // ancestors and root; two quads (six channel decodes) per thread at a time
-        const int n2 = gp.nnew[0] * rowq;
+        const int n2 = nnew0 * rowq;
         if (C420) {
             // 4:2:0: each sample of the quad from the luma walk and the
             // up-sampled chroma walks, inverse YCoCg-R, RGBA8
@@ -1068,7 +1077,7 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
                 const int y = ymin + yl, x0 = xq0 + 4 * qi;
                 const uint32_t nl = nodelist[0][k];
                 const int e = nl & 0xFF;
-                const int qb = lf_div_small(e, gp.nA[0]), b = gp.B0[0] + qb, a = gp.A0[0] + e - qb * gp.nA[0];
+                const int qb = lf_div_small(e, nA0), b = B00 + qb, a = A00 + e - qb * nA0;
                 uint32_t px[4];
 #pragma unroll 1
                 for (int t = 0; t < 4; t++) {
@@ -1156,10 +1165,9 @@ __device__ bool lf_tile_views(const LfGeom& g, const LfPtrs& p, const LfGeom& gc
         // at a time (the second view's sample reads in flight during the
         // first's blend)
         {
-            const int B00 = gp.B0[0], A00 = gp.A0[0], nA0 = gp.nA[0];
             // all views of the call share one st homography (a camera path with
             // one st window): each ray's (s, t) axis is computed once
-            const bool st_shared = gp.st_shared;
+            const bool st_shared = __builtin_amdgcn_readfirstlane(gp.st_shared) != 0;
             const float* hst = cams + 18 * v0 + 9;
             Ray rst;
             {
