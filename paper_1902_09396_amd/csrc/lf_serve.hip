@@ -65,14 +65,10 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
                                                     int max_tiles, uint8_t* __restrict__ pool)
 {
     TILE_LDS_DECL
-    __shared__ LfGeom sg;
-    __shared__ LfPtrs sp;
-    __shared__ int cur_field, next;
+    __shared__ int next;
     const int n = work[0];
     const ServeWork* items = reinterpret_cast<const ServeWork*>(work + 1);
     int32_t* fb = work + serve_fb_off(max_tiles);
-    if (threadIdx.x == 0) cur_field = -1;
-    __syncthreads();
     // workgroup b renders tile b first; the tiles past the grid come from a
     // queue (their costs differ widely): every workgroup takes the next one
     // until the queue is past n
@@ -80,22 +76,16 @@ __global__ void __launch_bounds__(NT, 3) k_serve_tiles(const LfGeom* __restrict_
         if (w >= n) break;  // uniform
         const ServeWork it = items[w];
         const ServeSlot* sl = slots + it.slot;
-        const int field = sl->field;
-        const bool change = field != cur_field;  // uniform: cur_field only changes after the barrier below
-        __syncthreads();
-        if (change) {
-            // stage the light field's geometry in LDS (uniform branch)
-            const uint32_t* src = reinterpret_cast<const uint32_t*>(geoms + field);
-            uint32_t* dst = reinterpret_cast<uint32_t*>(&sg);
-            for (int k = threadIdx.x; k < (int)(sizeof(LfGeom) / 4); k += NT) dst[k] = src[k];
-            if (threadIdx.x == 0) {
-                sp = ptrs[field];
-                cur_field = field;
-            }
-            __syncthreads();
-        }
-        const bool left = lf_tile_views<false, SMALL_BLOCKS>(sg, sp, sg, sp, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
-                                               reinterpret_cast<float*>(pool + sl->out_off), S);
+        // the field's geometry is read in place: the tables do not change
+        // while the kernel runs, and read through the constant address space
+        // with a uniform index its fields become scalar loads
+        const int field = __builtin_amdgcn_readfirstlane(sl->field);
+        typedef __attribute__((address_space(4))) const LfGeom ConstGeom;
+        typedef __attribute__((address_space(4))) const LfPtrs ConstPtrs;
+        const LfGeom& g = *(const LfGeom*)((ConstGeom*)geoms + field);
+        const LfPtrs& p = *(const LfPtrs*)((ConstPtrs*)ptrs + field);
+        const bool left = lf_tile_views<false, SMALL_BLOCKS>(g, p, g, p, sl->cam, 0, 1, 1, sl->wo, sl->ho, it.tx, it.ty,
+                                                             reinterpret_cast<float*>(pool + sl->out_off), S);
         if (left && threadIdx.x == 0) work[serve_fbl_off(max_tiles) + atomicAdd(fb, 1)] = w;
         if (threadIdx.x == 0) next = (int)gridDim.x + atomicAdd(fb + 1, 1);
         __syncthreads();
