@@ -37,8 +37,10 @@
 #define AD_MAX_PARTS 1024  // partial maxima of the shift reduction
 #define AD_TILE 16         // reference tile side of the pull kernel
 #define AD_PPT 1           // pixels per thread (rows AD_TILE * k / AD_PPT apart)
-#define AD_CAND_MAX 384    // candidate blocks a tile stages in LDS
-#define AD_WIN_MAX 4800    // sibling gradient values a tile stages in LDS (3 windows of up to 40 x 40)
+// LDS of the reference pull: 23.5 KB, six workgroups per CU (the budgets
+// fit tiles whose reach is up to 11 pixels; beyond, the unstaged paths)
+#define AD_CAND_MAX 192    // candidate blocks a tile stages in LDS
+#define AD_WIN_MAX 4336    // sibling gradient values a tile stages in LDS (3 windows of up to 38 x 38)
 
 __device__ __forceinline__ float ad_lerp(float p, float q, float f) { return fmaf(f, q - p, p); }
 

@@ -88,8 +88,8 @@ def test_adjoint_far_shifts(torch_mod, tiny_lf, tiny_cams_ez, block):
     """Shifts moved up to 6 pixels from their stored vectors, one of them by
     20 pixels: every reference tile's reach grows.  With 2x2 blocks a 16x16
     tile can then be reached by more predictive blocks than its LDS list
-    holds (3 * 31^2 > 384), so the reference pull runs its unstaged path;
-    with 8x8 blocks the list holds them but the sibling windows (the whole
+    holds (3 * 31^2 > 192), so the reference pull runs its unstaged path;
+    with 8x8 blocks the list holds them (3 * 8^2 = 192) but the sibling windows (the whole
     64x64 plane, three times) exceed the LDS window, so the taps are read
     from global memory.  Both must match the oracle."""
     torch = torch_mod
